@@ -1,0 +1,318 @@
+/*
+ * tr.h — C ABI of the MI355X (gfx950) library for block-randomized
+ * stochastic tensor-ring decomposition: TR-BRSGD and TR-ScaledBRSGD
+ * (Yu, Li, Zhou, "Block-Randomized Stochastic Methods for Tensor Ring
+ * Decomposition").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Indexing is 0-based (the paper is 1-based).
+ *
+ * Cores.  Core k (0 <= k < N) has shape R_k x I_k x R_{k+1}, R_N = R_0
+ * (tensor-ring format, Section 1).  It is stored as its classical mode-2
+ * unfolding G_{k(2)} (Definition "Classical Mode-n Unfolding"), an
+ * I_k x (R_k R_{k+1}) row-major matrix with column c = r + R_k*s holding
+ * G_k(r, i, s).  Lateral slice G_k(i) is then a contiguous column-major
+ * R_k x R_{k+1} block.
+ *
+ * Tensor X.  Dense, addressed by explicit element strides x_stride[k]:
+ * X(i_0..i_{N-1}) sits at sum_k i_k * x_stride[k].  Paper order
+ * (Definition "Multi-index", first index fastest) has strides 1, I_0,
+ * I_0*I_1, ...  A mode-major replica of mode n (tr_x_replicate) stores the
+ * cyclic unfolding X_[n] column-major, i.e. strides with x_stride[n] = 1.
+ *
+ * Sampled rows.  For mode n, sample f draws one slice index i_k per core
+ * k != n (Algorithm SSDTP).  idx is int32 [m][N] with idx[f][n] = -1.
+ * S is [m][R_n R_{n+1}] row-major with S[f][r + R_n*s] = M_f(s, r),
+ * M_f = G_{n+1}(i_{n+1}) ... G_{N-1}(i_{N-1}) G_0(i_0) ... G_{n-1}(i_{n-1})
+ * (Definition "Subchain Tensor": S holds rows of G^{!=n}_[2]).
+ *
+ * Random draws.  Philox4x64-10 (Salmon et al., SC'11) with key (seed, 0)
+ * and counter (step, sample, mode, stream); bounded integers by
+ * floor(r * n / 2^64) (Lemire 2019).  The mode of step t is
+ * floor(r * N / 2^64) with r from counter (t, 0, 0, TR_STREAM_MODE).
+ * Non-uniform laws are sampled from inclusive prefix sums ("CDF") of
+ * integer weights w_i = floor(p_i * 2^40) + 1: u = floor(r * W / 2^64),
+ * pick the first i with C_i > u; that index has probability w_i / W.
+ *
+ * Ownership.  The caller allocates every buffer (device memory unless
+ * marked host) and passes raw pointers and a HIP stream.  The library
+ * never allocates or frees on the hot path: scratch space is a caller
+ * workspace ``ws`` of at least the size returned by the matching
+ * *_workspace_size query, aligned to 256 bytes.  Only a batch plan owns
+ * memory; it is created and destroyed outside timed regions.
+ *
+ * Errors.  Host validation failures return a negative tr_status and
+ * enqueue nothing.  Numerical conditions found on the device set sticky
+ * bits (TR_DEV_*) in the caller's device word ``dev_status`` (OR-ed in,
+ * never cleared by the library).  Calls are asynchronous on ``stream``;
+ * results written to device scalars (loss, rse) are valid once the
+ * stream reaches them.  The library keeps no mutable global state.
+ */
+#ifndef TR_H_
+#define TR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* tr_stream_t;   /* a hipStream_t */
+
+#define TR_ABI_VERSION 1
+#define TR_MAX_ORDER 8
+#define TR_MAX_RANK 16
+
+typedef enum {
+    TR_OK = 0,
+    TR_E_ARG = -1,          /* null pointer or invalid scalar argument   */
+    TR_E_SHAPE = -2,        /* N, I, R or m outside the supported range  */
+    TR_E_DTYPE = -3,        /* unknown or unsupported dtype combination  */
+    TR_E_ALIGN = -4,        /* pointer not aligned to its element size   */
+    TR_E_WORKSPACE = -5,    /* workspace smaller than required           */
+    TR_E_HIP = -6,          /* a HIP launch or runtime call failed       */
+    TR_E_UNSUPPORTED = -7   /* valid request this build does not serve   */
+} tr_status;
+
+/* Sticky device status bits. */
+enum {
+    TR_DEV_NONFINITE = 1,   /* NaN/Inf met in an update                  */
+    TR_DEV_NOT_SPD = 2,     /* Gram not positive definite even damped    */
+    TR_DEV_ZERO_DIST = 4,   /* law with zero total mass; uniform used    */
+    TR_DEV_DAMPED = 8       /* Cholesky needed the damping fallback      */
+};
+
+typedef enum { TR_F64 = 0, TR_F32 = 1, TR_F16 = 2, TR_BF16 = 3 } tr_dtype;
+
+/* Arithmetic of the contractions in tr_grad.
+ *   TR_PREC_F64:  everything FP64 (FP64 cores and X).
+ *   TR_PREC_F32:  FP32 products (matrix cores), FP32 accumulation.
+ *   TR_PREC_BF16: mixed: the prediction G_{n(2)} S^T from hi/lo BF16
+ *                 splits of both operands (three BF16 products), the
+ *                 residual in BF16 times S split hi/lo, FP32 accumulation.
+ *   TR_PREC_F16:  FP16 products, FP32 accumulation.
+ * The Gram S^T D S is always accumulated in FP64. */
+typedef enum { TR_PREC_F64 = 0, TR_PREC_F32 = 1, TR_PREC_BF16 = 2, TR_PREC_F16 = 3 } tr_prec;
+
+/* Sampling laws of Section 3.2. */
+typedef enum { TR_LAW_UNIFORM = 0, TR_LAW_LEVERAGE = 1, TR_LAW_EUCLID = 2, TR_LAW_OPTIMAL = 3 } tr_law;
+
+/* Counter stream tags (fourth Philox counter word). */
+enum { TR_STREAM_MODE = 0, TR_STREAM_IDX = 1, TR_STREAM_H = 2, TR_STREAM_ENTRY = 3 };
+
+typedef struct {
+    int32_t N;                          /* order, 2 <= N <= TR_MAX_ORDER       */
+    int32_t I[TR_MAX_ORDER];            /* mode sizes I_k >= 1                  */
+    int32_t R[TR_MAX_ORDER];            /* ring ranks: core k is R[k] x I[k] x R[(k+1)%N], 1 <= R <= TR_MAX_RANK */
+    int64_t x_stride[TR_MAX_ORDER];     /* element strides of X                 */
+    int32_t core_dtype;                 /* tr_dtype of the cores (F64 or F32)   */
+    int32_t x_dtype;                    /* tr_dtype of X                        */
+} tr_desc;
+
+/* Step rule (equation eq:update_brsgd and the AdaGrad remark).
+ *   kind 0: fixed alpha:       G += alpha * p
+ *   kind 1: AdaGrad:           A += p*p;  G += eta * p / (b + A)^(1/2 + eps),
+ *                              no change where b + A == 0
+ *   kind 2: Robbins-Monro:     G += alpha / (1 + t/tau) * p                  */
+typedef struct {
+    int32_t kind;
+    double alpha, tau, eta, b, eps;
+} tr_step;
+
+/* ------------------------------------------------------------------ */
+/* Library metadata                                                    */
+/* ------------------------------------------------------------------ */
+int32_t tr_abi_version(void);
+const char* tr_status_str(int32_t status);
+
+/* Mode of step t (Algorithm TR-BRSGD: n uniform over the N modes).  Pure
+ * host function; the same value the device computes inside tr_run. */
+int32_t tr_mode(uint64_t seed, uint64_t step, int32_t N);
+
+/* ------------------------------------------------------------------ */
+/* a2: sampling laws                                                   */
+/* ------------------------------------------------------------------ */
+
+/* Integer-weight CDF of the leverage or Euclidean law of core k (Lemma
+ * "lev_est": p(i) = l_i(G_{k(2)}) / rank; Lemma "euc_est":
+ * p(i) = ||G_k(:,i,:)||_F^2 / ||G_k||_F^2).  core_k: G_{k(2)} in the core
+ * dtype.  cdf_k: uint64 [I_k], inclusive prefix sums of the weights.
+ * Leverage scores come from an FP64 Cholesky of the FP64 Gram
+ * G_{k(2)}^T G_{k(2)}; when I_k <= R_k R_{k+1} the rows are taken as
+ * linearly independent and the law is uniform.  A zero core or a Gram that
+ * is not positive definite sets TR_DEV_ZERO_DIST / TR_DEV_NOT_SPD and
+ * writes the uniform CDF.  law must be TR_LAW_LEVERAGE or TR_LAW_EUCLID. */
+tr_status tr_dist(const tr_desc* d, int32_t k, int32_t law, const void* core_k,
+                  uint64_t* cdf_k, int32_t* dev_status,
+                  void* ws, size_t ws_bytes, tr_stream_t stream);
+size_t tr_dist_workspace_size(const tr_desc* d, int32_t k, int32_t law);
+
+/* Integer-weight CDF over the J_n columns of X_[n] for the optimal law
+ * (equation eq:optimal_prob, unsquared norms): q(j) proportional to
+ * ||X_[n](:,j) - G_{n(2)} s_j||_2 * ||s_j||_2 with s_j the row j of
+ * G^{!=n}_[2].  cores: host array of N device pointers.  X: device tensor
+ * with the strides of d.  cdf_J: uint64 [J_n].  If every term is zero the
+ * uniform CDF is written and TR_DEV_ZERO_DIST is set. */
+tr_status tr_dist_optimal(const tr_desc* d, int32_t n, const void* const* cores,
+                          const void* X, uint64_t* cdf_J, int32_t* dev_status,
+                          void* ws, size_t ws_bytes, tr_stream_t stream);
+size_t tr_dist_optimal_workspace_size(const tr_desc* d, int32_t n);
+
+/* ------------------------------------------------------------------ */
+/* a1/a3/a4: draws and sampled subchain rows (Algorithm SSDTP)         */
+/* ------------------------------------------------------------------ */
+
+/* Draw m samples for mode n at step ``step``: idx int32 [m][N]
+ * (idx[f][n] = -1) and pF float64 [m] = prod_k p_k(i_k) multiplied in the
+ * order n+1, ..., N-1, 0, ..., n-1.  cdf: host array of N device pointers
+ * (entry k = CDF of mode k, or NULL for uniform, where p_k = 1/I_k); cdf
+ * itself may be NULL (all uniform).  cdf_J: CDF over J_n for the optimal
+ * law (then cdf is ignored and one index j is drawn per sample with
+ * counter slot k = n, decoded by the cyclic order), else NULL.
+ * stream_tag selects the counter stream (TR_STREAM_IDX for F_n,
+ * TR_STREAM_H for an independent H_n). */
+tr_status tr_sample(const tr_desc* d, uint64_t seed, uint64_t step, int32_t n, int32_t m,
+                    const uint64_t* const* cdf, const uint64_t* cdf_J, int32_t stream_tag,
+                    int32_t* idx, double* pF, tr_stream_t stream);
+
+/* Sampled rows of G^{!=n}_[2] for the draws in idx: S [m][R_n R_{n+1}] in
+ * the core dtype (slices-Hadamard products from identity slices). */
+tr_status tr_subchain(const tr_desc* d, int32_t n, const void* const* cores,
+                      const int32_t* idx, int32_t m, void* S, tr_stream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* a5/a6: fiber gather and stochastic gradient (eq:S_gradient)         */
+/* ------------------------------------------------------------------ */
+
+/* g = (G_{n(2)} S^T D S - X_F D S) / (m J_n), D = diag(1/pF), computed as
+ * E = X_F - G_{n(2)} S^T (fibers gathered from X by idx), g = -E D S/(m J_n).
+ * g: [I_n][R_n R_{n+1}] in the core dtype.  loss (device float64 scalar,
+ * may be NULL) = sum_f ||e_f||^2 / (2 m pF_f), an unbiased estimate of f.
+ * gram (device float64 [RR][RR], may be NULL) = S^T D S / (m J_n), the
+ * stochastic Hessian of eq:S_hessian with H_n = F_n.  Reductions over
+ * samples run in a fixed order: results are bitwise reproducible. */
+tr_status tr_grad(const tr_desc* d, int32_t n, const void* core_n, const void* X,
+                  const int32_t* idx, const void* S, const double* pF, int32_t m,
+                  int32_t prec, void* g, double* loss, double* gram,
+                  void* ws, size_t ws_bytes, tr_stream_t stream);
+size_t tr_grad_workspace_size(const tr_desc* d, int32_t m, int32_t prec);
+
+/* Stochastic Hessian from an independent draw H_n (eq:S_hessian):
+ * gram = S_H^T diag(1/pH) S_H / (m_H J_n), FP64 accumulation. */
+tr_status tr_gram(const tr_desc* d, int32_t n, const void* S_H, const double* pH, int32_t m_H,
+                  double* gram, void* ws, size_t ws_bytes, tr_stream_t stream);
+size_t tr_gram_workspace_size(const tr_desc* d, int32_t m_H);
+
+/* ------------------------------------------------------------------ */
+/* a7/a8: direction and update                                         */
+/* ------------------------------------------------------------------ */
+
+/* Direction p = -g (gram == NULL) or p = -g (h + damping I)^{-1} with
+ * h = gram (eq:scaledsg_direction and the amended preconditioner), solved
+ * by an FP64 Cholesky and two triangular solves.  If h + damping I is not
+ * positive definite the solve retries with damping + 10^(k-10) tr(h)/RR,
+ * k = 0..6 (TR_DEV_DAMPED), else leaves the core unchanged
+ * (TR_DEV_NOT_SPD).  Then core_n is updated in place by ``rule`` at step t;
+ * accum_n ([I_n][RR], core dtype) is the AdaGrad accumulator (required for
+ * kind 1, else may be NULL). */
+tr_status tr_update(const tr_desc* d, int32_t n, void* core_n, const void* g,
+                    const double* gram, double damping, const tr_step* rule, uint64_t t,
+                    void* accum_n, int32_t* dev_status,
+                    void* ws, size_t ws_bytes, tr_stream_t stream);
+size_t tr_update_workspace_size(const tr_desc* d, int32_t n, int32_t scaled);
+
+/* ------------------------------------------------------------------ */
+/* a9: reconstruction and relative error (RSE of Section 4)            */
+/* ------------------------------------------------------------------ */
+
+/* rse = ||TR(cores) - X_true||_F / ||X_true||_F, FP64 reduction.
+ * x_true_norm2 = ||X_true||_F^2 if known, else a negative value (then it
+ * is computed in the same pass).  rse: device float64 scalar.  Also
+ * writes ||TR(cores) - X_true||^2 and ||X_true||^2 into ws[0..1] (float64). */
+tr_status tr_relerr(const tr_desc* d, const void* const* cores, const void* X_true,
+                    double x_true_norm2, double* rse, void* ws, size_t ws_bytes,
+                    tr_stream_t stream);
+size_t tr_relerr_workspace_size(const tr_desc* d);
+
+/* X = TR(cores) written with the strides of d in the x dtype. */
+tr_status tr_reconstruct(const tr_desc* d, const void* const* cores, void* X, tr_stream_t stream);
+
+/* Mode-major replica: Xn holds X_[n] column-major (fiber of mode n
+ * contiguous, columns in the cyclic order n+1, ..., n-1), read from X with
+ * the strides of d. */
+tr_status tr_x_replicate(const tr_desc* d, const void* X, int32_t n, void* Xn, tr_stream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Whole iterations: Algorithm TR-BRSGD / TR-ScaledBRSGD on the device */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    tr_desc desc;                        /* X strides: paper order of X      */
+    void* cores[TR_MAX_ORDER];           /* device G_{k(2)}, updated in place */
+    void* accum[TR_MAX_ORDER];           /* AdaGrad accumulators or NULL     */
+    const void* X;                       /* device tensor (fit target)       */
+    const void* Xrep[TR_MAX_ORDER];      /* mode-major replicas or NULL      */
+    uint64_t* cdf[TR_MAX_ORDER];         /* per-mode CDF buffers [I_k] (laws L, E) */
+    uint64_t* cdf_J;                     /* CDF buffer [max_n J_n] (law O)   */
+} tr_problem;
+
+typedef struct {
+    int32_t m;          /* |F_n|                                             */
+    int32_t m_H;        /* |H_n| for an independent Hessian draw, 0: H_n = F_n */
+    int32_t law;        /* tr_law                                            */
+    int32_t scaled;     /* 0: TR-BRSGD, 1: TR-ScaledBRSGD                    */
+    int32_t prec;       /* tr_prec                                           */
+    double damping;     /* constant eta^t of the amended preconditioner      */
+    tr_step rule;
+    uint64_t seed;
+} tr_config;
+
+/* Enqueue ``steps`` iterations.  The step counter lives in device memory:
+ * t_dev (uint64) is read by every kernel and incremented at the end of
+ * each step, and the mode is computed on the device from (seed, t), so the
+ * enqueued sequence can be captured once in a HIP graph and replayed.
+ * loss_out (device float64 [steps] or NULL) receives each step's loss
+ * estimate.  Grids are sized for the largest mode. */
+tr_status tr_run(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps,
+                 double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                 tr_stream_t stream);
+size_t tr_run_workspace_size(const tr_problem* p, const tr_config* c);
+
+/* tr_run with HIP events (hipEvent_t handles created by the caller)
+ * recorded on ``stream`` right before and right after the dominant kernel
+ * of step i (the fused fiber-gather / gradient contraction): ev_begin[i],
+ * ev_end[i] for i < steps; NULL arrays or entries are skipped.  Lets a
+ * caller time that kernel inside a real run. */
+tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps,
+                        double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                        void* const* ev_begin, void* const* ev_end, tr_stream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* a10: sampled-entry loss, forward and backward for every core        */
+/* ------------------------------------------------------------------ */
+
+/* L = 1/(2B) sum_b (Trace(G_0(i_0^b) ... G_{N-1}(i_{N-1}^b)) - x_b)^2.
+ * idx int32 [B][N]; x [B] in the x dtype; resid float32 [B] receives the
+ * residuals (prediction - x); loss: device float64 scalar.  FP32 cores. */
+tr_status tr_entry_fwd(const tr_desc* d, const void* const* cores, const int32_t* idx,
+                       const void* x, int32_t B, float* resid, double* loss,
+                       void* ws, size_t ws_bytes, tr_stream_t stream);
+/* grads[k] (host array of N device pointers, G_{k(2)} layout, FP32) =
+ * scale * (*scale_dev) * sum_b resid_b * dTrace/dG_k at i^b, i.e. the
+ * block gradient of eq:gradient restricted to the sampled entries
+ * (dTrace/dG_k(i_k) is the transposed product of the other N-1 slices in
+ * ring order, recomputed per entry from the cores, not stored).
+ * scale_dev: device float64 multiplier (an upstream gradient) or NULL.
+ * Overwrites grads; the sum over entries runs in a fixed order. */
+tr_status tr_entry_bwd(const tr_desc* d, const void* const* cores, const int32_t* idx,
+                       const float* resid, int32_t B, double scale, const double* scale_dev,
+                       void* const* grads, void* ws, size_t ws_bytes, tr_stream_t stream);
+size_t tr_entry_workspace_size(const tr_desc* d, int32_t B);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TR_H_ */

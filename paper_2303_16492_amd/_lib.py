@@ -1,0 +1,138 @@
+"""ctypes view of the C ABI declared in include/tr.h.
+
+torch is imported before the shared library is opened so that the library's
+HIP runtime dependency resolves to the copy torch has already mapped (one
+runtime per process).  A missing library is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (must precede the library: one HIP runtime)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrsgd.so")
+
+TR_MAX_ORDER = 8
+TR_MAX_RANK = 16
+
+TR_OK = 0
+TR_F64, TR_F32, TR_F16, TR_BF16 = 0, 1, 2, 3
+TR_PREC_F64, TR_PREC_F32, TR_PREC_BF16, TR_PREC_F16 = 0, 1, 2, 3
+TR_LAW_UNIFORM, TR_LAW_LEVERAGE, TR_LAW_EUCLID, TR_LAW_OPTIMAL = 0, 1, 2, 3
+TR_STREAM_MODE, TR_STREAM_IDX, TR_STREAM_H, TR_STREAM_ENTRY = 0, 1, 2, 3
+TR_DEV_NONFINITE, TR_DEV_NOT_SPD, TR_DEV_ZERO_DIST, TR_DEV_DAMPED = 1, 2, 4, 8
+
+
+class tr_desc(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32),
+        ("I", C.c_int32 * TR_MAX_ORDER),
+        ("R", C.c_int32 * TR_MAX_ORDER),
+        ("x_stride", C.c_int64 * TR_MAX_ORDER),
+        ("core_dtype", C.c_int32),
+        ("x_dtype", C.c_int32),
+    ]
+
+
+class tr_step(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("alpha", C.c_double),
+        ("tau", C.c_double),
+        ("eta", C.c_double),
+        ("b", C.c_double),
+        ("eps", C.c_double),
+    ]
+
+
+class tr_problem(C.Structure):
+    _fields_ = [
+        ("desc", tr_desc),
+        ("cores", C.c_void_p * TR_MAX_ORDER),
+        ("accum", C.c_void_p * TR_MAX_ORDER),
+        ("X", C.c_void_p),
+        ("Xrep", C.c_void_p * TR_MAX_ORDER),
+        ("cdf", C.c_void_p * TR_MAX_ORDER),
+        ("cdf_J", C.c_void_p),
+    ]
+
+
+class tr_config(C.Structure):
+    _fields_ = [
+        ("m", C.c_int32),
+        ("m_H", C.c_int32),
+        ("law", C.c_int32),
+        ("scaled", C.c_int32),
+        ("prec", C.c_int32),
+        ("damping", C.c_double),
+        ("rule", tr_step),
+        ("seed", C.c_uint64),
+    ]
+
+
+VP = C.c_void_p
+PVP = C.POINTER(C.c_void_p)
+I32, U64, F64, SZ = C.c_int32, C.c_uint64, C.c_double, C.c_size_t
+PDESC = C.POINTER(tr_desc)
+
+_SIGS = {
+    "tr_abi_version": (I32, []),
+    "tr_status_str": (C.c_char_p, [I32]),
+    "tr_mode": (I32, [U64, U64, I32]),
+    "tr_dist": (I32, [PDESC, I32, I32, VP, VP, VP, VP, SZ, VP]),
+    "tr_dist_workspace_size": (SZ, [PDESC, I32, I32]),
+    "tr_dist_optimal": (I32, [PDESC, I32, PVP, VP, VP, VP, VP, SZ, VP]),
+    "tr_dist_optimal_workspace_size": (SZ, [PDESC, I32]),
+    "tr_sample": (I32, [PDESC, U64, U64, I32, I32, PVP, VP, I32, VP, VP, VP]),
+    "tr_subchain": (I32, [PDESC, I32, PVP, VP, I32, VP, VP]),
+    "tr_grad": (I32, [PDESC, I32, VP, VP, VP, VP, VP, I32, I32, VP, VP, VP, VP, SZ, VP]),
+    "tr_grad_workspace_size": (SZ, [PDESC, I32, I32]),
+    "tr_gram": (I32, [PDESC, I32, VP, VP, I32, VP, VP, SZ, VP]),
+    "tr_gram_workspace_size": (SZ, [PDESC, I32]),
+    "tr_update": (I32, [PDESC, I32, VP, VP, VP, F64, C.POINTER(tr_step), U64, VP, VP, VP, SZ, VP]),
+    "tr_update_workspace_size": (SZ, [PDESC, I32, I32]),
+    "tr_relerr": (I32, [PDESC, PVP, VP, F64, VP, VP, SZ, VP]),
+    "tr_relerr_workspace_size": (SZ, [PDESC]),
+    "tr_reconstruct": (I32, [PDESC, PVP, VP, VP]),
+    "tr_x_replicate": (I32, [PDESC, VP, I32, VP, VP]),
+    "tr_run": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP, SZ, VP]),
+    "tr_run_events": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP, SZ, PVP, PVP,
+                            VP]),
+    "tr_run_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_config)]),
+    "tr_entry_fwd": (I32, [PDESC, PVP, VP, VP, I32, VP, VP, VP, SZ, VP]),
+    "tr_entry_bwd": (I32, [PDESC, PVP, VP, VP, I32, F64, VP, PVP, VP, SZ, VP]),
+    "tr_entry_workspace_size": (SZ, [PDESC, I32]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2303_16492_amd.build`"
+            )
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+class TRError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = lib().tr_status_str(status).decode()
+        super().__init__(f"{fn} returned {status}: {msg}")
+        self.status = status
+
+
+def check(fn: str, status: int) -> None:
+    if status != TR_OK:
+        raise TRError(fn, status)

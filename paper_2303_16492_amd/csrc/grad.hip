@@ -1,0 +1,408 @@
+// a5/a6 (+ the Gram of a7): fiber gather, stochastic gradient, loss estimate.
+//
+// g = (G_{n(2)} S^T D S - X_F D S) / (m J_n) (equation eq:S_gradient) is
+// evaluated prediction-first: E = X_F - G_{n(2)} S^T, then g = -E D S/(m J_n).
+// The Gram-first order of the paper's cost remark subtracts two large terms
+// and, multiplied by an ill-conditioned inverse Gram in the scaled variant,
+// loses every digit; prediction-first keeps the error relative to E.
+//
+// Work split: blocks tile (rows of G_{n(2)}) x (groups of sample chunks).
+// A block gathers the X_F tile straight from HBM (one fiber per sample,
+// contiguous when a mode-major replica is given), forms E in LDS and keeps
+// its g rows in registers across its chunks; partial sums per group go to
+// the workspace and are added in a fixed order by the reduce kernel, so
+// results are bitwise reproducible.
+#include "internal.hpp"
+
+namespace trk {
+
+namespace {
+
+template <typename TC>
+struct GradCfg;
+template <> struct GradCfg<double> { static constexpr int TI = 32, TF = 32; };
+template <> struct GradCfg<float> { static constexpr int TI = 64, TF = 32; };
+
+__device__ inline void fiber_strides(const tr_desc& d, int n, bool replica, int64_t* xs) {
+    if (!replica) {
+        for (int k = 0; k < d.N; ++k) xs[k] = d.x_stride[k];
+        return;
+    }
+    int64_t s = d.I[n];
+    xs[n] = 1;
+    int k = n;
+    for (int q = 1; q < d.N; ++q) {
+        k = ring_next(k, d.N);
+        xs[k] = s;
+        s *= d.I[k];
+    }
+}
+
+}  // namespace
+
+template <typename TC, typename TX>
+__global__ __launch_bounds__(256) void k_grad_partial(tr_desc d, ModeSrc ms, Ptrs cores, XSrc xsrc,
+                                                      const int32_t* __restrict__ idx,
+                                                      const TC* __restrict__ S,
+                                                      const double* __restrict__ pF, int m,
+                                                      int groups, int row_tiles_max, int RRp,
+                                                      TC* __restrict__ gpart,
+                                                      double* __restrict__ lpart, int maxIRR) {
+    constexpr int TI = GradCfg<TC>::TI, TF = GradCfg<TC>::TF;
+    constexpr int MAXO = TI * kMaxRR / 256;
+    uint64_t t;
+    int n;
+    resolve_mode(ms, d.N, &t, &n);
+    const int N = d.N;
+    const int In = d.I[n];
+    const int RR = d.R[n] * d.R[ring_next(n, N)];
+    const int i0 = blockIdx.x * TI;
+    const int grp = blockIdx.y;
+    if (i0 >= In) return;
+    const int tid = threadIdx.x;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TC* sS = reinterpret_cast<TC*>(smem_raw);       // [TF][RRp]
+    TC* sG = sS + TF * RRp;                         // [TI][RRp]
+    TC* sE = sG + TI * RRp;                         // [TI][TF+1]
+    TC* sW = sE + TI * (TF + 1);                    // [TF]
+    double* sL = reinterpret_cast<double*>(sW + TF + (TF & 1));   // [TF]
+    int64_t* sB = reinterpret_cast<int64_t*>(sL + TF);            // [TF]
+
+    const TC* Gn = static_cast<const TC*>(cores.p[n]);
+    for (int e = tid; e < TI * RRp; e += 256) {
+        const int i = e / RRp, c = e - (e / RRp) * RRp;
+        sG[e] = (i0 + i < In && c < RR) ? Gn[(int64_t)(i0 + i) * RR + c] : TC(0);
+    }
+    const bool rep = xsrc.rep[n] != nullptr;
+    const TX* X = static_cast<const TX*>(rep ? xsrc.rep[n] : xsrc.X);
+    int64_t xs[kMaxOrder];
+    fiber_strides(d, n, rep, xs);
+    const int64_t xsn = xs[n];
+
+    TC acc[MAXO];
+#pragma unroll
+    for (int q = 0; q < MAXO; ++q) acc[q] = TC(0);
+    double lsum = 0.0;
+    const double Jn = (double)J_of(d, n);
+    const double wbase = 1.0 / ((double)m * Jn);
+
+    const int nchunks = (m + TF - 1) / TF;
+    const int cpg = (nchunks + groups - 1) / groups;
+    const int cbeg = grp * cpg, cend = min(nchunks, cbeg + cpg);
+    for (int ch = cbeg; ch < cend; ++ch) {
+        const int f0 = ch * TF;
+        __syncthreads();
+        for (int e = tid; e < TF * RRp; e += 256) {
+            const int f = e / RRp, c = e - (e / RRp) * RRp;
+            sS[e] = (f0 + f < m && c < RR) ? S[(int64_t)(f0 + f) * RR + c] : TC(0);
+        }
+        if (tid < TF) {
+            const int f = f0 + tid;
+            bool ok = f < m;
+            int64_t off = 0;
+            if (ok) {
+                for (int k = 0; k < N; ++k) {
+                    if (k == n) continue;
+                    const int ik = idx[(int64_t)f * N + k];
+                    if (ik < 0 || ik >= d.I[k]) ok = false;
+                    off += (int64_t)ik * xs[k];
+                }
+            }
+            if (ok) {
+                sB[tid] = off;
+                sW[tid] = (TC)(wbase / pF[f]);
+                sL[tid] = 1.0 / (2.0 * (double)m * pF[f]);
+            } else {   // past the end, or an invalid caller index: contributes nothing
+                sB[tid] = 0;
+                sW[tid] = TC(0);
+                sL[tid] = 0.0;
+            }
+        }
+        __syncthreads();
+        // E = X_F - G S^T for the tile, scaled by -w_f into sE.
+        for (int o = tid; o < TI * TF; o += 256) {
+            const int i = o % TI, f = o / TI;
+            TC val = TC(0);
+            if (i0 + i < In && f0 + f < m && sW[f] != TC(0)) {
+                TC dot = TC(0);
+                const TC* gr = sG + i * RRp;
+                const TC* sr = sS + f * RRp;
+                for (int c = 0; c < RR; ++c) dot += gr[c] * sr[c];
+                const TC x = (TC)to_f64(X[sB[f] + (int64_t)(i0 + i) * xsn]);
+                const TC e = x - dot;
+                lsum += (double)e * (double)e * sL[f];
+                val = -e * sW[f];
+            }
+            sE[i * (TF + 1) + f] = val;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXO; ++q) {
+            const int o = tid + 256 * q;
+            if (o < TI * RR) {
+                const int i = o / RR, c = o - (o / RR) * RR;
+                const TC* er = sE + i * (TF + 1);
+                TC a = acc[q];
+                for (int f = 0; f < TF; ++f) a += er[f] * sS[f * RRp + c];
+                acc[q] = a;
+            }
+        }
+    }
+    TC* out = gpart + (int64_t)grp * maxIRR;
+#pragma unroll
+    for (int q = 0; q < MAXO; ++q) {
+        const int o = tid + 256 * q;
+        if (o < TI * RR) {
+            const int i = o / RR, c = o - (o / RR) * RR;
+            if (i0 + i < In) out[(int64_t)(i0 + i) * RR + c] = acc[q];
+        }
+    }
+    __shared__ double red[4];
+    const double tot = block_sum(lsum, red);
+    if (tid == 0) lpart[(int64_t)grp * row_tiles_max + blockIdx.x] = tot;
+}
+
+// Fixed-order sum of the partials; optional plain update G += rule(-g).
+template <typename TC>
+__global__ __launch_bounds__(256) void k_grad_reduce(tr_desc d, ModeSrc ms, const TC* __restrict__ gpart,
+                                                     const double* __restrict__ lpart, int groups,
+                                                     int row_tiles_max, int TI, int maxIRR,
+                                                     TC* __restrict__ g, double* __restrict__ loss,
+                                                     int apply, MutPtrs cores, MutPtrs accum,
+                                                     tr_step rule, int32_t* status) {
+    uint64_t t;
+    int n;
+    resolve_mode(ms, d.N, &t, &n);
+    const int In = d.I[n];
+    const int RR = d.R[n] * d.R[ring_next(n, d.N)];
+    const int64_t total = (int64_t)In * RR;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && loss) {
+        const int rt = (In + TI - 1) / TI;
+        double s = 0.0;
+        if (threadIdx.x == 0) {
+            for (int gi = 0; gi < groups; ++gi)
+                for (int b = 0; b < rt; ++b) s += lpart[(int64_t)gi * row_tiles_max + b];
+            *loss = s;
+        }
+    }
+    if (e >= total) return;
+    TC acc = TC(0);
+    for (int gi = 0; gi < groups; ++gi) acc += gpart[(int64_t)gi * maxIRR + e];
+    if (g) g[e] = acc;
+    if (apply) {
+        TC* G = static_cast<TC*>(cores.p[n]);
+        TC* A = static_cast<TC*>(accum.p[n]);
+        apply_rule<TC>(G, A, e, -(double)acc, rule, t, status);
+    }
+}
+
+GradWs grad_ws_layout(const tr_desc& d, int m, int prec) {
+    GradWs L{};
+    const Shape sh = shape_of(d);
+    const bool f64 = d.core_dtype == TR_F64;
+    L.ti = f64 ? GradCfg<double>::TI : GradCfg<float>::TI;
+    L.tf = f64 ? GradCfg<double>::TF : GradCfg<float>::TF;
+    L.row_tiles = (sh.maxI + L.ti - 1) / L.ti;
+    const int nchunks = (m + L.tf - 1) / L.tf;
+    int groups = (512 + L.row_tiles - 1) / L.row_tiles;
+    groups = groups < 1 ? 1 : groups;
+    groups = groups > nchunks ? nchunks : groups;
+    const int cpg = (nchunks + groups - 1) / groups;
+    L.groups = (nchunks + cpg - 1) / cpg;
+    if (L.groups < 1) L.groups = 1;
+    const size_t es = f64 ? 8 : 4;
+    L.gpart_off = 0;
+    L.lpart_off = align_up((size_t)L.groups * sh.maxI * sh.maxRR * es);
+    L.total = L.lpart_off + align_up((size_t)L.groups * L.row_tiles * 8);
+    (void)prec;
+    return L;
+}
+
+hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
+                               const void* S, const double* pF, int m, int prec, void* ws,
+                               const GradWs& L, hipStream_t st) {
+    (void)prec;
+    const Shape sh = shape_of(d);
+    const int RRp = sh.maxRR | 1;   // odd row pitch: rows of sG/sS fall in different LDS banks
+    const dim3 grid(L.row_tiles, L.groups);
+    char* w = static_cast<char*>(ws);
+    const int maxIRR = sh.maxI * sh.maxRR;
+    if (d.core_dtype == TR_F64) {
+        constexpr int TI = GradCfg<double>::TI, TF = GradCfg<double>::TF;
+        const size_t shm = (size_t)(TF * RRp + TI * RRp + TI * (TF + 1) + TF + 1) * 8 + TF * 16;
+        if (d.x_dtype != TR_F64) return hipErrorInvalidValue;
+        if (!allow_lds(reinterpret_cast<const void*>(&k_grad_partial<double, double>), shm)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_grad_partial<double, double>), grid, dim3(256), shm, st, d, ms, cores, xs,
+                           idx, static_cast<const double*>(S), pF, m, L.groups, L.row_tiles, RRp,
+                           reinterpret_cast<double*>(w + L.gpart_off),
+                           reinterpret_cast<double*>(w + L.lpart_off), maxIRR);
+    } else {
+        constexpr int TI = GradCfg<float>::TI, TF = GradCfg<float>::TF;
+        const size_t shm = (size_t)(TF * RRp + TI * RRp + TI * (TF + 1) + TF + 1) * 4 + TF * 16 + 16;
+        float* gp = reinterpret_cast<float*>(w + L.gpart_off);
+        double* lp = reinterpret_cast<double*>(w + L.lpart_off);
+        const float* Sf = static_cast<const float*>(S);
+        const void* kern = d.x_dtype == TR_F32 ? reinterpret_cast<const void*>(&k_grad_partial<float, float>)
+                           : d.x_dtype == TR_F16 ? reinterpret_cast<const void*>(&k_grad_partial<float, __half>)
+                                                 : reinterpret_cast<const void*>(&k_grad_partial<float, __hip_bfloat16>);
+        if (!allow_lds(kern, shm)) return hipErrorInvalidValue;
+        switch (d.x_dtype) {
+            case TR_F32:
+                hipLaunchKernelGGL((k_grad_partial<float, float>), grid, dim3(256), shm, st, d, ms, cores,
+                                   xs, idx, Sf, pF, m, L.groups, L.row_tiles, RRp, gp, lp, maxIRR);
+                break;
+            case TR_F16:
+                hipLaunchKernelGGL((k_grad_partial<float, __half>), grid, dim3(256), shm, st, d, ms,
+                                   cores, xs, idx, Sf, pF, m, L.groups, L.row_tiles, RRp, gp, lp, maxIRR);
+                break;
+            case TR_BF16:
+                hipLaunchKernelGGL((k_grad_partial<float, __hip_bfloat16>), grid, dim3(256), shm, st, d,
+                                   ms, cores, xs, idx, Sf, pF, m, L.groups, L.row_tiles, RRp, gp, lp,
+                                   maxIRR);
+                break;
+            default:
+                return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, const GradWs& L, void* g,
+                              double* loss, bool apply, MutPtrs cores, MutPtrs accum, tr_step rule,
+                              int32_t* status, hipStream_t st) {
+    const Shape sh = shape_of(d);
+    const int maxIRR = sh.maxI * sh.maxRR;
+    const dim3 grid((unsigned)((maxIRR + 255) / 256));
+    const char* w = static_cast<const char*>(ws);
+    const double* lp = reinterpret_cast<const double*>(w + L.lpart_off);
+    if (d.core_dtype == TR_F64)
+        hipLaunchKernelGGL(k_grad_reduce<double>, grid, dim3(256), 0, st, d, ms,
+                           reinterpret_cast<const double*>(w + L.gpart_off), lp, L.groups, L.row_tiles,
+                           L.ti, maxIRR, static_cast<double*>(g), loss, (int)apply, cores, accum, rule,
+                           status);
+    else
+        hipLaunchKernelGGL(k_grad_reduce<float>, grid, dim3(256), 0, st, d, ms,
+                           reinterpret_cast<const float*>(w + L.gpart_off), lp, L.groups, L.row_tiles,
+                           L.ti, maxIRR, static_cast<float*>(g), loss, (int)apply, cores, accum, rule,
+                           status);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Gram --
+// gram[c][c'] = sum_f S[f][c] S[f][c'] / (m J_n pF_f), products and sums in
+// FP64 from the stored S.  Blocks tile the RR x RR output in 64 x 64 tiles
+// and split the samples into groups; a second kernel adds the groups in a
+// fixed order.
+
+constexpr int kGramT = 64, kGramTF = 32;
+
+template <typename TC>
+__global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, const TC* __restrict__ S,
+                                                      const double* __restrict__ pF, int m, int groups,
+                                                      int tiles_max, double* __restrict__ part,
+                                                      int maxRR2) {
+    uint64_t t;
+    int n;
+    resolve_mode(ms, d.N, &t, &n);
+    const int RR = d.R[n] * d.R[ring_next(n, d.N)];
+    const int tpd = (RR + kGramT - 1) / kGramT;
+    const int tile = blockIdx.x;
+    if (tile >= tpd * tpd) return;
+    const int c0 = (tile / tpd) * kGramT, e0 = (tile % tpd) * kGramT;
+    __shared__ double sA[kGramTF][kGramT + 1], sB[kGramTF][kGramT + 1];
+    const int tid = threadIdx.x;
+    const int tr_ = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4] = {};
+    const double wbase = 1.0 / ((double)m * (double)J_of(d, n));
+    const int nch = (m + kGramTF - 1) / kGramTF;
+    const int cpg = (nch + groups - 1) / groups;
+    const int cb = blockIdx.y * cpg, ce = min(nch, cb + cpg);
+    for (int ch = cb; ch < ce; ++ch) {
+        const int f0 = ch * kGramTF;
+        __syncthreads();
+        for (int e = tid; e < kGramTF * kGramT; e += 256) {
+            const int f = e / kGramT, c = e % kGramT;
+            const bool okf = f0 + f < m;
+            const double w = okf ? wbase / pF[f0 + f] : 0.0;
+            const double a = (okf && c0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + c0 + c] : 0.0;
+            const double b = (okf && e0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + e0 + c] : 0.0;
+            sA[f][c] = a * w;
+            sB[f][c] = b;
+        }
+        __syncthreads();
+        for (int f = 0; f < kGramTF; ++f) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = sA[f][tr_ + u];
+                b[u] = sB[f][tc + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+    }
+    double* out = part + (int64_t)blockIdx.y * maxRR2;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = c0 + tr_ + u, e = e0 + tc + v;
+            if (c < RR && e < RR) out[(int64_t)c * RR + e] = acc[u][v];
+        }
+    (void)tiles_max;
+}
+
+__global__ void k_gram_reduce(tr_desc d, ModeSrc ms, const double* __restrict__ part, int groups, int maxRR2,
+                              double* __restrict__ gram) {
+    uint64_t t;
+    int n;
+    resolve_mode(ms, d.N, &t, &n);
+    const int RR = d.R[n] * d.R[ring_next(n, d.N)];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= RR * RR) return;
+    double s = 0.0;
+    for (int g = 0; g < groups; ++g) s += part[(int64_t)g * maxRR2 + e];
+    gram[e] = s;
+}
+
+GramWs gram_ws_layout(const tr_desc& d, int m) {
+    GramWs L{};
+    const Shape sh = shape_of(d);
+    const int tpd = (sh.maxRR + kGramT - 1) / kGramT;
+    L.tiles = tpd * tpd;
+    const int nch = (m + kGramTF - 1) / kGramTF;
+    int groups = (256 + L.tiles - 1) / L.tiles;
+    groups = groups > nch ? nch : groups;
+    groups = groups < 1 ? 1 : groups;
+    const int cpg = (nch + groups - 1) / groups;
+    L.groups = (nch + cpg - 1) / cpg;
+    if (L.groups < 1) L.groups = 1;
+    L.part_off = 0;
+    L.total = align_up((size_t)L.groups * sh.maxRR * sh.maxRR * 8);
+    return L;
+}
+
+hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double* pF, int m, double* gram,
+                       void* ws, const GramWs& L, hipStream_t st) {
+    const Shape sh = shape_of(d);
+    const int maxRR2 = sh.maxRR * sh.maxRR;
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + L.part_off);
+    const dim3 grid(L.tiles, L.groups);
+    if (d.core_dtype == TR_F64)
+        hipLaunchKernelGGL(k_gram_partial<double>, grid, dim3(256), 0, st, d, ms,
+                           static_cast<const double*>(S), pF, m, L.groups, L.tiles, part, maxRR2);
+    else
+        hipLaunchKernelGGL(k_gram_partial<float>, grid, dim3(256), 0, st, d, ms,
+                           static_cast<const float*>(S), pF, m, L.groups, L.tiles, part, maxRR2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((maxRR2 + 255) / 256), dim3(256), 0, st, d, ms, part, L.groups,
+                       maxRR2, gram);
+    return hipGetLastError();
+}
+
+}  // namespace trk

@@ -1,0 +1,85 @@
+// Internal launchers shared by the C-ABI wrappers and the multi-step driver.
+#pragma once
+
+#include "common.hpp"
+
+namespace trk {
+
+// Fiber source: the tensor in the strides of the descriptor, and optional
+// mode-major replicas (X_[n] column-major) that make every fiber contiguous.
+struct XSrc {
+    const void* X;
+    const void* rep[kMaxOrder];
+};
+
+struct Shape {
+    int maxI = 0, maxR = 0, maxRR = 0;
+    int64_t maxJ = 0;
+};
+Shape shape_of(const tr_desc& d);
+
+tr_status validate_desc(const tr_desc* d);
+int dtype_size(int dt);
+
+// a3/a4: draw (optionally) and build sampled subchain rows (optionally).
+hipError_t launch_sample_subchain(const tr_desc& d, ModeSrc ms, int m, CdfPtrs cdf,
+                                  const uint64_t* cdf_J, int stream_tag, Ptrs cores,
+                                  int32_t* idx, double* pF, void* S, bool do_sample,
+                                  bool do_subchain, hipStream_t st);
+
+// a5/a6: partial gradients and loss.  Layout of the workspace returned by
+// grad_ws_layout.
+struct GradWs {
+    size_t gpart_off, lpart_off, total;
+    int groups, row_tiles, ti, tf;
+};
+GradWs grad_ws_layout(const tr_desc& d, int m, int prec);
+hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs,
+                               const int32_t* idx, const void* S, const double* pF, int m,
+                               int prec, void* ws, const GradWs& L, hipStream_t st);
+
+// Reduce partials into g (core dtype) and the loss; optionally apply the
+// plain direction p = -g with ``rule`` to the core in place.
+hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, const GradWs& L,
+                              void* g, double* loss, bool apply, MutPtrs cores, MutPtrs accum,
+                              tr_step rule, int32_t* status, hipStream_t st);
+
+// FP64-accumulated Gram S^T diag(1/(m J_n pF)) S.
+struct GramWs {
+    size_t part_off, total;
+    int groups, tiles;
+};
+GramWs gram_ws_layout(const tr_desc& d, int m);
+hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double* pF, int m,
+                       double* gram, void* ws, const GramWs& L, hipStream_t st);
+
+// a7/a8: Cholesky of gram + damping (with fallback) then solve and update.
+struct UpdWs {
+    size_t L_off, flag_off, total;
+};
+UpdWs upd_ws_layout(const tr_desc& d);
+hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping,
+                                const void* g, MutPtrs cores, MutPtrs accum, tr_step rule,
+                                int32_t* status, void* ws, const UpdWs& L, hipStream_t st);
+hipError_t launch_plain_update(const tr_desc& d, ModeSrc ms, const void* g, MutPtrs cores,
+                               MutPtrs accum, tr_step rule, int32_t* status, hipStream_t st);
+
+// a2: laws.
+size_t dist_ws_bytes(const tr_desc& d, int law);
+hipError_t launch_dist(const tr_desc& d, ModeSrc ms, bool use_mode, int k, int law, Ptrs cores,
+                       uint64_t* const* cdf_out, int32_t* status, void* ws, hipStream_t st);
+size_t dist_opt_ws_bytes(const tr_desc& d);
+hipError_t launch_dist_optimal(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs,
+                               uint64_t* cdf_J, int32_t* status, void* ws, hipStream_t st);
+
+hipError_t launch_bump(uint64_t* t_dev, hipStream_t st);
+
+}  // namespace trk
+
+namespace trk {
+size_t relerr_ws_bytes(const tr_desc& d);
+hipError_t launch_relerr(const tr_desc& d, Ptrs cores, const void* Xt, double xnorm2, double* rse, void* ws,
+                         hipStream_t st);
+hipError_t launch_reconstruct(const tr_desc& d, Ptrs cores, void* Xo, hipStream_t st);
+hipError_t launch_replicate(const tr_desc& d, const void* X, int n, void* Xn, hipStream_t st);
+}  // namespace trk

@@ -1,0 +1,278 @@
+"""Parity of every C-ABI entry point with the CPU oracle on identical inputs.
+
+Bars: sampled index sets and p_F bit-exact; floating results within the
+normwise relative tolerance of their arithmetic (1e-12 FP64, 1e-5 FP32)."""
+import numpy as np
+import pytest
+import torch
+
+import tr_inputs as ti
+from oracle import brsgd, sampling, tr
+from gpu_util import DEV, TOL, flat_paper, fold, problem, rel, rounded, say, to_dev, unfold
+
+pytestmark = pytest.mark.gpu
+
+from paper_2303_16492_amd import _lib as L  # noqa: E402
+from paper_2303_16492_amd import api  # noqa: E402
+
+SAMPLE_CASES = [
+    (3, [20, 20, 20], [3, 3, 3], 100),
+    (4, [7, 64, 3, 11], [2, 5, 3, 4], 513),
+    (5, [2, 3, 4, 5, 6], [1, 2, 3, 2, 1], 1),
+    (2, [9, 13], [4, 3], 37),
+    (3, [400, 400, 400], [10, 10, 10], 4096),
+    (8, [2, 3, 2, 3, 2, 3, 2, 2], [2, 1, 2, 3, 1, 2, 2, 1], 257),
+]
+
+
+@pytest.mark.parametrize("N,I,R,m", SAMPLE_CASES)
+def test_sample_uniform_bit_exact(N, I, R, m):
+    desc = api.make_desc(I, R, torch.float32)
+    for n in range(N):
+        for step in (0, 7, 123456789):
+            say("sample uniform", N, I, R, m, n, step)
+            idx, pF = api.tr_sample(desc, 11, step, n, m)
+            ridx, rpF = sampling.draw(11, step, n, m, I)
+            assert np.array_equal(idx.cpu().numpy(), ridx)
+            assert np.array_equal(pF.cpu().numpy(), rpF)
+
+
+@pytest.mark.parametrize("N,I,R,m", SAMPLE_CASES[:4])
+def test_sample_weighted_bit_exact(N, I, R, m):
+    desc = api.make_desc(I, R, torch.float32)
+    w = [ti.int_weights(20 + k, I[k], 1, 1 << 40) for k in range(N)]
+    cdf = [to_dev(np.cumsum(wk).astype(np.int64), torch.int64) for wk in w]
+    for n in range(N):
+        say("sample weighted", N, I, m, n)
+        idx, pF = api.tr_sample(desc, 5, 3, n, m, cdf=cdf)
+        ridx, rpF = sampling.draw(5, 3, n, m, I, w)
+        assert np.array_equal(idx.cpu().numpy(), ridx)
+        assert np.array_equal(pF.cpu().numpy(), rpF)
+
+
+def test_sample_optimal_direct_draw_bit_exact():
+    I, R = [5, 7, 4], [2, 3, 2]
+    desc = api.make_desc(I, R, torch.float32)
+    for n in range(3):
+        Jn = int(np.prod([I[k] for k in range(3) if k != n]))
+        wJ = ti.int_weights(40 + n, Jn, 1, 1 << 40)
+        say("sample optimal", n)
+        idx, pF = api.tr_sample(desc, 9, 4, n, 333, cdf_J=to_dev(np.cumsum(wJ).astype(np.int64), torch.int64))
+        ridx, rpF = sampling.draw(9, 4, n, 333, I, w_J=wJ)
+        assert np.array_equal(idx.cpu().numpy(), ridx)
+        assert np.array_equal(pF.cpu().numpy(), rpF)
+
+
+def test_sample_zero_samples_is_a_no_op():
+    desc = api.make_desc([3, 4, 5], [2, 2, 2], torch.float32)
+    idx = torch.full((1, 3), 77, dtype=torch.int32, device=DEV)
+    pF = torch.full((1,), 5.0, dtype=torch.float64, device=DEV)
+    api.tr_sample(desc, 0, 0, 0, 0, idx=idx, pF=pF)
+    assert int(idx[0, 0]) == 77 and float(pF[0]) == 5.0
+
+
+SUB_CASES = [
+    (3, [20, 20, 20], [3, 3, 3], 100),
+    (4, [6, 5, 7, 4], [2, 5, 3, 4], 77),
+    (5, [3, 4, 3, 5, 2], [8, 8, 8, 8, 8], 300),
+    (3, [5, 6, 7], [16, 16, 16], 65),
+    (2, [9, 13], [4, 3], 37),
+    (3, [4, 3, 5], [1, 1, 1], 10),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,I,R,m", SUB_CASES)
+def test_subchain_parity(N, I, R, m, dtype):
+    I, R, cores, X, dcores, dX = problem(1, N, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+    for n in range(N):
+        say("subchain", N, I, R, m, n, dtype)
+        idx, pF = api.tr_sample(desc, 3, 0, n, m)
+        S = api.tr_subchain(desc, n, dcores, idx, m)
+        ref = brsgd.subchain_rows(cores, n, idx.cpu().numpy())
+        assert rel(S.cpu().numpy(), ref) < TOL[dtype]
+
+
+GRAD_CASES = [
+    (3, [20, 20, 20], [3, 3, 3], 100),
+    (4, [12, 9, 17, 6], [2, 5, 3, 4], 513),
+    (3, [70, 33, 65], [4, 5, 3], 200),
+    (5, [3, 4, 3, 5, 2], [8, 8, 8, 8, 8], 97),
+    (2, [9, 13], [4, 3], 1),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,I,R,m", GRAD_CASES)
+def test_grad_loss_gram_parity(N, I, R, m, dtype):
+    I, R, cores, X, dcores, dX = problem(2, N, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+    prec = L.TR_PREC_F64 if dtype == torch.float64 else L.TR_PREC_F32
+    for n in range(N):
+        say("grad", N, I, R, m, n, dtype)
+        idx, pF = api.tr_sample(desc, 4, 1, n, m)
+        S = api.tr_subchain(desc, n, dcores, idx, m)
+        g, loss, gram = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, prec, want_gram=True)
+        idn, pFn = idx.cpu().numpy(), pF.cpu().numpy()
+        Sref = brsgd.subchain_rows(cores, n, idn)
+        XF = brsgd.gather_fibers(X, n, idn)
+        Jn = brsgd.J_of(I, n)
+        # identical inputs: feed the oracle the S the GPU used (rounded to dtype)
+        Sin = S.double().cpu().numpy()
+        assert rel(Sin, Sref) < TOL[dtype]
+        gref, lref = brsgd.stoch_grad(unfold(cores[n]), Sin, XF, pFn, Jn)
+        href = brsgd.stoch_hessian(Sin, pFn, Jn)
+        assert rel(g.cpu().numpy(), gref) < TOL[dtype]
+        assert abs(float(loss) - lref) <= TOL[dtype] * abs(lref)
+        assert rel(gram.cpu().numpy(), href) < 1e-12
+
+
+def test_grad_from_mode_major_replica():
+    """Fibers read from a replica (stride 1 along the mode) equal those from
+    the paper-order tensor."""
+    dtype = torch.float32
+    I, R, cores, X, dcores, dX = problem(3, 3, [30, 20, 25], [3, 4, 2], dtype)
+    desc = api.make_desc(I, R, dtype)
+    for n in range(3):
+        say("replica", n)
+        Xn = api.tr_x_replicate(desc, dX, n)
+        ref = tr.unfold_cyclic(X, n).reshape(-1, order="F")
+        assert np.array_equal(Xn.double().cpu().numpy(), ref)
+        order = [(n + q) % 3 for q in range(1, 3)]
+        strides = [0, 0, 0]
+        strides[n] = 1
+        s = I[n]
+        for k in order:
+            strides[k] = s
+            s *= I[k]
+        drep = api.make_desc(I, R, dtype, x_strides=strides)
+        idx, pF = api.tr_sample(desc, 8, 2, n, 150)
+        S = api.tr_subchain(desc, n, dcores, idx, 150)
+        g1, l1, _ = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, 150, L.TR_PREC_F32)
+        g2, l2, _ = api.tr_grad(drep, n, dcores[n], Xn, idx, S, pF, 150, L.TR_PREC_F32)
+        assert torch.equal(g1, g2) and float(l1) == float(l2)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", ["fixed", "robbins-monro", "adagrad"])
+def test_plain_update_parity(dtype, kind):
+    I, R, cores, X, dcores, dX = problem(4, 3, [17, 9, 12], [3, 2, 4], dtype)
+    desc = api.make_desc(I, R, dtype)
+    n = 1
+    rule = api.step_rule(kind, alpha=0.05, tau=10.0, eta=0.01)
+    cfg = brsgd.Config(m=1, rule=kind, alpha=0.05, tau=10.0, eta=0.01)
+    rng = np.random.default_rng(0)
+    g = rounded(rng.standard_normal((I[n], R[n] * R[2])), dtype)
+    acc0 = rounded(np.abs(rng.standard_normal(g.shape)), dtype)
+    acc = to_dev(acc0, dtype) if kind == "adagrad" else None
+    core = dcores[n].clone()
+    say("plain update", dtype, kind)
+    st = api.tr_update(desc, n, core, to_dev(g, dtype), rule=rule, t=7, accum=acc)
+    new, A = brsgd.update(unfold(cores[n]), -g, cfg, 7, acc0 if kind == "adagrad" else None)
+    assert rel(core.cpu().numpy(), new) < TOL[dtype]
+    if kind == "adagrad":
+        assert rel(acc.cpu().numpy(), A) < TOL[dtype]
+    assert int(st) == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("damping", [0.0, 0.3])
+def test_scaled_update_parity(dtype, damping):
+    I, R, cores, X, dcores, dX = problem(5, 3, [40, 30, 35], [3, 4, 3], dtype)
+    desc = api.make_desc(I, R, dtype)
+    prec = L.TR_PREC_F64 if dtype == torch.float64 else L.TR_PREC_F32
+    for n in range(3):
+        m = 300
+        say("scaled update", dtype, damping, n)
+        idx, pF = api.tr_sample(desc, 6, 0, n, m)
+        S = api.tr_subchain(desc, n, dcores, idx, m)
+        g, loss, gram = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, prec, want_gram=True)
+        core = dcores[n].clone()
+        st = api.tr_update(desc, n, core, g, gram=gram, damping=damping,
+                           rule=api.step_rule("fixed", alpha=0.7), t=0)
+        h = gram.cpu().numpy() + damping * np.eye(gram.shape[0])
+        p, sref = brsgd.scaled_direction(g.double().cpu().numpy(), h)
+        want = unfold(cores[n]) + 0.7 * p
+        assert rel(core.cpu().numpy(), want) < TOL[dtype]
+        assert int(st) == sref == 0
+
+
+def test_scaled_update_singular_gram_uses_damping_fallback():
+    dtype = torch.float64
+    I, R, cores, X, dcores, dX = problem(6, 3, [10, 8, 9], [2, 3, 2], dtype)
+    desc = api.make_desc(I, R, dtype)
+    n = 0
+    m = 3                                   # fewer rows than RR = 6: singular Gram
+    idx, pF = api.tr_sample(desc, 1, 0, n, m)
+    S = api.tr_subchain(desc, n, dcores, idx, m)
+    g, _, gram = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, L.TR_PREC_F64, want_gram=True)
+    core = dcores[n].clone()
+    say("singular gram")
+    st = int(api.tr_update(desc, n, core, g, gram=gram, rule=api.step_rule("fixed", alpha=1.0)))
+    p, sref = brsgd.scaled_direction(g.cpu().numpy(), gram.cpu().numpy())
+    assert st == sref
+    assert np.all(np.isfinite(core.cpu().numpy()))
+    if st == brsgd.DEV_DAMPED:
+        assert rel(core.cpu().numpy(), unfold(cores[n]) + p) < 1e-8
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("law", ["E", "L"])
+def test_product_laws_parity(dtype, law):
+    I, R, cores, X, dcores, dX = problem(7, 3, [40, 7, 25], [3, 2, 4], dtype)
+    desc = api.make_desc(I, R, dtype)
+    code = L.TR_LAW_EUCLID if law == "E" else L.TR_LAW_LEVERAGE
+    for k in range(3):
+        say("law", law, dtype, k)
+        cdf, st = api.tr_dist(desc, k, code, dcores[k])
+        w = np.diff(np.concatenate([[0], cdf.cpu().numpy().astype(np.uint64)]))
+        p_gpu = w.astype(np.float64) / float(w.sum())
+        if law == "E":
+            pref, _ = sampling.dist_euclid(cores[k])
+        else:
+            pref = sampling.dist_leverage(cores[k])
+        wref = sampling.quantize(pref)
+        assert np.max(np.abs(w.astype(np.int64) - wref.astype(np.int64))) <= 64
+        assert rel(p_gpu, wref.astype(np.float64) / float(wref.sum())) < 1e-10
+        assert int(st) == 0
+
+
+def test_optimal_law_parity():
+    dtype = torch.float64
+    I, R, cores, X, dcores, dX = problem(8, 3, [9, 7, 8], [2, 3, 2], dtype)
+    desc = api.make_desc(I, R, dtype)
+    for n in range(3):
+        say("optimal law", n)
+        cdf, st = api.tr_dist_optimal(desc, n, dcores, dX)
+        w = np.diff(np.concatenate([[0], cdf.cpu().numpy().astype(np.uint64)]))
+        q, _ = sampling.dist_optimal(cores, X, n)
+        wref = sampling.quantize(q)
+        assert np.max(np.abs(w.astype(np.int64) - wref.astype(np.int64))) <= 64
+        assert int(st) == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,I,R", [(3, [20, 20, 20], [3, 3, 3]), (4, [7, 5, 9, 6], [2, 3, 4, 2]),
+                                   (3, [300, 40, 33], [10, 10, 10]), (2, [33, 65], [5, 4])])
+def test_relerr_and_reconstruct_parity(N, I, R, dtype):
+    I, R, cores, X, dcores, dX = problem(9, N, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+    say("relerr", N, I, R, dtype)
+    Xh = api.tr_reconstruct(desc, dcores)
+    ref = tr.full_tensor(cores)
+    assert rel(Xh.cpu().numpy(), flat_paper(ref)) < TOL[dtype]
+    rse = float(api.tr_relerr(desc, dcores, dX))
+    want = tr.rse(cores, X)
+    assert abs(rse - want) <= 10 * TOL[dtype] * want
+    rse2 = float(api.tr_relerr(desc, dcores, dX, x_true_norm2=float(np.sum(X * X))))
+    assert abs(rse2 - want) <= 10 * TOL[dtype] * want
+
+
+def test_relerr_zero_at_truth_fp64():
+    cores = [rounded(c, torch.float64) for c in ti.gaussian_cores(3, 3, [12, 10, 11], [3, 2, 4])]
+    X = tr.full_tensor(cores)
+    desc = api.make_desc([12, 10, 11], [3, 2, 4], torch.float64)
+    rse = float(api.tr_relerr(desc, [to_dev(unfold(c), torch.float64) for c in cores],
+                              to_dev(flat_paper(X), torch.float64)))
+    assert rse < 1e-14

@@ -1,0 +1,179 @@
+"""Whole iterations on the GPU against the oracle: the FP64 20^3 rank-3
+trajectory with bit-exact index sets at every step, multi-step runs under
+every law and step rule, graph replay and run-to-run bitwise equality."""
+import numpy as np
+import pytest
+import torch
+
+import tr_inputs as ti
+from oracle import brsgd, tr
+from gpu_util import DEV, flat_paper, fold, rel, rounded, say, to_dev, unfold
+
+pytestmark = pytest.mark.gpu
+
+from paper_2303_16492_amd import _lib as L  # noqa: E402
+from paper_2303_16492_amd import api  # noqa: E402
+from paper_2303_16492_amd.driver import TRSolver  # noqa: E402
+
+
+def planted(N, I, R, dtype, seed=0, noise_db=None):
+    Xt = tr.full_tensor(ti.gaussian_cores(seed, N, I, R))
+    X = Xt if noise_db is None else brsgd.add_noise(Xt, ti.standard_normal(seed + 5, Xt.shape), noise_db)
+    X = rounded(X, dtype)
+    sig = brsgd.init_scale(X, [R] * N if np.isscalar(R) else R)
+    init = [rounded(c, dtype) for c in ti.gaussian_cores(seed + 1, N, I, R, scale=sig)]
+    return X, Xt, init
+
+
+def test_fp64_trajectory_indices_bit_exact_every_step():
+    """20^3, ranks 3, uniform fibers, m = 100, alpha = 0.2, 500 steps, seed 0:
+    the per-call path draws the oracle's index sets at every step."""
+    N, I, R, m, steps = 3, 20, 3, 100, 500
+    X, _, init = planted(N, I, R, torch.float64)
+    desc = api.make_desc([I] * N, [R] * N, torch.float64)
+    dX = to_dev(flat_paper(X), torch.float64)
+    dcores = [to_dev(unfold(c), torch.float64) for c in init]
+    st = brsgd.State(init)
+    cfg = brsgd.Config(m=m, alpha=0.2, seed=0)
+    rule = api.step_rule("fixed", alpha=0.2)
+    g_buf = None
+    for t in range(steps):
+        n = api.tr_mode(0, t, N)
+        trace = {}
+        brsgd.step(st, X, cfg, trace=trace)
+        assert trace["n"] == n
+        idx, pF = api.tr_sample(desc, 0, t, n, m)
+        S = api.tr_subchain(desc, n, dcores, idx, m)
+        g, _, _ = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, L.TR_PREC_F64)
+        api.tr_update(desc, n, dcores[n], g, rule=rule, t=t)
+        if t % 25 == 0 or t == steps - 1:
+            say("trajectory step", t)
+            assert np.array_equal(idx.cpu().numpy(), trace["idx"])
+            assert np.array_equal(pF.cpu().numpy(), trace["pF"])
+    for k in range(N):
+        assert rel(dcores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-10
+    want = tr.rse(st.cores, X)
+    assert want < 1e-8
+    got = float(api.tr_relerr(desc, dcores, dX))
+    assert abs(got - want) < 1e-10
+
+
+def _run_both(N, I, R, dtype, m, law, scaled, rule_kind, steps, seed=0, m_H=0, noise_db=40.0,
+              alpha=0.1, eta=0.05, damping=0.0):
+    X, _, init = planted(N, I, R, dtype, seed=seed, noise_db=noise_db)
+    II = [I] * N if np.isscalar(I) else I
+    RR_ = [R] * N if np.isscalar(R) else R
+    dX = to_dev(flat_paper(X), dtype)
+    dcores = [to_dev(unfold(c), dtype) for c in init]
+    rule = api.step_rule(rule_kind, alpha=alpha, eta=eta, tau=50.0)
+    prec = "f64" if dtype == torch.float64 else "f32"
+    sol = TRSolver(dcores, dX, II, RR_, m, law=law, scaled=scaled, prec=prec, rule=rule,
+                   damping=damping, m_H=m_H, seed=seed)
+    sol.run(steps)
+    st = brsgd.State(init)
+    cfg = brsgd.Config(m=m, dist=law, variant="scaled" if scaled else "plain", rule=rule_kind,
+                       alpha=alpha, eta=eta, tau=50.0, damping=damping, m_H=(m_H or None), seed=seed)
+    for _ in range(steps):
+        brsgd.step(st, X, cfg)
+    torch.cuda.synchronize()
+    return sol, st, X
+
+
+@pytest.mark.parametrize("law", ["U", "E", "L", "O"])
+def test_adagrad_run_each_law_fp64(law):
+    say("run law fp64", law)
+    sol, st, X = _run_both(4, [9, 8, 7, 10], [2, 3, 2, 3], torch.float64, 64, law, False, "adagrad", 40)
+    assert sol.t == 40 and int(sol.status.item()) == st.status
+    for k in range(4):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-10
+
+
+@pytest.mark.parametrize("law", ["U", "E", "L", "O"])
+def test_adagrad_run_each_law_fp32(law):
+    say("run law fp32", law)
+    sol, st, X = _run_both(4, [9, 8, 7, 10], [2, 3, 2, 3], torch.float32, 64, law, False, "adagrad", 25)
+    for k in range(4):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("m_H", [0, 150])
+def test_scaled_run(dtype, m_H):
+    say("scaled run", dtype, m_H)
+    sol, st, X = _run_both(3, [30, 25, 28], [3, 3, 3], dtype, 200, "U", True, "fixed", 20, m_H=m_H,
+                           alpha=0.5, noise_db=None)
+    tol = 1e-9 if dtype == torch.float64 else 2e-4
+    for k in range(3):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < tol
+
+
+def test_robbins_monro_run_fp64():
+    sol, st, X = _run_both(3, [12, 10, 11], [2, 3, 2], torch.float64, 50, "E", False, "robbins-monro", 30,
+                           alpha=0.05)
+    for k in range(3):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-10
+
+
+def test_planted_recovery_fp64_on_gpu():
+    """The device path recovers the planted 20^3 rank-3 ring to RSE <= 1e-10."""
+    N, I, R = 3, 20, 3
+    X, _, init = planted(N, I, R, torch.float64)
+    dX = to_dev(flat_paper(X), torch.float64)
+    sol = TRSolver([to_dev(unfold(c), torch.float64) for c in init], dX, [I] * N, [R] * N, 100,
+                   prec="f64", rule=api.step_rule("fixed", alpha=0.2))
+    sol.run(900)
+    rse = float(sol.rse())
+    say("planted rse", rse)
+    assert rse <= 1e-10
+
+
+def test_graph_replay_equals_eager_bitwise():
+    dtype = torch.float32
+    X, _, init = planted(3, [40, 30, 35], [3, 4, 3], dtype, noise_db=40.0)
+    dX = to_dev(flat_paper(X), dtype)
+    mk = lambda: TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [40, 30, 35], [3, 4, 3], 256,
+                          law="E", scaled=True, prec="f32", rule=api.step_rule("fixed", alpha=0.5))
+    a = mk()
+    a.run(1 + 3 * 5)
+    b = mk()
+    g = b.capture(5)            # one eager warm-up step + a 5-step graph
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        say("replay t", b.t)
+    torch.cuda.synchronize()
+    assert a.t == b.t == 16
+    for k in range(3):
+        assert torch.equal(a.cores[k], b.cores[k])
+
+
+def test_runs_are_bitwise_reproducible():
+    dtype = torch.float32
+    X, _, init = planted(4, [9, 8, 7, 10], [2, 3, 2, 3], dtype, noise_db=40.0)
+    dX = to_dev(flat_paper(X), dtype)
+    outs = []
+    for _ in range(2):
+        s = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [9, 8, 7, 10], [2, 3, 2, 3], 128,
+                     law="L", prec="f32", rule=api.step_rule("adagrad", eta=0.05))
+        s.run(30)
+        outs.append([c.clone() for c in s.cores])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_loss_estimates_written_per_step():
+    dtype = torch.float64
+    X, _, init = planted(3, [12, 10, 11], [2, 3, 2], dtype)
+    dX = to_dev(flat_paper(X), dtype)
+    s = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [12, 10, 11], [2, 3, 2], 64, prec="f64",
+                 rule=api.step_rule("fixed", alpha=0.1))
+    losses = torch.zeros(10, dtype=torch.float64, device=DEV)
+    s.run(10, loss_out=losses)
+    st = brsgd.State(init)
+    cfg = brsgd.Config(m=64, alpha=0.1)
+    ref = []
+    for _ in range(10):
+        tr_ = {}
+        brsgd.step(st, X, cfg, trace=tr_)
+        ref.append(tr_["loss"])
+    assert rel(losses.cpu().numpy(), np.array(ref)) < 1e-10
