@@ -209,7 +209,19 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // needs less LDS or report the error.
 inline bool allow_lds(const void* kernel, size_t bytes) {
     if (bytes <= 65536) return true;
-    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+    if (bytes > 160 * 1024) return false;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) return true;
+    (void)hipGetLastError();   // a refusal must not surface as a later launch error
+    return false;
+}
+
+// Broadcast of a uniform lane's double through the scalar unit (no LDS
+// round trip, unlike a shuffle).  ``lane`` must be the same in every lane.
+__device__ inline double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 }  // namespace trk

@@ -21,7 +21,6 @@ namespace {
 template <typename TC>
 struct GradCfg;
 template <> struct GradCfg<double> { static constexpr int TI = 32, TF = 32; };
-template <> struct GradCfg<float> { static constexpr int TI = 64, TF = 32; };
 
 __device__ inline void fiber_strides(const tr_desc& d, int n, bool replica, int64_t* xs) {
     if (!replica) {
@@ -189,7 +188,15 @@ __global__ __launch_bounds__(256) void k_grad_reduce(tr_desc d, ModeSrc ms, cons
     }
     if (e >= total) return;
     TC acc = TC(0);
-    for (int gi = 0; gi < groups; ++gi) acc += gpart[(int64_t)gi * maxIRR + e];
+    int gi = 0;
+    for (; gi + 8 <= groups; gi += 8) {   // loads issued together, added in group order
+        TC v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = gpart[(int64_t)(gi + u) * maxIRR + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; gi < groups; ++gi) acc += gpart[(int64_t)gi * maxIRR + e];
     if (g) g[e] = acc;
     if (apply) {
         TC* G = static_cast<TC*>(cores.p[n]);
@@ -202,11 +209,12 @@ GradWs grad_ws_layout(const tr_desc& d, int m, int prec) {
     GradWs L{};
     const Shape sh = shape_of(d);
     const bool f64 = d.core_dtype == TR_F64;
-    L.ti = f64 ? GradCfg<double>::TI : GradCfg<float>::TI;
-    L.tf = f64 ? GradCfg<double>::TF : GradCfg<float>::TF;
+    L.ti = f64 ? GradCfg<double>::TI : 64;   // FP32 runs the matrix-core kernel (64 x 64 tiles)
+    L.tf = f64 ? GradCfg<double>::TF : 64;
     L.row_tiles = (sh.maxI + L.ti - 1) / L.ti;
     const int nchunks = (m + L.tf - 1) / L.tf;
-    int groups = (512 + L.row_tiles - 1) / L.row_tiles;
+    // about one block per CU: fewer partial slices to add afterwards
+    int groups = ((f64 ? 512 : 256) + L.row_tiles - 1) / L.row_tiles;
     groups = groups < 1 ? 1 : groups;
     groups = groups > nchunks ? nchunks : groups;
     const int cpg = (nchunks + groups - 1) / groups;
@@ -239,32 +247,9 @@ hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
                            reinterpret_cast<double*>(w + L.gpart_off),
                            reinterpret_cast<double*>(w + L.lpart_off), maxIRR);
     } else {
-        constexpr int TI = GradCfg<float>::TI, TF = GradCfg<float>::TF;
-        const size_t shm = (size_t)(TF * RRp + TI * RRp + TI * (TF + 1) + TF + 1) * 4 + TF * 16 + 16;
-        float* gp = reinterpret_cast<float*>(w + L.gpart_off);
-        double* lp = reinterpret_cast<double*>(w + L.lpart_off);
-        const float* Sf = static_cast<const float*>(S);
-        const void* kern = d.x_dtype == TR_F32 ? reinterpret_cast<const void*>(&k_grad_partial<float, float>)
-                           : d.x_dtype == TR_F16 ? reinterpret_cast<const void*>(&k_grad_partial<float, __half>)
-                                                 : reinterpret_cast<const void*>(&k_grad_partial<float, __hip_bfloat16>);
-        if (!allow_lds(kern, shm)) return hipErrorInvalidValue;
-        switch (d.x_dtype) {
-            case TR_F32:
-                hipLaunchKernelGGL((k_grad_partial<float, float>), grid, dim3(256), shm, st, d, ms, cores,
-                                   xs, idx, Sf, pF, m, L.groups, L.row_tiles, RRp, gp, lp, maxIRR);
-                break;
-            case TR_F16:
-                hipLaunchKernelGGL((k_grad_partial<float, __half>), grid, dim3(256), shm, st, d, ms,
-                                   cores, xs, idx, Sf, pF, m, L.groups, L.row_tiles, RRp, gp, lp, maxIRR);
-                break;
-            case TR_BF16:
-                hipLaunchKernelGGL((k_grad_partial<float, __hip_bfloat16>), grid, dim3(256), shm, st, d,
-                                   ms, cores, xs, idx, Sf, pF, m, L.groups, L.row_tiles, RRp, gp, lp,
-                                   maxIRR);
-                break;
-            default:
-                return hipErrorInvalidValue;
-        }
+        return launch_grad_mfma_f32(d, ms, cores, xs, idx, static_cast<const float*>(S), pF, m, L.groups, L.row_tiles,
+                                    reinterpret_cast<float*>(w + L.gpart_off), reinterpret_cast<double*>(w + L.lpart_off),
+                                    st);
     }
     return hipGetLastError();
 }
@@ -322,14 +307,24 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
     for (int ch = cb; ch < ce; ++ch) {
         const int f0 = ch * kGramTF;
         __syncthreads();
-        for (int e = tid; e < kGramTF * kGramT; e += 256) {
-            const int f = e / kGramT, c = e % kGramT;
-            const bool okf = f0 + f < m;
-            const double w = okf ? wbase / pF[f0 + f] : 0.0;
-            const double a = (okf && c0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + c0 + c] : 0.0;
-            const double b = (okf && e0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + e0 + c] : 0.0;
-            sA[f][c] = a * w;
-            sB[f][c] = b;
+        {   // every load issued before any LDS store
+            constexpr int V = kGramTF * kGramT / 256;
+            const int c = tid % kGramT, fb = tid / kGramT;
+            double pv[V], av[V], bv[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int f = fb + (256 / kGramT) * v;
+                const bool okf = f0 + f < m;
+                pv[v] = okf ? pF[f0 + f] : 1.0;
+                av[v] = (okf && c0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + c0 + c] : 0.0;
+                bv[v] = (okf && e0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + e0 + c] : 0.0;
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int f = fb + (256 / kGramT) * v;
+                sA[f][c] = av[v] * (wbase / pv[v]);
+                sB[f][c] = bv[v];
+            }
         }
         __syncthreads();
         for (int f = 0; f < kGramTF; ++f) {
@@ -365,7 +360,15 @@ __global__ void k_gram_reduce(tr_desc d, ModeSrc ms, const double* __restrict__ 
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= RR * RR) return;
     double s = 0.0;
-    for (int g = 0; g < groups; ++g) s += part[(int64_t)g * maxRR2 + e];
+    int g = 0;
+    for (; g + 8 <= groups; g += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(g + u) * maxRR2 + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; g < groups; ++g) s += part[(int64_t)g * maxRR2 + e];
     gram[e] = s;
 }
 

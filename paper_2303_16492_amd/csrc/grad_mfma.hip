@@ -1,0 +1,263 @@
+// a5/a6 on the matrix cores: fused fiber gather + prediction + residual +
+// gradient contraction, FP32 in and out, v_mfma_f32_16x16x4_f32.
+//
+// Block = 4 wavefronts = 64 rows of G_{n(2)} (16 per wavefront) x a group
+// of 64-sample chunks.  Per chunk:
+//   GEMM1  P = G S^T      (64 x 64, K = R_n R_{n+1})  A = G rows (registers,
+//                                                     loaded once), B = S (LDS)
+//   E      = X_F - P      fibers read straight from HBM, each lane 4 rows of
+//                         one fiber; scaled by -1/(m J_n p_f); E -> LDS
+//   GEMM2  g += E S       (64 x RR, K = 64 samples)   A = E (LDS), B = S (LDS)
+// The g tile stays in accumulators across the group's chunks and is written
+// once as a partial sum; partials are added in a fixed order afterwards.
+//
+// Operand layouts of v_mfma_f32_16x16x4_f32 (one wavefront, lane l):
+//   A: A[l % 16][l / 16]   B: B[l / 16][l % 16]   D: D[4 (l / 16) + j][l % 16], j < 4.
+#include "internal.hpp"
+
+namespace trk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfTI = 64, kMfTF = 64, kMfEP = kMfTF + 4;
+
+// Row pitch of the staged S chunk: >= RRc and = 20 (mod 64) so that the
+// 16 x 4 lane patterns of both GEMMs fall in distinct LDS banks.
+__host__ __device__ constexpr int mf_pitch(int RRc) { return RRc + ((20 - RRc % 64) + 64) % 64; }
+
+template <typename TX, int CT>
+__global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Ptrs cores, XSrc xsrc,
+                                                       const int32_t* __restrict__ idx, const float* __restrict__ S,
+                                                       const double* __restrict__ pF, int m, int groups,
+                                                       int row_tiles_max, float* __restrict__ gpart,
+                                                       double* __restrict__ lpart, int maxIRR) {
+    uint64_t t;
+    int n;
+    resolve_mode(ms, d.N, &t, &n);
+    const int N = d.N;
+    const int In = d.I[n];
+    const int RR = d.R[n] * d.R[ring_next(n, N)];
+    // Tiles are fixed at compile time (CT column tiles of 16, KQ = 4 CT steps
+    // of K = 4) and every matrix instruction runs unconditionally on
+    // zero-padded operands: a run-time guard around an MFMA makes the compiler
+    // move the accumulators between registers around every instruction.
+    constexpr int KQ = 4 * CT, RRT = 16 * CT;
+    constexpr int RRs = mf_pitch(RRT);
+    const int i0 = blockIdx.x * kMfTI;
+    if (i0 >= In) return;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* sS = reinterpret_cast<float*>(smem_raw);             // [TF][RRs]
+    float* sE = sS + kMfTF * RRs;                               // [TI][EP]
+    float* sW = sE + kMfTI * kMfEP;                             // [TF]
+    double* sL = reinterpret_cast<double*>(sW + kMfTF);         // [TF]
+    int64_t* sB = reinterpret_cast<int64_t*>(sL + kMfTF);       // [TF]
+
+    // A operand of GEMM1: this lane's G row, K in steps of 4.
+    const float* Gn = static_cast<const float*>(cores.p[n]);
+    const int grow = i0 + 16 * w + lr;
+    float ag[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const int k = 4 * q + lk;
+        ag[q] = (grow < In && k < RR) ? Gn[(int64_t)grow * RR + k] : 0.f;
+    }
+    const bool rep = xsrc.rep[n] != nullptr;
+    const TX* X = static_cast<const TX*>(rep ? xsrc.rep[n] : xsrc.X);
+    int64_t xs[kMaxOrder];
+    if (rep) {
+        int64_t s = d.I[n];
+        xs[n] = 1;
+        int k = n;
+        for (int q = 1; q < N; ++q) {
+            k = ring_next(k, N);
+            xs[k] = s;
+            s *= d.I[k];
+        }
+    } else {
+        for (int k = 0; k < N; ++k) xs[k] = d.x_stride[k];
+    }
+    const int64_t xsn = xs[n];
+
+    f32x4 acc2[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc2[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    double lsum = 0.0;
+    const double wbase = 1.0 / ((double)m * (double)J_of(d, n));
+    const int nchunks = (m + kMfTF - 1) / kMfTF;
+    const int cpg = (nchunks + groups - 1) / groups;
+    const int cbeg = blockIdx.y * cpg, cend = min(nchunks, cbeg + cpg);
+    const int erow = 16 * w + 4 * lk;   // first of this lane's 4 D rows (block-local)
+
+    constexpr int SB = (16 * CT + 63) / 64;   // 64-column strips of a staged row
+    for (int ch = cbeg; ch < cend; ++ch) {
+        const int f0 = ch * kMfTF;
+        __syncthreads();
+        {   // stage the S chunk: every load issued before any LDS store
+            float v[16][SB];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                const int f = w + 4 * a;
+                const bool okf = f0 + f < m;
+                const float* src = S + (int64_t)(f0 + f) * RR;
+#pragma unroll
+                for (int b = 0; b < SB; ++b) {
+                    const int c = l + 64 * b;
+                    v[a][b] = (okf && c < RR) ? src[c] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 16; ++a)
+#pragma unroll
+                for (int b = 0; b < SB; ++b) {
+                    const int c = l + 64 * b;
+                    if (c < RRT) sS[(w + 4 * a) * RRs + c] = v[a][b];
+                }
+        }
+        if (tid < kMfTF) {
+            const int f = f0 + tid;
+            bool ok = f < m;
+            int64_t off = 0;
+            int ik[kMaxOrder];
+#pragma unroll
+            for (int k = 0; k < kMaxOrder; ++k) ik[k] = (ok && k < N) ? idx[(int64_t)f * N + k] : 0;
+#pragma unroll
+            for (int k = 0; k < kMaxOrder; ++k) {
+                if (k >= N || k == n) continue;
+                if (ik[k] < 0 || ik[k] >= d.I[k]) ok = false;
+                off += (int64_t)ik[k] * xs[k];
+            }
+            sB[tid] = ok ? off : 0;
+            sW[tid] = ok ? (float)(wbase / pF[f]) : 0.f;
+            sL[tid] = ok ? 1.0 / (2.0 * (double)m * pF[f]) : 0.0;
+        }
+        __syncthreads();
+        // Fiber entries this lane needs, loaded before GEMM1 so that the HBM
+        // latency overlaps the matrix-core work (clamped, branch-free).
+        float xv[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int fl = 16 * u + lr;
+            const bool okf = sW[fl] != 0.f;
+            const int64_t base = sB[fl];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = i0 + erow + j;
+                const int64_t o = (okf && row < In) ? base + (int64_t)row * xsn : 0;
+                xv[u][j] = (float)to_f64(X[o]);
+            }
+        }
+
+        // GEMM1: P[16w + 4lk + j][16t + lr]
+        f32x4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const float a = ag[q];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float b = sS[(16 * u + lr) * RRs + 4 * q + lk];
+                p[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, p[u], 0, 0, 0);
+            }
+        }
+        // E = X_F - P, scaled; loss estimate
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int fl = 16 * u + lr;
+            const float wf = sW[fl];
+            const double lf = sL[fl];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool ok = (i0 + erow + j < In) && wf != 0.f;
+                const float e = ok ? xv[u][j] - p[u][j] : 0.f;
+                lsum += (double)e * (double)e * lf;
+                sE[(erow + j) * kMfEP + fl] = -e * wf;
+            }
+        }
+        __syncthreads();
+        // GEMM2: g[16w + 4lk + j][16ct + lr] += sum_f E[.][f] S[f][.]
+#pragma unroll
+        for (int q = 0; q < kMfTF / 4; ++q) {
+            const float a = sE[(16 * w + lr) * kMfEP + 4 * q + lk];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const float b = sS[(4 * q + lk) * RRs + 16 * c + lr];
+                acc2[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2[c], 0, 0, 0);
+            }
+        }
+    }
+    float* out = gpart + (int64_t)blockIdx.y * maxIRR;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const int col = 16 * c + lr;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = i0 + erow + j;
+            if (row < In && col < RR) out[(int64_t)row * RR + col] = acc2[c][j];
+        }
+    }
+    __shared__ double red[4];
+    const double tot = block_sum(lsum, red);
+    if (tid == 0) lpart[(int64_t)blockIdx.y * row_tiles_max + blockIdx.x] = tot;
+}
+
+template <int CT>
+static constexpr size_t grad_mfma_shm() {
+    return (size_t)(kMfTF * mf_pitch(16 * CT) + kMfTI * kMfEP + kMfTF) * 4 + (size_t)kMfTF * 16 + 64;
+}
+
+template <typename TX, int CT>
+static hipError_t launch_ct(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
+                            const double* pF, int m, dim3 grid, int groups, int row_tiles, float* gp, double* lp,
+                            int maxIRR, hipStream_t st) {
+    constexpr size_t shm = grad_mfma_shm<CT>();
+    if (!allow_lds(reinterpret_cast<const void*>(&k_grad_mfma_f32<TX, CT>), shm)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_grad_mfma_f32<TX, CT>), grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
+                       row_tiles, gp, lp, maxIRR);
+    return hipGetLastError();
+}
+
+// Smallest compiled tile count covering ceil(maxRR / 16) column tiles.
+template <typename TX>
+static hipError_t launch_tx(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
+                            const double* pF, int m, dim3 grid, int groups, int row_tiles, float* gp, double* lp,
+                            int maxIRR, int maxRR, hipStream_t st) {
+    const int nct = (maxRR + 15) / 16;
+#define TRK_CT(C) \
+    if (nct <= C) return launch_ct<TX, C>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st)
+    TRK_CT(1);
+    TRK_CT(2);
+    TRK_CT(3);
+    TRK_CT(4);
+    TRK_CT(5);
+    TRK_CT(6);
+    TRK_CT(7);
+    TRK_CT(8);
+    TRK_CT(10);
+    TRK_CT(12);
+    TRK_CT(16);
+#undef TRK_CT
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
+                                const float* S, const double* pF, int m, int groups, int row_tiles, float* gp,
+                                double* lp, hipStream_t st) {
+    const Shape sh = shape_of(d);
+    const dim3 grid(row_tiles, groups);
+    const int maxIRR = sh.maxI * sh.maxRR;
+    switch (d.x_dtype) {
+        case TR_F32:
+            return launch_tx<float>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
+                                    sh.maxRR, st);
+        case TR_F16:
+            return launch_tx<__half>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
+                                     sh.maxRR, st);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace trk

@@ -34,6 +34,9 @@ struct GradWs {
     int groups, row_tiles, ti, tf;
 };
 GradWs grad_ws_layout(const tr_desc& d, int m, int prec);
+hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
+                                const float* S, const double* pF, int m, int groups, int row_tiles, float* gp,
+                                double* lp, hipStream_t st);
 hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs,
                                const int32_t* idx, const void* S, const double* pF, int m,
                                int prec, void* ws, const GradWs& L, hipStream_t st);
@@ -55,7 +58,7 @@ hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double
 
 // a7/a8: Cholesky of gram + damping (with fallback) then solve and update.
 struct UpdWs {
-    size_t L_off, flag_off, total;
+    size_t L_off, dinv_off, flag_off, total;
 };
 UpdWs upd_ws_layout(const tr_desc& d);
 hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping,

@@ -100,6 +100,9 @@ GRAD_CASES = [
     (3, [70, 33, 65], [4, 5, 3], 200),
     (5, [3, 4, 3, 5, 2], [8, 8, 8, 8, 8], 97),
     (2, [9, 13], [4, 3], 1),
+    (3, [70, 33, 130], [10, 12, 9], 300),     # RR in (64, 128]
+    (3, [40, 20, 30], [16, 16, 16], 129),     # RR = 256
+    (3, [1, 5, 7], [2, 3, 2], 65),            # a mode of size 1
 ]
 
 
@@ -198,6 +201,24 @@ def test_scaled_update_parity(dtype, damping):
         assert int(st) == sref == 0
 
 
+def test_scaled_update_large_gram_global_memory_path():
+    """RR = 144: the factorisation and the solves run from global memory."""
+    dtype = torch.float32
+    I, R, cores, X, dcores, dX = problem(15, 3, [200, 30, 35], [12, 12, 12], dtype)
+    desc = api.make_desc(I, R, dtype)
+    n, m = 0, 700
+    idx, pF = api.tr_sample(desc, 6, 0, n, m)
+    S = api.tr_subchain(desc, n, dcores, idx, m)
+    g, loss, gram = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, L.TR_PREC_F32, want_gram=True)
+    core = dcores[n].clone()
+    say("scaled update RR=144")
+    st = api.tr_update(desc, n, core, g, gram=gram, rule=api.step_rule("fixed", alpha=0.7), t=0)
+    p, sref = brsgd.scaled_direction(g.double().cpu().numpy(), gram.cpu().numpy())
+    assert int(st) == sref
+    cond = np.linalg.cond(gram.cpu().numpy())
+    assert rel(core.cpu().numpy(), unfold(cores[n]) + 0.7 * p) < max(TOL[dtype], 1e-15 * cond)
+
+
 def test_scaled_update_singular_gram_uses_damping_fallback():
     dtype = torch.float64
     I, R, cores, X, dcores, dX = problem(6, 3, [10, 8, 9], [2, 3, 2], dtype)
@@ -214,7 +235,13 @@ def test_scaled_update_singular_gram_uses_damping_fallback():
     assert st == sref
     assert np.all(np.isfinite(core.cpu().numpy()))
     if st == brsgd.DEV_DAMPED:
-        assert rel(core.cpu().numpy(), unfold(cores[n]) + p) < 1e-8
+        # the damped matrix is nearly singular: agreement is bounded by its
+        # condition number times the unit roundoff
+        h = gram.cpu().numpy()
+        ok = [k for k in range(7)
+              if np.all(np.linalg.eigvalsh(h + 10.0 ** (k - 10) * np.trace(h) / 6 * np.eye(6)) > 0)]
+        hd = h + 10.0 ** (ok[0] - 10) * np.trace(h) / 6 * np.eye(6)
+        assert rel(core.cpu().numpy(), unfold(cores[n]) + p) < 1e-15 * np.linalg.cond(hd)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -276,3 +303,54 @@ def test_relerr_zero_at_truth_fp64():
     rse = float(api.tr_relerr(desc, [to_dev(unfold(c), torch.float64) for c in cores],
                               to_dev(flat_paper(X), torch.float64)))
     assert rse < 1e-14
+
+
+def test_full_size_scaled_step_at_bench_configuration():
+    """One TR-ScaledBRSGD step of the 400^3, rank-10, kappa = 1e4 workload with
+    |F_n| = 4096, in the launch configuration the benchmark times: indices
+    bit-exact, S, g, Gram, the updated core and the RSE against the oracle."""
+    dtype = torch.float32
+    N, I, R, m = 3, 400, 10, 4096
+    true3 = ti.illcond_cores(0, N, I, R, 1e4)
+    X = tr.full_tensor(true3)
+    X = rounded(X / np.sqrt(np.mean(X * X)), dtype)
+    init = [rounded(c, dtype) for c in ti.gaussian_cores(1, N, I, R, scale=(1.0 / R ** N) ** (1 / (2 * N)))]
+    desc = api.make_desc([I] * N, [R] * N, dtype)
+    dX = to_dev(flat_paper(X), dtype)
+    dc = [to_dev(unfold(c), dtype) for c in init]
+    Xr = [api.tr_x_replicate(desc, dX, k) for k in range(N)]
+    for step in range(3):
+        n = api.tr_mode(0, step, N)
+        say("full-size step", step, "mode", n)
+        idx, pF = api.tr_sample(desc, 0, step, n, m)
+        ridx, rpF = sampling.draw(0, step, n, m, [I] * N)
+        assert np.array_equal(idx.cpu().numpy(), ridx) and np.array_equal(pF.cpu().numpy(), rpF)
+        S = api.tr_subchain(desc, n, dc, idx, m)
+        cores_now = [fold(c.double().cpu().numpy(), R, R) for c in dc]
+        assert rel(S.cpu().numpy(), brsgd.subchain_rows(cores_now, n, ridx)) < TOL[dtype]
+        order = [(n + q) % N for q in range(1, N)]
+        strides = [0] * N
+        strides[n] = 1
+        sz = I
+        for k in order:
+            strides[k] = sz
+            sz *= I
+        drep = api.make_desc([I] * N, [R] * N, dtype, x_strides=strides)
+        g, loss, gram = api.tr_grad(drep, n, dc[n], Xr[n], idx, S, pF, m, L.TR_PREC_F32, want_gram=True)
+        Sin = S.double().cpu().numpy()
+        XF = brsgd.gather_fibers(X, n, ridx)
+        gref, lref = brsgd.stoch_grad(unfold(cores_now[n]), Sin, XF, rpF, I * I)
+        assert rel(g.cpu().numpy(), gref) < TOL[dtype]
+        assert abs(float(loss) - lref) <= TOL[dtype] * lref
+        href = brsgd.stoch_hessian(Sin, rpF, I * I)
+        assert rel(gram.cpu().numpy(), href) < 1e-12
+        before = unfold(cores_now[n])
+        api.tr_update(desc, n, dc[n], g, gram=gram, rule=api.step_rule("fixed", alpha=1.0), t=step)
+        p, st = brsgd.scaled_direction(g.double().cpu().numpy(), gram.cpu().numpy())
+        got = dc[n].double().cpu().numpy()
+        # the solve amplifies rounding by the condition number of h
+        cond = np.linalg.cond(gram.cpu().numpy())
+        assert rel(got - before, p) < max(1e-5, 1e-15 * cond), (rel(got - before, p), cond)
+    cores_now = [fold(c.double().cpu().numpy(), R, R) for c in dc]
+    rse = float(api.tr_relerr(desc, dc, dX))
+    assert abs(rse - tr.rse(cores_now, X)) < 1e-5 * tr.rse(cores_now, X)
