@@ -169,7 +169,7 @@ def main():
     achieved = flops / (kern_avg_us * 1e-6) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 5), "traffic": None,
-            "kernel": "k_grad_mfma_f32", "kernel_avg_us": round(kern_avg_us, 3),
+            "kernel": "k_grad_mfma_f32" if args.prec == "f32" else "k_grad_mixed", "kernel_avg_us": round(kern_avg_us, 3),
             "flops_per_launch": flops, "alg_bytes_per_launch": bytes_alg,
             "alg_hbm_gbs": round(bytes_alg / (kern_avg_us * 1e-6) / 1e9, 1)}
 

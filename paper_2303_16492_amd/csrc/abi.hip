@@ -228,8 +228,7 @@ tr_status tr_subchain(const tr_desc* d, int32_t n, const void* const* cores, con
 static tr_status check_prec(const tr_desc* d, int32_t prec) {
     if (d->core_dtype == TR_F64) return prec == TR_PREC_F64 ? TR_OK : TR_E_DTYPE;
     if (d->x_dtype == TR_BF16) return TR_E_UNSUPPORTED;
-    if (prec == TR_PREC_F32) return TR_OK;
-    if (prec == TR_PREC_BF16 || prec == TR_PREC_F16) return TR_E_UNSUPPORTED;
+    if (prec == TR_PREC_F32 || prec == TR_PREC_BF16 || prec == TR_PREC_F16) return TR_OK;
     return TR_E_DTYPE;
 }
 

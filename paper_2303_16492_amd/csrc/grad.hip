@@ -231,7 +231,6 @@ GradWs grad_ws_layout(const tr_desc& d, int m, int prec) {
 hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
                                const void* S, const double* pF, int m, int prec, void* ws,
                                const GradWs& L, hipStream_t st) {
-    (void)prec;
     const Shape sh = shape_of(d);
     const int RRp = sh.maxRR | 1;   // odd row pitch: rows of sG/sS fall in different LDS banks
     const dim3 grid(L.row_tiles, L.groups);
@@ -246,6 +245,10 @@ hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
                            idx, static_cast<const double*>(S), pF, m, L.groups, L.row_tiles, RRp,
                            reinterpret_cast<double*>(w + L.gpart_off),
                            reinterpret_cast<double*>(w + L.lpart_off), maxIRR);
+    } else if (prec == TR_PREC_BF16 || prec == TR_PREC_F16) {
+        return launch_grad_mixed(d, ms, cores, xs, idx, static_cast<const float*>(S), pF, m, prec, L.groups,
+                                 L.row_tiles, reinterpret_cast<float*>(w + L.gpart_off),
+                                 reinterpret_cast<double*>(w + L.lpart_off), st);
     } else {
         return launch_grad_mfma_f32(d, ms, cores, xs, idx, static_cast<const float*>(S), pF, m, L.groups, L.row_tiles,
                                     reinterpret_cast<float*>(w + L.gpart_off), reinterpret_cast<double*>(w + L.lpart_off),

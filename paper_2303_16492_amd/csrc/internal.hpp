@@ -37,6 +37,9 @@ GradWs grad_ws_layout(const tr_desc& d, int m, int prec);
 hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
                                 const float* S, const double* pF, int m, int groups, int row_tiles, float* gp,
                                 double* lp, hipStream_t st);
+hipError_t launch_grad_mixed(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
+                             const double* pF, int m, int prec, int groups, int row_tiles, float* gp, double* lp,
+                             hipStream_t st);
 hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs,
                                const int32_t* idx, const void* S, const double* pF, int m,
                                int prec, void* ws, const GradWs& L, hipStream_t st);

@@ -354,3 +354,76 @@ def test_full_size_scaled_step_at_bench_configuration():
     cores_now = [fold(c.double().cpu().numpy(), R, R) for c in dc]
     rse = float(api.tr_relerr(desc, dc, dX))
     assert abs(rse - tr.rse(cores_now, X)) < 1e-5 * tr.rse(cores_now, X)
+
+
+MIXED_CASES = [
+    (3, [20, 20, 20], [3, 3, 3], 100),
+    (4, [12, 9, 17, 6], [2, 5, 3, 4], 513),
+    (3, [70, 33, 130], [10, 12, 9], 300),
+    (3, [40, 20, 30], [16, 16, 16], 129),
+    (2, [9, 13], [4, 3], 1),
+]
+
+
+@pytest.mark.parametrize("prec,xdt", [(L.TR_PREC_BF16, torch.float32), (L.TR_PREC_F16, torch.float32),
+                                      (L.TR_PREC_F16, torch.float16), (L.TR_PREC_BF16, torch.float16)])
+@pytest.mark.parametrize("N,I,R,m", MIXED_CASES)
+def test_grad_mixed_precision_parity(N, I, R, m, prec, xdt):
+    """16-bit matrix-core gradient (hi/lo split prediction) against the FP64
+    oracle on the same inputs: normwise 5e-3 (the 16-bit bar)."""
+    I, R, cores, X, dcores, dX = problem(12, N, I, R, torch.float32)
+    X = rounded(X, xdt)
+    dX = to_dev(flat_paper(X), xdt)
+    desc = api.make_desc(I, R, torch.float32, xdt)
+    for n in range(N):
+        say("mixed grad", prec, xdt, N, I, R, m, n)
+        idx, pF = api.tr_sample(desc, 4, 1, n, m)
+        S = api.tr_subchain(desc, n, dcores, idx, m)
+        g, loss, _ = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, prec)
+        idn, pFn = idx.cpu().numpy(), pF.cpu().numpy()
+        gref, lref = brsgd.stoch_grad(unfold(cores[n]), S.double().cpu().numpy(),
+                                      brsgd.gather_fibers(X, n, idn), pFn, brsgd.J_of(I, n))
+        assert rel(g.cpu().numpy(), gref) < TOL[torch.bfloat16]
+        assert abs(float(loss) - lref) <= TOL[torch.bfloat16] * lref
+
+
+def test_mixed_prediction_resolves_small_residuals():
+    """Near a fit (residual ~1e-2 of X) the hi/lo prediction (16 mantissa
+    bits, error ~1e-5 |X|) keeps the gradient within the 16-bit bar relative
+    to the residual; one BF16 product (error ~2^-9 |X|) would be ~20% off."""
+    I, R = [60, 50, 40], [4, 3, 5]
+    cores = [rounded(c, torch.float32) for c in ti.gaussian_cores(3, 3, I, R)]
+    Xc = tr.full_tensor(cores)
+    X = rounded(Xc + 1e-2 * np.sqrt(np.mean(Xc * Xc)) * ti.standard_normal(4, I), torch.float32)
+    desc = api.make_desc(I, R, torch.float32)
+    dc = [to_dev(unfold(c), torch.float32) for c in cores]
+    dX = to_dev(flat_paper(X), torch.float32)
+    n, m = 1, 512
+    idx, pF = api.tr_sample(desc, 2, 0, n, m)
+    S = api.tr_subchain(desc, n, dc, idx, m)
+    g, _, _ = api.tr_grad(desc, n, dc[n], dX, idx, S, pF, m, L.TR_PREC_BF16)
+    gref, _ = brsgd.stoch_grad(unfold(cores[n]), S.double().cpu().numpy(),
+                               brsgd.gather_fibers(X, n, idx.cpu().numpy()), pF.cpu().numpy(), 60 * 40)
+    assert rel(g.cpu().numpy(), gref) < TOL[torch.bfloat16]
+
+
+def test_full_size_mixed_gradient_at_bench_configuration():
+    dtype = torch.float32
+    N, I, R, m = 3, 400, 10, 4096
+    true3 = ti.illcond_cores(0, N, I, R, 1e4)
+    X = tr.full_tensor(true3)
+    X = rounded(X / np.sqrt(np.mean(X * X)), dtype)
+    init = [rounded(c, dtype) for c in ti.gaussian_cores(1, N, I, R, scale=(1.0 / R ** N) ** (1 / (2 * N)))]
+    desc = api.make_desc([I] * N, [R] * N, dtype)
+    dX = to_dev(flat_paper(X), dtype)
+    dc = [to_dev(unfold(c), dtype) for c in init]
+    for step in range(3):
+        n = api.tr_mode(0, step, N)
+        say("full-size mixed", step, n)
+        idx, pF = api.tr_sample(desc, 0, step, n, m)
+        S = api.tr_subchain(desc, n, dc, idx, m)
+        g, loss, _ = api.tr_grad(desc, n, dc[n], dX, idx, S, pF, m, L.TR_PREC_BF16)
+        gref, lref = brsgd.stoch_grad(unfold(init[n]), S.double().cpu().numpy(),
+                                      brsgd.gather_fibers(X, n, idx.cpu().numpy()), pF.cpu().numpy(), I * I)
+        assert rel(g.cpu().numpy(), gref) < TOL[torch.bfloat16]
+        assert abs(float(loss) - lref) <= TOL[torch.bfloat16] * lref

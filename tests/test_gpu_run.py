@@ -177,3 +177,22 @@ def test_loss_estimates_written_per_step():
         brsgd.step(st, X, cfg, trace=tr_)
         ref.append(tr_["loss"])
     assert rel(losses.cpu().numpy(), np.array(ref)) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_mixed_scaled_run_tracks_oracle(prec):
+    """A few mixed-precision scaled steps stay within the 16-bit bar of the
+    FP64 oracle's trajectory."""
+    dtype = torch.float32
+    X, _, init = planted(3, [30, 25, 28], [3, 3, 3], dtype, noise_db=None)
+    dX = to_dev(flat_paper(X), dtype)
+    sol = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [30, 25, 28], [3, 3, 3], 200, scaled=True,
+                   prec=prec, rule=api.step_rule("fixed", alpha=0.5))
+    sol.run(6)
+    st = brsgd.State(init)
+    cfg = brsgd.Config(m=200, variant="scaled", alpha=0.5)
+    for _ in range(6):
+        brsgd.step(st, X, cfg)
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 5e-3
