@@ -78,11 +78,22 @@ hipError_t launch_bump(uint64_t* t_dev, hipStream_t st) {
     return hipGetLastError();
 }
 
+// A kernel, not hipMemsetAsync: tr_run may be captured into a graph.
+__global__ void k_zero_u32(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((n + 63) / 64), dim3(64), 0, st, p, n);
+    return hipGetLastError();
+}
+
 constexpr int kMaxM = 1 << 24;
 
 // Workspace plan of tr_run.
 struct RunWs {
-    size_t idx, pF, S, g, gram, idxH, pH, SH, grad, gramws, upd, dist, opt, loss, total;
+    size_t idx, pF, S, g, gram, idxH, pH, SH, grad, gramws, upd, dist, opt, loss, ctr, total;
     GradWs gl;
     GramWs ml, mlH;
     UpdWs ul;
@@ -118,6 +129,7 @@ static RunWs run_layout(const tr_problem* p, const tr_config* c) {
     L.dist = take(dist_ws_bytes(d, c->law));
     L.opt = take(c->law == TR_LAW_OPTIMAL ? dist_opt_ws_bytes(d) : 0);
     L.loss = take(8);
+    L.ctr = take(4);
     L.total = o;
     return L;
 }
@@ -405,6 +417,12 @@ tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev
     xs_paper.X = p->X;
     hipError_t e = hipSuccess;
     const bool refresh = c->law == TR_LAW_LEVERAGE || c->law == TR_LAW_EUCLID;
+    // The step counter advances in the last kernel of a step when that is
+    // the update; the law refresh of E/L reads the step's mode after it, so
+    // those laws keep a separate bump.
+    unsigned* ctr = reinterpret_cast<unsigned*>(w + L.ctr);
+    const StepBump fused = refresh ? StepBump{} : StepBump{t_dev, ctr};
+    if (!refresh) e = launch_zero_u32(ctr, 1, st);
     if (refresh)
         for (int k = 0; k < d.N && e == hipSuccess; ++k)
             e = launch_dist(d, ModeSrc{nullptr, 0, k, 0}, false, k, c->law, cores, p->cdf, dev_status,
@@ -422,8 +440,12 @@ tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev
         if (e == hipSuccess && ev_end && ev_end[it]) e = hipEventRecord((hipEvent_t)ev_end[it], st);
         if (e != hipSuccess) break;
         if (c->scaled) {
-            e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, loss, false, MutPtrs{}, MutPtrs{}, c->rule, dev_status,
-                                   st);
+            // RR <= 128: the sweep's apply kernel adds the gradient partials
+            // and the loss itself
+            const bool sweep = sweep_supported(d);
+            if (!sweep)
+                e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, loss, false, MutPtrs{}, MutPtrs{}, c->rule,
+                                       dev_status, st);
             if (e == hipSuccess) {
                 if (c->m_H > 0) {
                     int32_t* idxH = reinterpret_cast<int32_t*>(w + L.idxH);
@@ -436,15 +458,27 @@ tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev
                     e = launch_gram(d, ms, S, pF, c->m, gram, w + L.gramws, L.ml, st);
                 }
             }
-            if (e == hipSuccess)
+            if (e == hipSuccess && sweep) {
+                const Shape sh = shape_of(d);
+                const char* gw = w + L.grad;
+                e = launch_sweep_update(d, ms, gram, c->damping, gw + L.gl.gpart_off, L.gl.groups,
+                                        (int64_t)sh.maxI * sh.maxRR,
+                                        LossParts{reinterpret_cast<const double*>(gw + L.gl.lpart_off), L.gl.groups,
+                                                  L.gl.row_tiles, L.gl.ti},
+                                        loss, mcores, acc, c->rule, dev_status, w + L.upd, L.ul, fused, st);
+            } else if (e == hipSuccess) {
                 e = launch_scaled_update(d, ms, gram, c->damping, g, mcores, acc, c->rule, dev_status, w + L.upd, L.ul,
                                          st);
+                if (e == hipSuccess && fused.t) e = launch_bump(t_dev, st);
+            }
         } else {
-            e = launch_grad_reduce(d, ms, w + L.grad, L.gl, nullptr, loss, true, mcores, acc, c->rule, dev_status, st);
+            e = launch_grad_reduce(d, ms, w + L.grad, L.gl, nullptr, loss, true, mcores, acc, c->rule, dev_status, st,
+                                   fused);
         }
-        if (e == hipSuccess && refresh)
+        if (e == hipSuccess && refresh) {
             e = launch_dist(d, ms, true, 0, c->law, cores, p->cdf, dev_status, w + L.dist, st);
-        if (e == hipSuccess) e = launch_bump(t_dev, st);
+            if (e == hipSuccess) e = launch_bump(t_dev, st);
+        }
     }
     return hip_status(e);
 }

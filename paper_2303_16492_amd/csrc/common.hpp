@@ -181,6 +181,28 @@ __device__ inline void set_status(int32_t* st, int32_t bits) {
 // Step rule for one core entry: eq:update_brsgd (fixed alpha), Robbins-Monro
 // alpha_t = alpha/(1 + t/tau), or the AdaGrad remark (accumulator includes
 // the current step; no change where b + A == 0).
+// The same with the entry's current value ``old`` and AdaGrad accumulator
+// ``acc_old`` already loaded (callers that fetch them early).
+template <typename TC>
+__device__ inline void apply_rule_loaded(TC* G, TC* A, int64_t e, double old, double acc_old, double p,
+                                         const tr_step& rule, uint64_t t, int32_t* status) {
+    double nv;
+    if (rule.kind == 1) {
+        const double a = acc_old + p * p;
+        A[e] = (TC)a;
+        const double base = rule.b + a;
+        double stepm = 0.0;
+        if (base > 0.0) stepm = rule.eta / (rule.eps == 0.0 ? sqrt(base) : pow(base, 0.5 + rule.eps));
+        nv = old + stepm * p;
+    } else if (rule.kind == 2) {
+        nv = old + rule.alpha / (1.0 + (double)t / rule.tau) * p;
+    } else {
+        nv = old + rule.alpha * p;
+    }
+    if (!isfinite(nv)) set_status(status, TR_DEV_NONFINITE);
+    G[e] = (TC)nv;
+}
+
 template <typename TC>
 __device__ inline void apply_rule(TC* G, TC* A, int64_t e, double p, const tr_step& rule, uint64_t t,
                                   int32_t* status) {

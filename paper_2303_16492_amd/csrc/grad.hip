@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_grad_reduce(tr_desc d, ModeSrc ms, cons
                                                      int row_tiles_max, int TI, int maxIRR,
                                                      TC* __restrict__ g, double* __restrict__ loss,
                                                      int apply, MutPtrs cores, MutPtrs accum,
-                                                     tr_step rule, int32_t* status) {
+                                                     tr_step rule, int32_t* status, StepBump step) {
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
@@ -178,31 +178,29 @@ __global__ __launch_bounds__(256) void k_grad_reduce(tr_desc d, ModeSrc ms, cons
     const int64_t total = (int64_t)In * RR;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (blockIdx.x == 0 && loss) {
-        const int rt = (In + TI - 1) / TI;
-        double s = 0.0;
-        if (threadIdx.x == 0) {
-            for (int gi = 0; gi < groups; ++gi)
-                for (int b = 0; b < rt; ++b) s += lpart[(int64_t)gi * row_tiles_max + b];
-            *loss = s;
+        __shared__ double red[4];
+        const double s = loss_parts_sum(LossParts{lpart, groups, row_tiles_max, TI}, In, red);
+        if (threadIdx.x == 0) *loss = s;
+    }
+    if (e < total) {
+        constexpr int GB = 32;   // partial slices fetched together, added in group order
+        TC acc = TC(0);
+        for (int gi = 0; gi < groups; gi += GB) {
+            TC v[GB];
+#pragma unroll
+            for (int u = 0; u < GB; ++u) v[u] = gi + u < groups ? gpart[(int64_t)(gi + u) * maxIRR + e] : TC(0);
+#pragma unroll
+            for (int u = 0; u < GB; ++u)
+                if (gi + u < groups) acc += v[u];
+        }
+        if (g) g[e] = acc;
+        if (apply) {
+            TC* G = static_cast<TC*>(cores.p[n]);
+            TC* A = static_cast<TC*>(accum.p[n]);
+            apply_rule<TC>(G, A, e, -(double)acc, rule, t, status);
         }
     }
-    if (e >= total) return;
-    TC acc = TC(0);
-    int gi = 0;
-    for (; gi + 8 <= groups; gi += 8) {   // loads issued together, added in group order
-        TC v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = gpart[(int64_t)(gi + u) * maxIRR + e];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
-    }
-    for (; gi < groups; ++gi) acc += gpart[(int64_t)gi * maxIRR + e];
-    if (g) g[e] = acc;
-    if (apply) {
-        TC* G = static_cast<TC*>(cores.p[n]);
-        TC* A = static_cast<TC*>(accum.p[n]);
-        apply_rule<TC>(G, A, e, -(double)acc, rule, t, status);
-    }
+    bump_if_last(step);
 }
 
 GradWs grad_ws_layout(const tr_desc& d, int m, int prec) {
@@ -259,7 +257,7 @@ hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
 
 hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, const GradWs& L, void* g,
                               double* loss, bool apply, MutPtrs cores, MutPtrs accum, tr_step rule,
-                              int32_t* status, hipStream_t st) {
+                              int32_t* status, hipStream_t st, StepBump step) {
     const Shape sh = shape_of(d);
     const int maxIRR = sh.maxI * sh.maxRR;
     const dim3 grid((unsigned)((maxIRR + 255) / 256));
@@ -269,22 +267,34 @@ hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, cons
         hipLaunchKernelGGL(k_grad_reduce<double>, grid, dim3(256), 0, st, d, ms,
                            reinterpret_cast<const double*>(w + L.gpart_off), lp, L.groups, L.row_tiles,
                            L.ti, maxIRR, static_cast<double*>(g), loss, (int)apply, cores, accum, rule,
-                           status);
+                           status, step);
     else
         hipLaunchKernelGGL(k_grad_reduce<float>, grid, dim3(256), 0, st, d, ms,
                            reinterpret_cast<const float*>(w + L.gpart_off), lp, L.groups, L.row_tiles,
                            L.ti, maxIRR, static_cast<float*>(g), loss, (int)apply, cores, accum, rule,
-                           status);
+                           status, step);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ Gram --
 // gram[c][c'] = sum_f S[f][c] S[f][c'] / (m J_n pF_f), products and sums in
-// FP64 from the stored S.  Blocks tile the RR x RR output in 64 x 64 tiles
-// and split the samples into groups; a second kernel adds the groups in a
-// fixed order.
+// FP64 from the stored S.  Blocks take the lower-triangular 32 x 32 tiles
+// of the RR x RR output times groups of samples: a block fetches its
+// samples' S columns and weights in one batch (FP32 S stays FP32 in LDS),
+// then each thread accumulates a 2 x 2 block.  A second kernel adds the
+// groups in a fixed order and mirrors the lower triangle.
 
-constexpr int kGramT = 64, kGramTF = 32;
+constexpr int kGramT = 32;
+template <typename TC>
+struct GramChunk {   // samples staged per round: 2 x F x 33 values of TC stay under 64 KiB
+    static constexpr int F = sizeof(TC) == 8 ? 64 : 128;
+};
+
+__host__ __device__ inline void gram_tile(int tile, int& ct, int& et) {   // tile -> (ct >= et)
+    ct = 0;
+    while ((ct + 1) * (ct + 2) / 2 <= tile) ++ct;
+    et = tile - ct * (ct + 1) / 2;
+}
 
 template <typename TC>
 __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, const TC* __restrict__ S,
@@ -297,63 +307,67 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
     const int RR = d.R[n] * d.R[ring_next(n, d.N)];
     const int tpd = (RR + kGramT - 1) / kGramT;
     const int tile = blockIdx.x;
-    if (tile >= tpd * tpd) return;
-    const int c0 = (tile / tpd) * kGramT, e0 = (tile % tpd) * kGramT;
-    __shared__ double sA[kGramTF][kGramT + 1], sB[kGramTF][kGramT + 1];
+    if (tile >= tpd * (tpd + 1) / 2) return;
+    int ct, et;
+    gram_tile(tile, ct, et);
+    const int c0 = ct * kGramT, e0 = et * kGramT;
+    constexpr int kGramF = GramChunk<TC>::F;
+    __shared__ TC sA[kGramF][kGramT + 1], sB[kGramF][kGramT + 1];
+    __shared__ double sw[kGramF];
     const int tid = threadIdx.x;
-    const int tr_ = (tid / 16) * 4, tc = (tid % 16) * 4;
-    double acc[4][4] = {};
     const double wbase = 1.0 / ((double)m * (double)J_of(d, n));
-    const int nch = (m + kGramTF - 1) / kGramTF;
-    const int cpg = (nch + groups - 1) / groups;
-    const int cb = blockIdx.y * cpg, ce = min(nch, cb + cpg);
-    for (int ch = cb; ch < ce; ++ch) {
-        const int f0 = ch * kGramTF;
+    const int per = (m + groups - 1) / groups;
+    const int fb = blockIdx.y * per, fe = min(m, fb + per);
+    const int tr_ = (tid >> 4) * 2, tc = (tid & 15) * 2;
+    double acc[2][2] = {};
+    for (int f0 = fb; f0 < fe; f0 += kGramF) {
         __syncthreads();
-        {   // every load issued before any LDS store
-            constexpr int V = kGramTF * kGramT / 256;
-            const int c = tid % kGramT, fb = tid / kGramT;
-            double pv[V], av[V], bv[V];
+        {   // every load of the chunk issued before any LDS store
+            constexpr int V = kGramF * kGramT / 256;
+            const int c = tid & (kGramT - 1), fo = tid >> 5;
+            TC av[V], bv[V];
+            double pv = 1.0;
+            if (tid < kGramF) pv = f0 + tid < fe ? pF[f0 + tid] : 1.0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int f = fb + (256 / kGramT) * v;
-                const bool okf = f0 + f < m;
-                pv[v] = okf ? pF[f0 + f] : 1.0;
-                av[v] = (okf && c0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + c0 + c] : 0.0;
-                bv[v] = (okf && e0 + c < RR) ? (double)S[(int64_t)(f0 + f) * RR + e0 + c] : 0.0;
+                const int f = fo + 8 * v;
+                const bool okf = f0 + f < fe;
+                av[v] = (okf && c0 + c < RR) ? S[(int64_t)(f0 + f) * RR + c0 + c] : TC(0);
+                bv[v] = (okf && e0 + c < RR) ? S[(int64_t)(f0 + f) * RR + e0 + c] : TC(0);
             }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int f = fb + (256 / kGramT) * v;
-                sA[f][c] = av[v] * (wbase / pv[v]);
+                const int f = fo + 8 * v;
+                sA[f][c] = av[v];
                 sB[f][c] = bv[v];
             }
+            if (tid < kGramF) sw[tid] = f0 + tid < fe ? wbase / pv : 0.0;
         }
         __syncthreads();
-        for (int f = 0; f < kGramTF; ++f) {
-            double a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = sA[f][tr_ + u];
-                b[u] = sB[f][tc + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        const int nf = min(kGramF, fe - f0);
+        for (int f = 0; f < nf; ++f) {
+            const double w = sw[f];
+            const double a0 = (double)sA[f][tr_] * w, a1 = (double)sA[f][tr_ + 1] * w;
+            const double b0 = (double)sB[f][tc], b1 = (double)sB[f][tc + 1];
+            acc[0][0] += a0 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][0] += a1 * b0;
+            acc[1][1] += a1 * b1;
         }
     }
     double* out = part + (int64_t)blockIdx.y * maxRR2;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 2; ++v) {
             const int c = c0 + tr_ + u, e = e0 + tc + v;
             if (c < RR && e < RR) out[(int64_t)c * RR + e] = acc[u][v];
         }
     (void)tiles_max;
 }
 
+// gram = sum of the group partials in group order; entries above the
+// diagonal come from their mirror (only lower tiles are computed).
 __global__ void k_gram_reduce(tr_desc d, ModeSrc ms, const double* __restrict__ part, int groups, int maxRR2,
                               double* __restrict__ gram) {
     uint64_t t;
@@ -362,16 +376,23 @@ __global__ void k_gram_reduce(tr_desc d, ModeSrc ms, const double* __restrict__ 
     const int RR = d.R[n] * d.R[ring_next(n, d.N)];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= RR * RR) return;
+    const int r = e / RR, c = e - r * RR;
+    const bool lower = (r / kGramT) >= (c / kGramT);   // tile computed as stored
+    const int src = lower ? e : c * RR + r;
+    constexpr int GB = 32;
     double s = 0.0;
-    int g = 0;
-    for (; g + 8 <= groups; g += 8) {
-        double v[8];
+    for (int g = 0; g < groups; g += GB) {
+        double v[GB];
+        const double* q = part + (int64_t)g * maxRR2 + src;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(g + u) * maxRR2 + e];
+        for (int u = 0; u < GB; ++u) {
+            v[u] = g + u < groups ? *q : 0.0;
+            q += maxRR2;
+        }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
+        for (int u = 0; u < GB; ++u)
+            if (g + u < groups) s += v[u];
     }
-    for (; g < groups; ++g) s += part[(int64_t)g * maxRR2 + e];
     gram[e] = s;
 }
 
@@ -379,13 +400,14 @@ GramWs gram_ws_layout(const tr_desc& d, int m) {
     GramWs L{};
     const Shape sh = shape_of(d);
     const int tpd = (sh.maxRR + kGramT - 1) / kGramT;
-    L.tiles = tpd * tpd;
-    const int nch = (m + kGramTF - 1) / kGramTF;
-    int groups = (256 + L.tiles - 1) / L.tiles;
-    groups = groups > nch ? nch : groups;
+    L.tiles = tpd * (tpd + 1) / 2;
+    // about 320 blocks, at least 16 samples per group
+    int groups = (320 + L.tiles - 1) / L.tiles;
+    const int gmax = (m + 15) / 16;
+    groups = groups > gmax ? gmax : groups;
     groups = groups < 1 ? 1 : groups;
-    const int cpg = (nch + groups - 1) / groups;
-    L.groups = (nch + cpg - 1) / cpg;
+    const int per = (m + groups - 1) / groups;
+    L.groups = (m + per - 1) / per;
     if (L.groups < 1) L.groups = 1;
     L.part_off = 0;
     L.total = align_up((size_t)L.groups * sh.maxRR * sh.maxRR * 8);

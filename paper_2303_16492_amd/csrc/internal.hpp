@@ -44,11 +44,51 @@ hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
                                const int32_t* idx, const void* S, const double* pF, int m,
                                int prec, void* ws, const GradWs& L, hipStream_t st);
 
+// Per-block loss partials of the gradient kernels: part[g * tiles_max + b]
+// for sample group g and row tile b < ceil(I_n / ti).
+struct LossParts {
+    const double* part;
+    int groups, tiles_max, ti;
+};
+// Their sum in a fixed order (strided per thread, then the block tree);
+// valid in every thread.  ``red`` needs blockDim/64 entries.
+__device__ inline double loss_parts_sum(const LossParts& lp, int In, double* red) {
+    const int rt = (In + lp.ti - 1) / lp.ti;
+    const int tot = lp.groups * rt;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int g = i / rt, b = i - g * rt;
+        s += lp.part[(int64_t)g * lp.tiles_max + b];
+    }
+    return block_sum(s, red);
+}
+
+// Step-counter advance folded into the last kernel of a step: every block
+// counts itself in ``ctr`` once it is done (and so has read the counter);
+// the last one resets ``ctr`` and adds 1 to ``t``.  Disabled when t is null.
+struct StepBump {
+    uint64_t* t;
+    unsigned* ctr;
+};
+__device__ inline void bump_if_last(const StepBump& b) {
+    if (!b.t) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+        if (atomicAdd(b.ctr, 1u) == nb - 1) {
+            atomicExch(b.ctr, 0u);
+            atomicAdd(reinterpret_cast<unsigned long long*>(b.t), 1ull);
+            __threadfence();
+        }
+    }
+}
+
 // Reduce partials into g (core dtype) and the loss; optionally apply the
 // plain direction p = -g with ``rule`` to the core in place.
 hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, const GradWs& L,
                               void* g, double* loss, bool apply, MutPtrs cores, MutPtrs accum,
-                              tr_step rule, int32_t* status, hipStream_t st);
+                              tr_step rule, int32_t* status, hipStream_t st, StepBump step = StepBump{});
 
 // FP64-accumulated Gram S^T diag(1/(m J_n pF)) S.
 struct GramWs {
@@ -67,6 +107,14 @@ UpdWs upd_ws_layout(const tr_desc& d);
 hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping,
                                 const void* g, MutPtrs cores, MutPtrs accum, tr_step rule,
                                 int32_t* status, void* ws, const UpdWs& L, hipStream_t st);
+// The same for RR <= 128 through the blocked sweep: g is the fixed-order
+// sum of ``groups`` slices of gsrc (stride gstride; 1 and 0 for a plain g);
+// with lp.part set the loss is written too.
+bool sweep_supported(const tr_desc& d);
+hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* gsrc,
+                               int groups, int64_t gstride, LossParts lp, double* loss, MutPtrs cores,
+                               MutPtrs accum, tr_step rule, int32_t* status, void* ws, const UpdWs& L,
+                               StepBump step, hipStream_t st);
 hipError_t launch_plain_update(const tr_desc& d, ModeSrc ms, const void* g, MutPtrs cores,
                                MutPtrs accum, tr_step rule, int32_t* status, hipStream_t st);
 
@@ -79,6 +127,7 @@ hipError_t launch_dist_optimal(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
                                uint64_t* cdf_J, int32_t* status, void* ws, hipStream_t st);
 
 hipError_t launch_bump(uint64_t* t_dev, hipStream_t st);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 
 }  // namespace trk
 

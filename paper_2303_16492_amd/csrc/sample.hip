@@ -1,128 +1,206 @@
 // a1/a3/a4: mode pick, index draws with their probabilities, and the sampled
 // rows of the subchain matrix (Algorithm SSDTP).
 //
-// One thread per (sample f, row s of M_f).  Every thread of a sample draws
-// the sample's indices itself (a few Philox blocks: cheaper than a barrier),
-// the s == 0 thread stores idx and p_F.  The row s of
-// M_f = G_{n+1}(i_{n+1}) ... G_{n-1}(i_{n-1}) starts as e_s and is carried
-// through the chain in registers: v <- v * G_k(i_k), R_k x R_{k+1} slices
-// read from L1/L2 (cores are small).  The thread writes S[f][r + R_n s] for
-// r < R_n: the R_{n+1} threads of a sample write one contiguous row.
+// S[f][r + R_n s] = M_f(s, r) with M_f = G_{n+1}(i_{n+1}) ... G_{n-1}(i_{n-1})
+// (the product of slices of the subchain, Section 3.2).
 #include "internal.hpp"
 
 namespace trk {
 
+// A block takes SB samples.  Phase 1: one thread per (sample, mode) draws
+// the index (the optimal law: one thread per sample draws over J_n); the
+// probabilities are multiplied per sample in the order n+1, ..., n-1.
+// Phase 2: the N-1 core slices of every sample are copied to LDS in one
+// batch (a slice G_k(i) is row i of G_k(2): R_k R_{k+1} contiguous values).
+// Phase 3: the chain products M <- M G_k(i_k), one output entry per thread
+// at a time, the last product written straight to S[f][r + R_n s] = M_f(s, r)
+// (consecutive threads, consecutive columns).  Products accumulate in the
+// core dtype with the inner index ascending.
 template <typename TC>
-__global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, int m, CdfPtrs cdf,
-                                                         const uint64_t* __restrict__ cdf_J,
-                                                         int stream_tag, Ptrs cores,
-                                                         int32_t* __restrict__ idx,
-                                                         double* __restrict__ pF,
-                                                         TC* __restrict__ S, int do_sample,
-                                                         int do_subchain) {
+__global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, int m, int SB, CdfPtrs cdf,
+                                                         const uint64_t* __restrict__ cdf_J, int stream_tag,
+                                                         Ptrs cores, int32_t* __restrict__ idx, double* __restrict__ pF,
+                                                         TC* __restrict__ S, int do_sample, int do_subchain) {
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
-    const int N = d.N;
+    const int N = d.N, tid = threadIdx.x;
     const int n1 = ring_next(n, N);
-    const int Rn = d.R[n], Rn1 = d.R[n1];
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t f = gid / Rn1;
-    const int s = (int)(gid - f * Rn1);
-    if (f >= m) return;
+    const int Rn = d.R[n], Rn1 = d.R[n1], RR = Rn * Rn1;
+    const int f0 = blockIdx.x * SB;
+    const int nb = min(SB, m - f0);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int* sidx = reinterpret_cast<int*>(smem_raw);                   // [SB][kMaxOrder]
+    double* sp = reinterpret_cast<double*>(sidx + SB * kMaxOrder);  // [SB][kMaxOrder], order of the chain
+    int* sok = reinterpret_cast<int*>(sp + SB * kMaxOrder);         // [SB]
+    TC* sl = reinterpret_cast<TC*>(sok + ((SB + 3) & ~3));          // slices, then two product buffers
 
-    int ik[kMaxOrder];
+    // chain order n+1, ..., n-1: stage q is mode (n + 1 + q) mod N; its
+    // slice starts at soff[q] within a sample's slices
+    __shared__ int soff[kMaxOrder + 1];
+    if (tid == 0) {
+        int o = 0;
+        for (int q = 0; q < N - 1; ++q) {
+            soff[q] = o;
+            const int k = (n + 1 + q) % N;
+            o += d.R[k] * d.R[ring_next(k, N)];
+        }
+        soff[N - 1] = o;
+    }
+    int mr = 0;   // largest rank: stride of the product buffers
+    for (int k = 0; k < N; ++k) mr = max(mr, d.R[k]);
     if (do_sample) {
-        double p = 1.0;
         if (cdf_J) {
-            const int64_t J = J_of(d, n);
-            const uint64_t r = draw_word(ms.seed, t, (uint64_t)f, (uint64_t)n, (uint64_t)stream_tag);
-            double pj;
-            int64_t j;
-            {   // first j with cdf_J[j] > u over [0, J)
+            for (int fl = tid; fl < nb; fl += blockDim.x) {
+                const int64_t f = f0 + fl;
+                const int64_t J = J_of(d, n);
+                const uint64_t r = draw_word(ms.seed, t, (uint64_t)f, (uint64_t)n, (uint64_t)stream_tag);
                 const uint64_t W = cdf_J[J - 1];
                 const uint64_t u = mulhi64(r, W);
-                int64_t lo = 0, hi = J - 1;
+                int64_t lo = 0, hi = J - 1;   // first j with cdf_J[j] > u
                 while (lo < hi) {
                     const int64_t mid = (lo + hi) >> 1;
                     if (cdf_J[mid] > u) hi = mid; else lo = mid + 1;
                 }
                 const uint64_t prev = lo > 0 ? cdf_J[lo - 1] : 0ull;
-                pj = (double)(cdf_J[lo] - prev) / (double)W;
-                j = lo;
-            }
-            p = pj;
-            int k = n1;
-            for (int q = 1; q < N; ++q) {
-                ik[k] = (int)(j % d.I[k]);
-                j /= d.I[k];
-                k = ring_next(k, N);
+                sp[fl * kMaxOrder] = (double)(cdf_J[lo] - prev) / (double)W;
+                int64_t j = lo;
+                for (int q = 0; q < N - 1; ++q) {
+                    const int k = (n + 1 + q) % N;
+                    sidx[fl * kMaxOrder + k] = (int)(j % d.I[k]);
+                    j /= d.I[k];
+                }
+                sidx[fl * kMaxOrder + n] = -1;
+                sok[fl] = 1;
             }
         } else {
-            int k = n1;
-            for (int q = 1; q < N; ++q) {
-                const uint64_t r = draw_word(ms.seed, t, (uint64_t)f, (uint64_t)k, (uint64_t)stream_tag);
+            for (int w = tid; w < nb * (N - 1); w += blockDim.x) {
+                const int fl = w / (N - 1), q = w - fl * (N - 1);
+                const int k = (n + 1 + q) % N;
+                const uint64_t r = draw_word(ms.seed, t, (uint64_t)(f0 + fl), (uint64_t)k, (uint64_t)stream_tag);
                 double pk;
+                int i;
                 if (cdf.p[k]) {
-                    ik[k] = cdf_pick(cdf.p[k], d.I[k], r, &pk);
+                    i = cdf_pick(cdf.p[k], d.I[k], r, &pk);
                 } else {
-                    ik[k] = (int)mulhi64(r, (uint64_t)d.I[k]);
+                    i = (int)mulhi64(r, (uint64_t)d.I[k]);
                     pk = 1.0 / (double)d.I[k];
                 }
-                p = p * pk;
-                k = ring_next(k, N);
+                sidx[fl * kMaxOrder + k] = i;
+                sp[fl * kMaxOrder + q] = pk;
+                if (q == 0) {
+                    sidx[fl * kMaxOrder + n] = -1;
+                    sok[fl] = 1;
+                }
             }
         }
-        ik[n] = -1;
-        if (s == 0) {
-            for (int k = 0; k < N; ++k) idx[f * N + k] = ik[k];
+        __syncthreads();
+        for (int fl = tid; fl < nb; fl += blockDim.x) {
+            const int64_t f = f0 + fl;
+            double p;
+            if (cdf_J) {
+                p = sp[fl * kMaxOrder];
+            } else {
+                p = 1.0;
+                for (int q = 0; q < N - 1; ++q) p = p * sp[fl * kMaxOrder + q];
+            }
             pF[f] = p;
+            for (int k = 0; k < N; ++k) idx[f * N + k] = sidx[fl * kMaxOrder + k];
         }
     } else {
-        bool ok = true;
-        for (int k = 0; k < N; ++k) {
-            ik[k] = idx[f * N + k];
-            if (k != n && (ik[k] < 0 || ik[k] >= d.I[k])) ok = false;
+        for (int fl = tid; fl < nb; fl += blockDim.x) {
+            const int64_t f = f0 + fl;
+            int ok = 1;
+            for (int k = 0; k < N; ++k) {
+                const int i = idx[f * N + k];
+                sidx[fl * kMaxOrder + k] = i;
+                if (k != n && (i < 0 || i >= d.I[k])) ok = 0;
+            }
+            sok[fl] = ok;   // invalid caller index: the row is NaN, nothing is read
         }
-        if (!ok) {   // invalid caller index: the row is NaN, nothing is read
-            TC* out = S + f * (int64_t)(Rn * Rn1) + (int64_t)Rn * s;
-            for (int r = 0; r < Rn; ++r) out[r] = TC(NAN);
-            return;
-        }
+        __syncthreads();
     }
     if (!do_subchain) return;
 
-    // Row s of M_f through the chain n+1, ..., n-1.
-    TC v[kMaxRank];
-    int k = n1;
-    {
-        const TC* A = static_cast<const TC*>(cores.p[k]) + (int64_t)ik[k] * d.R[k] * d.R[ring_next(k, N)];
-        const int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
+    // Phase 2: slices of every sample, all loads in flight together.
+    const int per = soff[N - 1];   // slice values per sample
+    const int tot = nb * per;
+    constexpr int LB = 16;
+    for (int e0 = 0; e0 < tot; e0 += 256 * LB) {
+        TC v[LB];
 #pragma unroll
-        for (int c = 0; c < kMaxRank; ++c) v[c] = c < Rk1 ? A[s + Rk * c] : TC(0);
-    }
-    for (int q = 2; q < N; ++q) {
-        k = ring_next(k, N);
-        const int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
-        const TC* A = static_cast<const TC*>(cores.p[k]) + (int64_t)ik[k] * Rk * Rk1;
-        TC w[kMaxRank];
-#pragma unroll
-        for (int c = 0; c < kMaxRank; ++c) {
-            TC acc = TC(0);
-            if (c < Rk1) {
-#pragma unroll
-                for (int r = 0; r < kMaxRank; ++r)
-                    if (r < Rk) acc += v[r] * A[r + Rk * c];
+        for (int u = 0; u < LB; ++u) {
+            const int e = e0 + u * 256 + tid;
+            v[u] = TC(0);
+            if (e < tot) {
+                const int fl = e / per, w = e - fl * per;
+                int q = 0;
+                while (q + 1 < N - 1 && w >= soff[q + 1]) ++q;
+                const int k = (n + 1 + q) % N;
+                const int i = sidx[fl * kMaxOrder + k];
+                if (sok[fl])
+                    v[u] = static_cast<const TC*>(cores.p[k])[(int64_t)i * (soff[q + 1] - soff[q]) + (w - soff[q])];
             }
-            w[c] = acc;
         }
 #pragma unroll
-        for (int c = 0; c < kMaxRank; ++c) v[c] = w[c];
+        for (int u = 0; u < LB; ++u) {
+            const int e = e0 + u * 256 + tid;
+            if (e < tot) sl[e] = v[u];
+        }
     }
-    TC* out = S + f * (int64_t)(Rn * Rn1) + (int64_t)Rn * s;
-#pragma unroll
-    for (int r = 0; r < kMaxRank; ++r)
-        if (r < Rn) out[r] = v[r];
+    __syncthreads();
+
+    // Phase 3: M (R_{n+1} x R_{k+1}, row-major per sample, stride mr^2)
+    // through the chain; slice q of sample fl holds (r, c) at
+    // sl[fl * per + soff[q] + r + R_k c].  The last product goes to S.
+    const size_t P2 = (size_t)mr * mr;
+    TC* bufA = sl + (size_t)SB * per;
+    TC* bufB = bufA + (size_t)SB * P2;
+    if (N == 2) {
+        for (int e = tid; e < nb * RR; e += blockDim.x) {
+            const int fl = e / RR, w = e - fl * RR;
+            const int s = w / Rn, r = w - s * Rn;
+            S[(int64_t)(f0 + fl) * RR + w] = sok[fl] ? sl[(size_t)fl * per + s + Rn1 * r] : TC(NAN);
+        }
+        return;
+    }
+    const TC* Mc = nullptr;     // current product; null: the first slice
+    int cols = d.R[ring_next(n1, N)];
+    for (int q = 1; q < N - 1; ++q) {
+        const int k = (n + 1 + q) % N, Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
+        const bool last = q == N - 2;   // then Rk1 == R_n
+        TC* Mo = (q & 1) ? bufA : bufB;
+        for (int e = tid; e < nb * Rn1 * Rk1; e += blockDim.x) {
+            const int fl = e / (Rn1 * Rk1), w = e - fl * (Rn1 * Rk1);
+            const int s = w / Rk1, c = w - s * Rk1;
+            const TC* A = sl + (size_t)fl * per + soff[q];
+            TC acc = TC(0);
+            for (int r = 0; r < Rk; ++r) {
+                const TC mv = Mc ? Mc[(size_t)fl * P2 + s * cols + r] : sl[(size_t)fl * per + s + Rn1 * r];
+                acc += mv * A[r + Rk * c];
+            }
+            if (last)
+                S[(int64_t)(f0 + fl) * RR + w] = sok[fl] ? acc : TC(NAN);
+            else
+                Mo[(size_t)fl * P2 + s * Rk1 + c] = acc;
+        }
+        if (!last) __syncthreads();
+        Mc = Mo;
+        cols = Rk1;
+    }
+}
+
+// Samples per block: the slices of all of them and two product buffers fit
+// in 48 KiB of LDS.
+static int sample_block(const tr_desc& d, const Shape& sh, size_t es, size_t* lds) {
+    const size_t per = (size_t)(d.N - 1) * sh.maxR * sh.maxR;
+    const size_t prod = d.N > 3 ? 2 * (size_t)sh.maxR * sh.maxR : 0;   // product buffers
+    const size_t need = (per + prod) * es + kMaxOrder * 12 + 4;
+    int SB = (int)((48 * 1024) / need);
+    SB = SB < 1 ? 1 : (SB > 16 ? 16 : SB);
+    *lds = (size_t)SB * kMaxOrder * 12 + (size_t)((SB + 3) & ~3) * 4 + 16 +
+           ((size_t)SB * per + (size_t)SB * prod) * es;
+    return SB;
 }
 
 hipError_t launch_sample_subchain(const tr_desc& d, ModeSrc ms, int m, CdfPtrs cdf,
@@ -131,14 +209,16 @@ hipError_t launch_sample_subchain(const tr_desc& d, ModeSrc ms, int m, CdfPtrs c
                                   bool do_subchain, hipStream_t st) {
     if (m <= 0) return hipSuccess;
     const Shape sh = shape_of(d);
-    const int64_t threads = (int64_t)m * sh.maxR;
-    const dim3 grid((unsigned)((threads + 255) / 256));
+    const size_t es = d.core_dtype == TR_F64 ? 8 : 4;
+    size_t lds = 0;
+    const int SB = sample_block(d, sh, es, &lds);
+    const dim3 grid((unsigned)((m + SB - 1) / SB));
     if (d.core_dtype == TR_F64)
-        hipLaunchKernelGGL(k_sample_subchain<double>, grid, dim3(256), 0, st, d, ms, m, cdf, cdf_J,
+        hipLaunchKernelGGL(k_sample_subchain<double>, grid, dim3(256), lds, st, d, ms, m, SB, cdf, cdf_J,
                            stream_tag, cores, idx, pF, static_cast<double*>(S), (int)do_sample,
                            (int)do_subchain);
     else
-        hipLaunchKernelGGL(k_sample_subchain<float>, grid, dim3(256), 0, st, d, ms, m, cdf, cdf_J,
+        hipLaunchKernelGGL(k_sample_subchain<float>, grid, dim3(256), lds, st, d, ms, m, SB, cdf, cdf_J,
                            stream_tag, cores, idx, pF, static_cast<float*>(S), (int)do_sample,
                            (int)do_subchain);
     return hipGetLastError();
