@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the Gram/inverse branch on the main stream too")
     return ap.parse_args()
 
 
@@ -125,6 +127,7 @@ def main():
                           "(multi-GPU sharding is a design note, not implemented)"}))
         sys.exit(2)
     import torch
+    from paper_2303_16492_amd import _lib as L
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
 
@@ -134,7 +137,8 @@ def main():
     desc, X, true3, init3 = build_problem(args.seed, I, R, kappa, dev)
     cores = cores_to_device(init3, torch.float32, dev)
     solver = TRSolver(cores, X, [I] * N, [R] * N, m, law="U", scaled=True, prec=args.prec,
-                      rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed)
+                      rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
+                      overlap=not args.no_overlap)
     print(f"[bench] workload ready: {I}^3 rank {R}, m={m}, prec={args.prec}", file=sys.stderr, flush=True)
     solver.run(args.warmup)
     torch.cuda.synchronize()
@@ -144,12 +148,18 @@ def main():
     hip, evs = hip_events(2 * K + 2)
     begin = (C.c_void_p * K)(*[e.value for e in evs[2:2 + K]])
     end = (C.c_void_p * K)(*[e.value for e in evs[2 + K:2 + 2 * K]])
+    opts = L.tr_run_opts()
+    if solver.opts is not None:
+        so = solver.opts
+        opts.aux, opts.ev_fork, opts.ev_gram, opts.ev_join = so.aux, so.ev_fork, so.ev_gram, so.ev_join
+    opts.ev_begin = C.cast(begin, C.POINTER(C.c_void_p))
+    opts.ev_end = C.cast(end, C.POINTER(C.c_void_p))
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
     assert hip.hipEventRecord(evs[0], C.c_void_p(stream.cuda_stream)) == 0
-    rc = api.lib().tr_run_events(C.byref(solver.problem), C.byref(solver.config), C.c_void_p(solver.t_dev.data_ptr()),
-                                 K, None, C.c_void_p(solver.status.data_ptr()), C.c_void_p(solver.ws.data_ptr()),
-                                 solver.ws.numel(), C.cast(begin, C.POINTER(C.c_void_p)),
-                                 C.cast(end, C.POINTER(C.c_void_p)), C.c_void_p(stream.cuda_stream))
+    rc = api.lib().tr_run_ex(C.byref(solver.problem), C.byref(solver.config), C.c_void_p(solver.t_dev.data_ptr()),
+                             K, None, C.c_void_p(solver.status.data_ptr()), C.c_void_p(solver.ws.data_ptr()),
+                             solver.ws.numel(), C.c_void_p(stream.cuda_stream), C.byref(opts))
     assert rc == 0, rc
     assert hip.hipEventRecord(evs[1], C.c_void_p(stream.cuda_stream)) == 0
     torch.cuda.synchronize()
@@ -194,7 +204,8 @@ def main():
         "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": "scaled-illcond-n3-i400-r10", "N": N, "I": I, "R": R, "kappa": kappa,
-                   "m": m, "m_H": m, "law": "uniform", "alpha": args.alpha, "prec": args.prec},
+                   "m": m, "m_H": m, "law": "uniform", "alpha": args.alpha, "prec": args.prec,
+                   "overlap": not args.no_overlap},
         "roofline": roof,
         "cpu_baseline": cpu,
         "rse_after": rse,

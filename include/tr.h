@@ -289,6 +289,35 @@ tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev
                         double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
                         void* const* ev_begin, void* const* ev_end, tr_stream_t stream);
 
+/* Options of tr_run_ex (all fields may be NULL).
+ *   aux, ev_fork, ev_gram, ev_join: a second stream and three hipEvent_t
+ *     handles, created by the caller (default stream priority).  With them
+ *     a scaled step (RR <= 128) runs the Gram, its reduction and the
+ *     inverse (equation eq:scaledsg_direction) on ``aux`` and the gradient
+ *     on ``stream``: ev_fork is recorded on ``stream`` after the draws and
+ *     waited on by ``aux``; ev_gram is recorded on ``aux`` once the Gram's
+ *     per-group sums are written and waited on by ``stream`` before the
+ *     gradient (so the gradient runs beside the reduction and the one-
+ *     workgroup inverse instead of competing with the Gram); ev_join is
+ *     recorded on ``aux`` after the inverse and waited on by ``stream``
+ *     before the update.  Work of one step never overlaps the next; the
+ *     fork/join is graph-capturable; results are bitwise those of the
+ *     one-stream run.  All four must be set together, or all NULL.
+ *   ev_begin, ev_end: as in tr_run_events. */
+typedef struct {
+    tr_stream_t aux;
+    void* ev_fork;
+    void* ev_gram;
+    void* ev_join;
+    void* const* ev_begin;
+    void* const* ev_end;
+} tr_run_opts;
+
+/* tr_run with options; opts NULL is tr_run.  Same workspace. */
+tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps,
+                    double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                    tr_stream_t stream, const tr_run_opts* opts);
+
 /* ------------------------------------------------------------------ */
 /* a10: sampled-entry loss, forward and backward for every core        */
 /* ------------------------------------------------------------------ */

@@ -74,6 +74,18 @@ class tr_config(C.Structure):
 
 VP = C.c_void_p
 PVP = C.POINTER(C.c_void_p)
+
+
+class tr_run_opts(C.Structure):
+    _fields_ = [
+        ("aux", C.c_void_p),
+        ("ev_fork", C.c_void_p),
+        ("ev_gram", C.c_void_p),
+        ("ev_join", C.c_void_p),
+        ("ev_begin", PVP),
+        ("ev_end", PVP),
+    ]
+
 I32, U64, F64, SZ = C.c_int32, C.c_uint64, C.c_double, C.c_size_t
 PDESC = C.POINTER(tr_desc)
 
@@ -100,6 +112,8 @@ _SIGS = {
     "tr_run": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP, SZ, VP]),
     "tr_run_events": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP, SZ, PVP, PVP,
                             VP]),
+    "tr_run_ex": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP, SZ, VP,
+                        C.POINTER(tr_run_opts)]),
     "tr_run_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_config)]),
     "tr_entry_fwd": (I32, [PDESC, PVP, VP, VP, I32, VP, VP, VP, SZ, VP]),
     "tr_entry_bwd": (I32, [PDESC, PVP, VP, VP, I32, F64, VP, PVP, VP, SZ, VP]),
@@ -136,3 +150,43 @@ class TRError(RuntimeError):
 def check(fn: str, status: int) -> None:
     if status != TR_OK:
         raise TRError(fn, status)
+
+
+_hip = None
+
+
+def hip():
+    """The HIP runtime this process already uses (torch's), for events."""
+    global _hip
+    if _hip is None:
+        import torch
+        h = C.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+        h.hipEventCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+        h.hipEventCreateWithFlags.restype = C.c_int
+        h.hipEventDestroy.argtypes = [C.c_void_p]
+        h.hipEventDestroy.restype = C.c_int
+        h.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+        h.hipEventRecord.restype = C.c_int
+        h.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        h.hipEventElapsedTime.restype = C.c_int
+        _hip = h
+    return _hip
+
+
+HIP_EVENT_DISABLE_TIMING = 0x2
+
+
+class HipEvent:
+    """A raw hipEvent_t owned by Python (destroyed with the object)."""
+
+    def __init__(self, timing: bool = True):
+        e = C.c_void_p()
+        rc = hip().hipEventCreateWithFlags(C.byref(e), 0 if timing else HIP_EVENT_DISABLE_TIMING)
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed: {rc}")
+        self.handle = e
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _hip is not None:
+            _hip.hipEventDestroy(h)

@@ -204,6 +204,13 @@ def tr_run(problem: L.tr_problem, config: L.tr_config, t_dev, steps, loss_out, s
                                  _p(status), _p(ws), ws.numel(), _stream()))
 
 
+def tr_run_ex(problem: L.tr_problem, config: L.tr_config, t_dev, steps, loss_out, status, ws, opts=None):
+    """tr_run with options (an L.tr_run_opts or None)."""
+    check("tr_run_ex", lib().tr_run_ex(C.byref(problem), C.byref(config), _p(t_dev), steps, _p(loss_out),
+                                       _p(status), _p(ws), ws.numel(), _stream(),
+                                       C.byref(opts) if opts is not None else None))
+
+
 def tr_run_workspace_size(problem, config) -> int:
     return lib().tr_run_workspace_size(C.byref(problem), C.byref(config))
 

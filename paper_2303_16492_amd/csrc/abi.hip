@@ -362,13 +362,26 @@ size_t tr_run_workspace_size(const tr_problem* p, const tr_config* c) {
 
 tr_status tr_run(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps, double* loss_out,
                  int32_t* dev_status, void* ws, size_t ws_bytes, tr_stream_t stream) {
-    return tr_run_events(p, c, t_dev, steps, loss_out, dev_status, ws, ws_bytes, nullptr, nullptr, stream);
+    return tr_run_ex(p, c, t_dev, steps, loss_out, dev_status, ws, ws_bytes, stream, nullptr);
 }
 
 tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps, double* loss_out,
                         int32_t* dev_status, void* ws, size_t ws_bytes, void* const* ev_begin, void* const* ev_end,
                         tr_stream_t stream) {
+    tr_run_opts o{};
+    o.ev_begin = ev_begin;
+    o.ev_end = ev_end;
+    return tr_run_ex(p, c, t_dev, steps, loss_out, dev_status, ws, ws_bytes, stream, &o);
+}
+
+tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps, double* loss_out,
+                    int32_t* dev_status, void* ws, size_t ws_bytes, tr_stream_t stream, const tr_run_opts* opts) {
+    const tr_run_opts o = opts ? *opts : tr_run_opts{};
+    void* const* ev_begin = o.ev_begin;
+    void* const* ev_end = o.ev_end;
     if (!p || !c || !t_dev) return TR_E_ARG;
+    const bool any_aux = o.aux || o.ev_fork || o.ev_gram || o.ev_join;
+    if (any_aux && !(o.aux && o.ev_fork && o.ev_gram && o.ev_join)) return TR_E_ARG;
     const tr_desc& d = p->desc;
     tr_status s = validate_desc(&d);
     if (s != TR_OK) return s;
@@ -435,45 +448,78 @@ tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev
         if (e == hipSuccess)
             e = launch_sample_subchain(d, ms, c->m, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr, TR_STREAM_IDX,
                                        cores, idx, pF, S, true, true, st);
-        if (e == hipSuccess && ev_begin && ev_begin[it]) e = hipEventRecord((hipEvent_t)ev_begin[it], st);
-        if (e == hipSuccess) e = launch_grad_partial(d, ms, cores, xs, idx, S, pF, c->m, c->prec, w + L.grad, L.gl, st);
-        if (e == hipSuccess && ev_end && ev_end[it]) e = hipEventRecord((hipEvent_t)ev_end[it], st);
-        if (e != hipSuccess) break;
-        if (c->scaled) {
-            // RR <= 128: the sweep's apply kernel adds the gradient partials
-            // and the loss itself
-            const bool sweep = sweep_supported(d);
-            if (!sweep)
-                e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, loss, false, MutPtrs{}, MutPtrs{}, c->rule,
-                                       dev_status, st);
+        // Scaled steps (RR <= 128) with a second stream: the Gram, its
+        // reduction and the inverse need only the draws, so they run on
+        // ``hs``; the gradient waits for the Gram's group sums (it is not
+        // on the critical path) and then runs beside the reduction and the
+        // inverse, and the gradient partials are added on ``st`` too.
+        const bool fork = any_aux && c->scaled && sweep_supported(d);
+        hipStream_t hs = fork ? (hipStream_t)o.aux : st;
+        if (c->scaled && sweep_supported(d)) {
+            const Shape sh = shape_of(d);
+            if (e == hipSuccess && fork) {
+                e = hipEventRecord((hipEvent_t)o.ev_fork, st);
+                if (e == hipSuccess) e = hipStreamWaitEvent(hs, (hipEvent_t)o.ev_fork, 0);
+            }
             if (e == hipSuccess) {
                 if (c->m_H > 0) {
                     int32_t* idxH = reinterpret_cast<int32_t*>(w + L.idxH);
                     double* pH = reinterpret_cast<double*>(w + L.pH);
                     void* SH = w + L.SH;
                     e = launch_sample_subchain(d, ms, c->m_H, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr,
-                                               TR_STREAM_H, cores, idxH, pH, SH, true, true, st);
-                    if (e == hipSuccess) e = launch_gram(d, ms, SH, pH, c->m_H, gram, w + L.gramws, L.mlH, st);
+                                               TR_STREAM_H, cores, idxH, pH, SH, true, true, hs);
+                    if (e == hipSuccess)
+                        e = launch_gram(d, ms, SH, pH, c->m_H, gram, w + L.gramws, L.mlH, hs,
+                                        fork ? (hipEvent_t)o.ev_gram : nullptr);
                 } else {
-                    e = launch_gram(d, ms, S, pF, c->m, gram, w + L.gramws, L.ml, st);
+                    e = launch_gram(d, ms, S, pF, c->m, gram, w + L.gramws, L.ml, hs,
+                                    fork ? (hipEvent_t)o.ev_gram : nullptr);
                 }
             }
-            if (e == hipSuccess && sweep) {
-                const Shape sh = shape_of(d);
-                const char* gw = w + L.grad;
-                e = launch_sweep_update(d, ms, gram, c->damping, gw + L.gl.gpart_off, L.gl.groups,
-                                        (int64_t)sh.maxI * sh.maxRR,
-                                        LossParts{reinterpret_cast<const double*>(gw + L.gl.lpart_off), L.gl.groups,
-                                                  L.gl.row_tiles, L.gl.ti},
-                                        loss, mcores, acc, c->rule, dev_status, w + L.upd, L.ul, fused, st);
-            } else if (e == hipSuccess) {
-                e = launch_scaled_update(d, ms, gram, c->damping, g, mcores, acc, c->rule, dev_status, w + L.upd, L.ul,
-                                         st);
-                if (e == hipSuccess && fused.t) e = launch_bump(t_dev, st);
-            }
+            if (e == hipSuccess) e = launch_sweep_inverse(d, ms, gram, c->damping, L.ul, w + L.upd, dev_status, hs);
+            if (e == hipSuccess && fork) e = hipEventRecord((hipEvent_t)o.ev_join, hs);
+            if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, (hipEvent_t)o.ev_gram, 0);
+            if (e == hipSuccess && ev_begin && ev_begin[it]) e = hipEventRecord((hipEvent_t)ev_begin[it], st);
+            if (e == hipSuccess)
+                e = launch_grad_partial(d, ms, cores, xs, idx, S, pF, c->m, c->prec, w + L.grad, L.gl, st);
+            if (e == hipSuccess && ev_end && ev_end[it]) e = hipEventRecord((hipEvent_t)ev_end[it], st);
+            if (e == hipSuccess)
+                e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, loss, false, MutPtrs{}, MutPtrs{}, c->rule,
+                                       dev_status, st);
+            if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, (hipEvent_t)o.ev_join, 0);
+            if (e == hipSuccess)
+                e = launch_sweep_apply(d, ms, g, 1, 0, LossParts{}, nullptr, mcores, acc, c->rule, dev_status,
+                                       w + L.upd, L.ul, fused, st);
         } else {
-            e = launch_grad_reduce(d, ms, w + L.grad, L.gl, nullptr, loss, true, mcores, acc, c->rule, dev_status, st,
-                                   fused);
+            if (e == hipSuccess && ev_begin && ev_begin[it]) e = hipEventRecord((hipEvent_t)ev_begin[it], st);
+            if (e == hipSuccess)
+                e = launch_grad_partial(d, ms, cores, xs, idx, S, pF, c->m, c->prec, w + L.grad, L.gl, st);
+            if (e == hipSuccess && ev_end && ev_end[it]) e = hipEventRecord((hipEvent_t)ev_end[it], st);
+            if (e != hipSuccess) break;
+            if (c->scaled) {   // RR > 128: Cholesky path
+                e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, loss, false, MutPtrs{}, MutPtrs{}, c->rule,
+                                       dev_status, st);
+                if (e == hipSuccess) {
+                    if (c->m_H > 0) {
+                        int32_t* idxH = reinterpret_cast<int32_t*>(w + L.idxH);
+                        double* pH = reinterpret_cast<double*>(w + L.pH);
+                        void* SH = w + L.SH;
+                        e = launch_sample_subchain(d, ms, c->m_H, cdf,
+                                                   c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr, TR_STREAM_H, cores,
+                                                   idxH, pH, SH, true, true, st);
+                        if (e == hipSuccess) e = launch_gram(d, ms, SH, pH, c->m_H, gram, w + L.gramws, L.mlH, st);
+                    } else {
+                        e = launch_gram(d, ms, S, pF, c->m, gram, w + L.gramws, L.ml, st);
+                    }
+                }
+                if (e == hipSuccess)
+                    e = launch_scaled_update(d, ms, gram, c->damping, g, mcores, acc, c->rule, dev_status, w + L.upd,
+                                             L.ul, st);
+                if (e == hipSuccess && fused.t) e = launch_bump(t_dev, st);
+            } else {
+                e = launch_grad_reduce(d, ms, w + L.grad, L.gl, nullptr, loss, true, mcores, acc, c->rule,
+                                       dev_status, st, fused);
+            }
         }
         if (e == hipSuccess && refresh) {
             e = launch_dist(d, ms, true, 0, c->law, cores, p->cdf, dev_status, w + L.dist, st);

@@ -415,7 +415,7 @@ GramWs gram_ws_layout(const tr_desc& d, int m) {
 }
 
 hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double* pF, int m, double* gram,
-                       void* ws, const GramWs& L, hipStream_t st) {
+                       void* ws, const GramWs& L, hipStream_t st, hipEvent_t mid) {
     const Shape sh = shape_of(d);
     const int maxRR2 = sh.maxRR * sh.maxRR;
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + L.part_off);
@@ -428,6 +428,7 @@ hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double
                            static_cast<const float*>(S), pF, m, L.groups, L.tiles, part, maxRR2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (mid && (e = hipEventRecord(mid, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_gram_reduce, dim3((maxRR2 + 255) / 256), dim3(256), 0, st, d, ms, part, L.groups,
                        maxRR2, gram);
     return hipGetLastError();

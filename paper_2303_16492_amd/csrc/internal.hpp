@@ -96,8 +96,10 @@ struct GramWs {
     int groups, tiles;
 };
 GramWs gram_ws_layout(const tr_desc& d, int m);
+// ``mid`` (optional) is recorded between the per-group sums and their
+// reduction.
 hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double* pF, int m,
-                       double* gram, void* ws, const GramWs& L, hipStream_t st);
+                       double* gram, void* ws, const GramWs& L, hipStream_t st, hipEvent_t mid = nullptr);
 
 // a7/a8: Cholesky of gram + damping (with fallback) then solve and update.
 struct UpdWs {
@@ -115,6 +117,13 @@ hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram,
                                int groups, int64_t gstride, LossParts lp, double* loss, MutPtrs cores,
                                MutPtrs accum, tr_step rule, int32_t* status, void* ws, const UpdWs& L,
                                StepBump step, hipStream_t st);
+// The two halves: -(gram + damping I)^{-1} (one workgroup) and the
+// row-parallel p = g (-M^{-1}) with the rule.
+hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const UpdWs& L,
+                                void* ws, int32_t* status, hipStream_t st);
+hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* gsrc, int groups, int64_t gstride,
+                              LossParts lp, double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
+                              void* ws, const UpdWs& L, StepBump step, hipStream_t st);
 hipError_t launch_plain_update(const tr_desc& d, ModeSrc ms, const void* g, MutPtrs cores,
                                MutPtrs accum, tr_step rule, int32_t* status, hipStream_t st);
 

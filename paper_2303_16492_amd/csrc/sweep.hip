@@ -429,10 +429,8 @@ __global__ __launch_bounds__(256) void k_scaled_apply(tr_desc d, ModeSrc ms, con
 
 bool sweep_supported(const tr_desc& d) { return shape_of(d).maxRR <= 128; }
 
-hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* gsrc,
-                               int groups, int64_t gstride, LossParts lp, double* loss,
-                               MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status, void* ws,
-                               const UpdWs& L, StepBump step, hipStream_t st) {
+hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const UpdWs& L,
+                                void* ws, int32_t* status, hipStream_t st) {
     const Shape sh = shape_of(d);
     if (sh.maxRR > 128) return hipErrorInvalidValue;
     char* w = static_cast<char*>(ws);
@@ -452,8 +450,17 @@ hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram,
         default: TRK_SWEEP(8); break;
     }
 #undef TRK_SWEEP
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* gsrc, int groups, int64_t gstride,
+                              LossParts lp, double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
+                              void* ws, const UpdWs& L, StepBump step, hipStream_t st) {
+    const Shape sh = shape_of(d);
+    if (sh.maxRR > 128) return hipErrorInvalidValue;
+    char* w = static_cast<char*>(ws);
+    const double* hm = reinterpret_cast<const double*>(w + L.L_off);
+    const int* flag = reinterpret_cast<const int*>(w + L.flag_off);
     const size_t shm = ((size_t)sh.maxRR * sh.maxRR + (size_t)kApplyRows * sh.maxRR) * 8;
     const dim3 grid((sh.maxI + kApplyRows - 1) / kApplyRows);
     if (d.core_dtype == TR_F64) {
@@ -466,6 +473,15 @@ hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram,
                            groups, gstride, lp, loss, hm, flag, cores, accum, rule, status, step);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* gsrc,
+                               int groups, int64_t gstride, LossParts lp, double* loss, MutPtrs cores, MutPtrs accum,
+                               tr_step rule, int32_t* status, void* ws, const UpdWs& L, StepBump step,
+                               hipStream_t st) {
+    hipError_t e = launch_sweep_inverse(d, ms, gram, damping, L, ws, status, st);
+    if (e != hipSuccess) return e;
+    return launch_sweep_apply(d, ms, gsrc, groups, gstride, lp, loss, cores, accum, rule, status, ws, L, step, st);
 }
 
 }  // namespace trk

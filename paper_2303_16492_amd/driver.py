@@ -43,7 +43,7 @@ def cores_to_host(cores2, R):
 
 class TRSolver:
     def __init__(self, cores, X, I, R, m, law="U", scaled=False, prec="f32", rule=None,
-                 damping=0.0, m_H=0, seed=0, replicas=True):
+                 damping=0.0, m_H=0, seed=0, replicas=True, overlap=True):
         self.I, self.R = list(I), list(R)
         self.N = len(I)
         self.cores = cores
@@ -79,9 +79,18 @@ class TRSolver:
         self.config = c
         self.ws = api.workspace(api.tr_run_workspace_size(p, c), dev)
         self.rse_ws = None
+        # scaled steps: the Gram/inverse branch on a second stream (RR <= 128)
+        self.opts = None
+        if overlap and scaled:
+            self.aux = torch.cuda.Stream(device=dev)
+            self.events = [L.HipEvent(timing=False) for _ in range(3)]
+            o = L.tr_run_opts()
+            o.aux = self.aux.cuda_stream
+            o.ev_fork, o.ev_gram, o.ev_join = (e.handle.value for e in self.events)
+            self.opts = o
 
     def run(self, steps: int, loss_out=None):
-        api.tr_run(self.problem, self.config, self.t_dev, steps, loss_out, self.status, self.ws)
+        api.tr_run_ex(self.problem, self.config, self.t_dev, steps, loss_out, self.status, self.ws, self.opts)
 
     def capture(self, steps: int):
         """HIP graph of ``steps`` iterations (replay with graph.replay())."""

@@ -196,3 +196,26 @@ def test_mixed_scaled_run_tracks_oracle(prec):
     torch.cuda.synchronize()
     for k in range(3):
         assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 5e-3
+
+
+@pytest.mark.parametrize("m_H", [0, 150])
+def test_overlapped_branch_equals_serial_bitwise(m_H):
+    """The Gram/inverse branch on a second stream changes no arithmetic: the
+    same cores, step counter and loss as the one-stream run."""
+    dtype = torch.float32
+    X, _, init = planted(3, [30, 25, 28], [3, 4, 3], dtype, noise_db=40.0)
+    dX = to_dev(flat_paper(X), dtype)
+    outs = []
+    for overlap in (False, True):
+        s = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [30, 25, 28], [3, 4, 3], 200, scaled=True,
+                     prec="f32", rule=api.step_rule("fixed", alpha=0.5), m_H=m_H, overlap=overlap)
+        losses = torch.zeros(12, dtype=torch.float64, device=DEV)
+        s.run(12, loss_out=losses)
+        torch.cuda.synchronize()
+        say("overlap", overlap, "t", s.t)
+        outs.append(([c.clone() for c in s.cores], s.t, losses.clone()))
+    (ca, ta, la), (cb, tb, lb) = outs
+    assert ta == tb == 12
+    assert torch.equal(la, lb)
+    for a, b in zip(ca, cb):
+        assert torch.equal(a, b)
