@@ -3,14 +3,15 @@
 Workload (default): the ill-conditioned planted ring of the second synthetic
 experiment at 400 x 400 x 400 (64M FP32 entries), ranks 10, each core's
 mode-2 unfolding with singular values geometric from 1 to 1e-4, mini-batch
-|F_n| = 4096 with H_n = F_n, uniform fibers, FP64 Cholesky of the 100 x 100
-Gram.  One step = mode pick, draws, sampled subchain, fiber gather,
-gradient, Gram, Cholesky solve and update (every row of the hot path).
+|F_n| = 4096 with H_n = F_n, uniform fibers, FP64 Gram and inverse.  One
+step = mode pick, draws, sampled subchain, fiber gather, gradient, Gram,
+inverse and update (every row of the single-problem hot path).
 
-Prints one JSON line: steps/s (whole job), the dominant kernel's roofline
-(fused fiber-gather/gradient contraction, timed with HIP events around each
-launch inside the timed region), the CPU oracle timed on a bounded sample,
-and the RSE reached.
+Prints one JSON line: steps/s of the --prec form (whole job), the same for
+the other form (FP32 vs BF16 mixed), the dominant kernel's roofline (HIP
+events around each launch inside the timed region), time to RSE 1e-4 for
+both forms (capped), the 64-problem batched workload (problem-steps/s with
+the tuner's tile choice), and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -43,6 +44,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the Gram/inverse branch on the main stream too")
+    ap.add_argument("--ttt-steps", type=int, default=3000,
+                    help="step cap of each time-to-target run (0: skip them)")
+    ap.add_argument("--batch-steps", type=int, default=50,
+                    help="timed steps of the 64-problem batched workload (0: skip it)")
     return ap.parse_args()
 
 
@@ -52,6 +57,7 @@ def hip_events(n):
     hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
     hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
     hip.hipEventDestroy.argtypes = [C.c_void_p]
+    hip.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
     evs = []
     for _ in range(n):
         e = C.c_void_p()
@@ -92,6 +98,36 @@ def build_problem(seed, I, R, kappa, dev):
     return desc, X, true3, init3
 
 
+def build_batch(seed, dev):
+    """The 64 independent planted problems (orders 3-5, sizes 16-128, ranks
+    3-12, 40 dB noise, FP16 tensors, m = 1024, AdaGrad) as a TRBatch."""
+    import torch
+    import tr_inputs as ti
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRBatch, cores_to_device
+    insts = ti.batched_instances(seed)
+    probs = []
+    gen = torch.Generator(device=dev)
+    for b in insts:
+        d32 = api.make_desc(b.I, b.R, torch.float32, torch.float32)
+        d16 = api.make_desc(b.I, b.R, torch.float32, torch.float16)
+        true = cores_to_device(ti.gaussian_cores(b.seed, b.N, b.I, b.R), torch.float32, dev)
+        X = api.tr_reconstruct(d32, true)
+        gen.manual_seed(b.seed + 5)
+        sigma = 10.0 ** (-40.0 / 20.0) * float(X.double().norm()) / (X.numel() ** 0.5)
+        X.add_(torch.randn(X.numel(), generator=gen, device=dev, dtype=torch.float32), alpha=sigma)
+        X16 = X.half()
+        del X
+        ms2 = float(X16.float().pow(2).mean())
+        sig = (ms2 / float(np.prod(b.R))) ** (1.0 / (2 * b.N))
+        cores = cores_to_device(ti.gaussian_cores(b.seed + 1, b.N, b.I, b.R, scale=sig), torch.float32, dev)
+        reps = [api.tr_x_replicate(d16, X16, n) for n in range(b.N)]
+        del X16
+        probs.append(dict(cores=cores, Xrep=reps, I=b.I, R=b.R, m=1024,
+                          rule=api.step_rule("adagrad", eta=0.05), seed=b.seed))
+    return TRBatch(probs, dev), insts
+
+
 def cpu_baseline(seconds, seed, I, R, kappa, m, alpha):
     """The oracle as it stands, on the same workload, for a bounded number
     of steps; returns (steps/s, steps, threads)."""
@@ -120,40 +156,30 @@ def cpu_baseline(seconds, seed, I, R, kappa, m, alpha):
     return k / dt, k, threads
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is a design note, not implemented)"}))
-        sys.exit(2)
+def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup):
+    """K timed steps of the scaled method in precision ``prec`` from the
+    initial cores; per-launch HIP events around the gradient and the
+    inverse kernels."""
     import torch
     from paper_2303_16492_amd import _lib as L
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
-
-    dev = "cuda:0"
-    I, R, kappa, m = 400, 10, 1e4, 4096
     N = 3
-    desc, X, true3, init3 = build_problem(args.seed, I, R, kappa, dev)
     cores = cores_to_device(init3, torch.float32, dev)
-    solver = TRSolver(cores, X, [I] * N, [R] * N, m, law="U", scaled=True, prec=args.prec,
+    solver = TRSolver(cores, X, [I] * N, [R] * N, m, law="U", scaled=True, prec=prec,
                       rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
                       overlap=not args.no_overlap)
-    print(f"[bench] workload ready: {I}^3 rank {R}, m={m}, prec={args.prec}", file=sys.stderr, flush=True)
-    solver.run(args.warmup)
+    solver.run(warmup)
     torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
-
-    K = args.steps
-    hip, evs = hip_events(2 * K + 2)
-    begin = (C.c_void_p * K)(*[e.value for e in evs[2:2 + K]])
-    end = (C.c_void_p * K)(*[e.value for e in evs[2 + K:2 + 2 * K]])
+    hip, evs = hip_events(4 * K + 2)
+    arr = lambda j: (C.c_void_p * K)(*[e.value for e in evs[2 + j * K:2 + (j + 1) * K]])
+    gb, ge, ib, ie = arr(0), arr(1), arr(2), arr(3)
     opts = L.tr_run_opts()
     if solver.opts is not None:
         so = solver.opts
         opts.aux, opts.ev_fork, opts.ev_gram, opts.ev_join = so.aux, so.ev_fork, so.ev_gram, so.ev_join
-    opts.ev_begin = C.cast(begin, C.POINTER(C.c_void_p))
-    opts.ev_end = C.cast(end, C.POINTER(C.c_void_p))
+    P = lambda a: C.cast(a, C.POINTER(C.c_void_p))
+    opts.ev_begin, opts.ev_end, opts.ev_inv_begin, opts.ev_inv_end = P(gb), P(ge), P(ib), P(ie)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     assert hip.hipEventRecord(evs[0], C.c_void_p(stream.cuda_stream)) == 0
@@ -164,24 +190,119 @@ def main():
     assert hip.hipEventRecord(evs[1], C.c_void_p(stream.cuda_stream)) == 0
     torch.cuda.synchronize()
     total_ms = elapsed_ms(hip, evs[0], evs[1])
-    kern_ms = [elapsed_ms(hip, evs[2 + i], evs[2 + K + i]) for i in range(K)]
-    kern_avg_us = 1e3 * float(np.mean(kern_ms))
-    ms_per_step = total_ms / K
+    grad_us = 1e3 * float(np.mean([elapsed_ms(hip, gb[i], ge[i]) for i in range(K)]))
+    inv_us = (1e3 * float(np.mean([elapsed_ms(hip, ib[i], ie[i]) for i in range(K)]))
+              if solver.opts is not None else None)
     rse = float(solver.rse())
     status = int(solver.status.item())
-    print(f"[bench] timed {K} steps: {ms_per_step * 1e3:.2f} us/step, kernel {kern_avg_us:.2f} us, "
-          f"rse {rse:.3e}", file=sys.stderr, flush=True)
+    for e in evs:
+        hip.hipEventDestroy(e)
+    del solver
+    return dict(ms_per_step=total_ms / K, grad_us=grad_us, inv_us=inv_us, rse_after=rse, dev_status=status)
+
+
+def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100):
+    """Wall time from the initial cores until an RSE check reaches
+    ``target`` (checks every ``every`` steps count toward the time), capped
+    at args.ttt_steps steps."""
+    import torch
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    N = 3
+    solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law="U", scaled=True,
+                      prec=prec, rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
+                      overlap=not args.no_overlap)
+    solver.rse()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, rse, hist = 0, float("nan"), []
+    while steps < args.ttt_steps:
+        solver.run(every)
+        steps += every
+        rse = float(solver.rse())          # synchronises
+        hist.append((steps, rse))
+        if rse <= target:
+            break
+    wall = time.perf_counter() - t0
+    del solver
+    return {"prec": prec, "target": target, "reached": rse <= target,
+            "seconds": round(wall, 4) if rse <= target else None, "steps": steps,
+            "rse_at_stop": rse, "wall_s_at_stop": round(wall, 4), "rse_every": every,
+            "rse_trace": [[s_, float(f"{r_:.4e}")] for s_, r_ in hist[:: max(1, len(hist) // 10)]]}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is a design note, not implemented)"}))
+        sys.exit(2)
+    import torch
+
+    dev = "cuda:0"
+    I, R, kappa, m = 400, 10, 1e4, 4096
+    N = 3
+    desc, X, true3, init3 = build_problem(args.seed, I, R, kappa, dev)
+    print(f"[bench] workload ready: {I}^3 rank {R}, m={m}", file=sys.stderr, flush=True)
+    K = args.steps
+    main = timed_run(args, args.prec, init3, X, I, R, m, dev, K, args.warmup)
+    print(f"[bench] {args.prec}: {main['ms_per_step'] * 1e3:.2f} us/step, gradient {main['grad_us']:.2f} us, "
+          f"inverse {main['inv_us']} us, rse {main['rse_after']:.3e}", file=sys.stderr, flush=True)
+    other = "bf16" if args.prec == "f32" else "f32"
+    alt = timed_run(args, other, init3, X, I, R, m, dev, K, args.warmup)
+    print(f"[bench] {other}: {alt['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+    ttt = []
+    if args.ttt_steps > 0:
+        for pr in ("f32", "bf16"):
+            ttt.append(time_to_target(args, pr, init3, X, I, R, m, dev))
+            print(f"[bench] time-to-target {pr}: {ttt[-1]['reached']} after {ttt[-1]['steps']} steps, "
+                  f"rse {ttt[-1]['rse_at_stop']:.3e}", file=sys.stderr, flush=True)
 
     RR = R * R
     flops = 4.0 * I * m * RR                       # prediction + gradient contractions
     bytes_alg = I * m * 4 + m * RR * 4 + I * RR * 4  # fibers + sampled rows + core
     peak, unit = PEAK[args.prec]
-    achieved = flops / (kern_avg_us * 1e-6) / 1e12
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 5), "traffic": None,
-            "kernel": "k_grad_mfma_f32" if args.prec == "f32" else "k_grad_mixed", "kernel_avg_us": round(kern_avg_us, 3),
-            "flops_per_launch": flops, "alg_bytes_per_launch": bytes_alg,
-            "alg_hbm_gbs": round(bytes_alg / (kern_avg_us * 1e-6) / 1e9, 1)}
+    g_ach = flops / (main["grad_us"] * 1e-6) / 1e12
+    grad_roof = {"bound": "mfma", "achieved": round(g_ach, 3), "peak": peak, "unit": unit,
+                 "frac": round(g_ach / peak, 5), "traffic": None,
+                 "kernel": "k_grad_mfma_f32" if args.prec == "f32" else "k_grad_mixed",
+                 "kernel_avg_us": round(main["grad_us"], 3), "flops_per_launch": flops,
+                 "alg_bytes_per_launch": bytes_alg,
+                 "alg_hbm_gbs": round(bytes_alg / (main["grad_us"] * 1e-6) / 1e9, 1)}
+    roof = grad_roof
+    if main["inv_us"] is not None and main["inv_us"] > main["grad_us"]:
+        inv_flops = 2.0 * RR ** 3                 # Gauss-Jordan inverse of the RR x RR system
+        i_ach = inv_flops / (main["inv_us"] * 1e-6) / 1e12
+        roof = {"bound": "mfma", "achieved": round(i_ach, 6), "peak": PEAK["f64"][0], "unit": "TFLOP/s",
+                "frac": round(i_ach / PEAK["f64"][0], 7), "traffic": None, "kernel": "k_sweep",
+                "kernel_avg_us": round(main["inv_us"], 3), "flops_per_launch": inv_flops,
+                "note": "one workgroup, 13 dependent 8-pivot steps: bound by its dependency chain"}
+
+    batched = None
+    if args.batch_steps > 0:
+        print("[bench] building the 64-problem batch ...", file=sys.stderr, flush=True)
+        del X
+        torch.cuda.empty_cache()
+        B, insts = build_batch(args.seed, dev)
+        torch.cuda.synchronize()
+        tune = B.tune(steps=3, reps=2)
+        print(f"[bench] batch tuned: {tune} -> chunk {B.chunk}, waves {B.waves}", file=sys.stderr, flush=True)
+        B.run(2)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        B.run(args.batch_steps)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.batch_steps
+        batched = {"workload": "batched-64-planted-fp16", "problems": B.count, "m": 1024,
+                   "steps": args.batch_steps, "ms_per_batch_step": round(ms, 5),
+                   "problem_steps_per_s": round(B.count * 1e3 / ms, 1),
+                   "tiles": {"chunk": B.chunk, "waves": B.waves},
+                   "tuner_ms_per_step": {f"{c}x{w}": round(v, 5) for (c, w), v in tune.items()},
+                   "precision": "fp16 matrix cores, fp32 accumulation, fp64 loss",
+                   "mean_loss_estimate": float(B.loss.mean()), "dev_status_or": int(B.status.max())}
+        print(f"[bench] batch: {ms * 1e3:.1f} us per step of all 64 problems", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -191,13 +312,13 @@ def main():
                "sample": f"{k} oracle steps (FP64 numpy/scipy) of the same 400^3 workload after 1 warm-up step"}
 
     out = {
-        "metric": "sampled-gradient steps/s (TR-ScaledBRSGD, FP64 Cholesky), 1 GPU",
-        "value": round(1e3 / ms_per_step, 2),
+        "metric": "sampled-gradient steps/s + time to rel.err 1e-4: mixed vs plain FP32, 1 GPU",
+        "value": round(1e3 / main["ms_per_step"], 2),
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(main["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -207,9 +328,18 @@ def main():
                    "m": m, "m_H": m, "law": "uniform", "alpha": args.alpha, "prec": args.prec,
                    "overlap": not args.no_overlap},
         "roofline": roof,
+        "roofline_gradient": grad_roof,
         "cpu_baseline": cpu,
-        "rse_after": rse,
-        "dev_status": status,
+        "forms": {args.prec: {"steps_per_s": round(1e3 / main["ms_per_step"], 2), "rse_after": main["rse_after"],
+                              "gradient_us": round(main["grad_us"], 3),
+                              "inverse_us": None if main["inv_us"] is None else round(main["inv_us"], 3)},
+                  other: {"steps_per_s": round(1e3 / alt["ms_per_step"], 2), "rse_after": alt["rse_after"],
+                          "gradient_us": round(alt["grad_us"], 3),
+                          "inverse_us": None if alt["inv_us"] is None else round(alt["inv_us"], 3)}},
+        "time_to_target": ttt,
+        "batched": batched,
+        "rse_after": main["rse_after"],
+        "dev_status": main["dev_status"],
     }
     print(json.dumps(out), flush=True)
 

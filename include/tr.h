@@ -303,7 +303,9 @@ tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev
  *     before the update.  Work of one step never overlaps the next; the
  *     fork/join is graph-capturable; results are bitwise those of the
  *     one-stream run.  All four must be set together, or all NULL.
- *   ev_begin, ev_end: as in tr_run_events. */
+ *   ev_begin, ev_end: as in tr_run_events.
+ *   ev_inv_begin, ev_inv_end: the same around the RR x RR inverse of step i
+ *     (scaled steps with RR <= 128), recorded on the stream it runs on. */
 typedef struct {
     tr_stream_t aux;
     void* ev_fork;
@@ -311,6 +313,8 @@ typedef struct {
     void* ev_join;
     void* const* ev_begin;
     void* const* ev_end;
+    void* const* ev_inv_begin;
+    void* const* ev_inv_end;
 } tr_run_opts;
 
 /* tr_run with options; opts NULL is tr_run.  Same workspace. */
@@ -339,6 +343,46 @@ tr_status tr_entry_bwd(const tr_desc* d, const void* const* cores, const int32_t
                        const float* resid, int32_t B, double scale, const double* scale_dev,
                        void* const* grads, void* ws, size_t ws_bytes, tr_stream_t stream);
 size_t tr_entry_workspace_size(const tr_desc* d, int32_t B);
+
+/* ------------------------------------------------------------------ */
+/* a11: many independent problems in one persistent launch             */
+/* ------------------------------------------------------------------ */
+
+/* One problem of a batch: TR-BRSGD (Algorithm alg:TR_BRSGD) with uniform
+ * fiber sampling (Section "Four probability distributions", the uniform
+ * case) and the step rule ``rule``.  Cores FP32 (updated in place), the
+ * tensor as FP16 mode-major replicas (tr_x_replicate layout, all N
+ * required).  Limits: N <= 5, I_n <= 128, R_n <= 12 (R_n R_{n+1} <= 144). */
+typedef struct {
+    tr_desc desc;                        /* core_dtype TR_F32, x_dtype TR_F16 */
+    void* cores[TR_MAX_ORDER];
+    void* accum[TR_MAX_ORDER];           /* AdaGrad accumulators, or NULL     */
+    const void* Xrep[TR_MAX_ORDER];      /* mode-major replicas, FP16         */
+    uint64_t* t_dev;                     /* the problem's step counter        */
+    double* loss;                        /* device float64: last step's loss estimate, or NULL */
+    int32_t* dev_status;                 /* sticky TR_DEV_* bits, or NULL     */
+    int32_t m;                           /* |F_n| drawn per step              */
+    int32_t reserved;                    /* 0                                 */
+    tr_step rule;
+    uint64_t seed;
+} tr_batch_item;
+
+/* Bytes of the device table that holds ``count`` items. */
+size_t tr_batch_table_size(int32_t count);
+/* Validate ``count`` host items and copy them to the device table (caller
+ * allocated, 256-byte aligned).  Fails (nothing enqueued) on the first
+ * invalid item. */
+tr_status tr_batch_upload(const tr_batch_item* items, int32_t count, void* table, size_t table_bytes,
+                          tr_stream_t stream);
+/* Advance every problem of the table by ``steps`` steps in one launch:
+ * workgroup p owns problem p for all its steps (no inter-problem
+ * synchronisation).  Per step the gradient GEMMs run on FP16 matrix cores
+ * with FP32 accumulation; the loss estimate is FP64.  chunk (samples per
+ * round: 32 or 64) and waves (wavefronts per workgroup: 4 or 8) are the
+ * tile choice (see the package's batch tuner); every choice computes the
+ * same step.  Graph-capturable. */
+tr_status tr_batch_run(const void* table, int32_t count, int32_t steps, int32_t chunk, int32_t waves,
+                       tr_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -76,6 +76,22 @@ VP = C.c_void_p
 PVP = C.POINTER(C.c_void_p)
 
 
+class tr_batch_item(C.Structure):
+    _fields_ = [
+        ("desc", tr_desc),
+        ("cores", C.c_void_p * 8),
+        ("accum", C.c_void_p * 8),
+        ("Xrep", C.c_void_p * 8),
+        ("t_dev", C.c_void_p),
+        ("loss", C.c_void_p),
+        ("dev_status", C.c_void_p),
+        ("m", C.c_int32),
+        ("reserved", C.c_int32),
+        ("rule", tr_step),
+        ("seed", C.c_uint64),
+    ]
+
+
 class tr_run_opts(C.Structure):
     _fields_ = [
         ("aux", C.c_void_p),
@@ -84,6 +100,8 @@ class tr_run_opts(C.Structure):
         ("ev_join", C.c_void_p),
         ("ev_begin", PVP),
         ("ev_end", PVP),
+        ("ev_inv_begin", PVP),
+        ("ev_inv_end", PVP),
     ]
 
 I32, U64, F64, SZ = C.c_int32, C.c_uint64, C.c_double, C.c_size_t
@@ -115,6 +133,9 @@ _SIGS = {
     "tr_run_ex": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP, SZ, VP,
                         C.POINTER(tr_run_opts)]),
     "tr_run_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_config)]),
+    "tr_batch_table_size": (SZ, [I32]),
+    "tr_batch_upload": (I32, [C.POINTER(tr_batch_item), I32, VP, SZ, VP]),
+    "tr_batch_run": (I32, [VP, I32, I32, I32, I32, VP]),
     "tr_entry_fwd": (I32, [PDESC, PVP, VP, VP, I32, VP, VP, VP, SZ, VP]),
     "tr_entry_bwd": (I32, [PDESC, PVP, VP, VP, I32, F64, VP, PVP, VP, SZ, VP]),
     "tr_entry_workspace_size": (SZ, [PDESC, I32]),

@@ -476,7 +476,10 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                                     fork ? (hipEvent_t)o.ev_gram : nullptr);
                 }
             }
+            if (e == hipSuccess && o.ev_inv_begin && o.ev_inv_begin[it])
+                e = hipEventRecord((hipEvent_t)o.ev_inv_begin[it], hs);
             if (e == hipSuccess) e = launch_sweep_inverse(d, ms, gram, c->damping, L.ul, w + L.upd, dev_status, hs);
+            if (e == hipSuccess && o.ev_inv_end && o.ev_inv_end[it]) e = hipEventRecord((hipEvent_t)o.ev_inv_end[it], hs);
             if (e == hipSuccess && fork) e = hipEventRecord((hipEvent_t)o.ev_join, hs);
             if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, (hipEvent_t)o.ev_gram, 0);
             if (e == hipSuccess && ev_begin && ev_begin[it]) e = hipEventRecord((hipEvent_t)ev_begin[it], st);
@@ -527,6 +530,45 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
         }
     }
     return hip_status(e);
+}
+
+size_t tr_batch_table_size(int32_t count) { return count > 0 ? align_up((size_t)count * sizeof(tr_batch_item)) : 0; }
+
+tr_status tr_batch_upload(const tr_batch_item* items, int32_t count, void* table, size_t table_bytes,
+                          tr_stream_t stream) {
+    if (!items || count < 1 || count > 65535 || !table) return TR_E_ARG;
+    if (table_bytes < tr_batch_table_size(count)) return TR_E_WORKSPACE;
+    if (!aligned(table, 256)) return TR_E_ALIGN;
+    for (int p = 0; p < count; ++p) {
+        const tr_batch_item& it = items[p];
+        const tr_desc& d = it.desc;
+        tr_status s = validate_desc(&d);
+        if (s != TR_OK) return s;
+        if (d.core_dtype != TR_F32 || d.x_dtype != TR_F16) return TR_E_DTYPE;
+        if (d.N > 5) return TR_E_SHAPE;
+        if ((s = check_cores(&d, const_cast<const void* const*>(it.cores))) != TR_OK) return s;
+        for (int k = 0; k < d.N; ++k) {
+            if (d.I[k] > 128 || d.R[k] > 12) return TR_E_SHAPE;
+            if (d.R[k] * d.R[(k + 1) % d.N] > 144) return TR_E_SHAPE;
+            if (!it.Xrep[k]) return TR_E_ARG;
+            if (it.rule.kind == 1 && !it.accum[k]) return TR_E_ARG;
+        }
+        if (!it.t_dev || it.m < 1 || it.m > kMaxM) return TR_E_ARG;
+        if (it.rule.kind < 0 || it.rule.kind > 2) return TR_E_ARG;
+        if (it.rule.kind == 2 && !(it.rule.tau > 0.0)) return TR_E_ARG;
+    }
+    return hip_status(hipMemcpyAsync(table, items, (size_t)count * sizeof(tr_batch_item), hipMemcpyHostToDevice,
+                                     (hipStream_t)stream));
+}
+
+tr_status tr_batch_run(const void* table, int32_t count, int32_t steps, int32_t chunk, int32_t waves,
+                       tr_stream_t stream) {
+    if (!table || count < 1 || count > 65535 || steps < 0) return TR_E_ARG;
+    if (!((chunk == 32 || chunk == 64) && (waves == 4 || waves == 8))) return TR_E_ARG;
+    if (!aligned(table, 256)) return TR_E_ALIGN;
+    if (steps == 0) return TR_OK;
+    return hip_status(launch_batch_steps(static_cast<const tr_batch_item*>(table), count, steps, chunk, waves,
+                                         (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -1,0 +1,314 @@
+// a11: many independent TR problems (uneven order, sizes and ranks) advance
+// by TR-BRSGD steps (Algorithm alg:TR_BRSGD with uniform fiber sampling) in
+// one persistent launch: workgroup p owns problem p and runs all its steps
+// itself, so problems never wait on each other and no grid-wide
+// synchronisation exists.  One step of one problem:
+//   mode n from (seed, t); per chunk of CH samples: Philox draws (one per
+//   (sample, core)), the sampled subchain rows S (slice products, stored as
+//   FP16 in LDS row-major and transposed), the fibers from the mode-major
+//   replica, E = X_F - G_n S^T on FP16 matrix cores with FP32 accumulation
+//   (E scaled by 1/(J_n p_f) and rounded to FP16), g += E S on FP16 matrix
+//   cores into an FP32 LDS accumulator; then p = g / m (eq:S_gradient with
+//   the sign of the direction folded in) and the step rule on the core.
+// The loss estimate of the step is written in FP64.  The chunk size and the
+// number of wavefronts are template parameters picked by the host tuner.
+#include "internal.hpp"
+
+namespace trk {
+
+typedef float f32x4b __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBatchMaxI = 128;     // I_n
+constexpr int kBatchMaxRR = 160;    // R_n R_{n+1} <= 144, padded to the K step (32)
+constexpr int kBatchRank = 12;      // R_n
+constexpr int kBatchGroup = 16;     // samples whose core slices are staged together
+constexpr int kBatchMaxN = 5;       // order (slices per sample: N - 1)
+// the FP32 slices of a group, each padded to 12 x 12
+constexpr int kBatchSliceFloats = kBatchGroup * (kBatchMaxN - 1) * 12 * 12;
+
+template <int CH>
+struct BatchLds {
+    static constexpr int SP = kBatchMaxRR + 8;   // pitch of S rows (FP16)
+    static constexpr int TP = CH + 8;            // pitch of S^T and E rows (FP16)
+    static constexpr size_t s_off = 0;
+    static constexpr size_t t_off = s_off + (size_t)CH * SP * 2;
+    static constexpr size_t e_off = t_off + (size_t)kBatchMaxRR * TP * 2;
+    static constexpr size_t c_off = e_off + (size_t)kBatchMaxI * TP * 2;     // staged slices (FP32)
+    static constexpr size_t a_off = c_off + (size_t)kBatchSliceFloats * 4;   // G_n rows (FP16), pitch SP
+    static constexpr size_t i_off = a_off + (size_t)kBatchMaxI * SP * 2;     // sample indices [CH][8]
+    static constexpr size_t w_off = i_off + (size_t)CH * kMaxOrder * 4;      // weights [CH] float
+    static constexpr size_t o_off = w_off + (size_t)CH * 4;                  // fiber offsets [CH] int64
+    static constexpr size_t total = o_off + (size_t)CH * 8 + 64;
+};
+
+template <int CH, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item* __restrict__ items, int steps) {
+    using Lz = BatchLds<CH>;
+    constexpr int NT = 64 * WAVES;
+    constexpr int RTW = 8 / WAVES;                           // row tiles of E per wavefront
+    constexpr int GSL = (8 * 9 + WAVES - 1) / WAVES;       // g tiles per wavefront (MT <= 8, CT <= 9)
+    constexpr int KS = kBatchMaxRR / 32;                     // K steps of the prediction GEMM
+    // The problem's record in LDS: its sizes, ranks and core pointers are
+    // indexed by mode at run time, which from global memory would cost a
+    // dependent load per use.
+    __shared__ __align__(16) tr_batch_item it;
+    {
+        const int* src = reinterpret_cast<const int*>(items + blockIdx.x);
+        int* dst = reinterpret_cast<int*>(&it);
+        for (int i = threadIdx.x; i < (int)(sizeof(tr_batch_item) / 4); i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
+    const tr_desc& d = it.desc;
+    const int N = d.N, tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int wv = tid >> 6;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    _Float16* sS = reinterpret_cast<_Float16*>(smem_raw + Lz::s_off);
+    _Float16* sT = reinterpret_cast<_Float16*>(smem_raw + Lz::t_off);
+    _Float16* sE = reinterpret_cast<_Float16*>(smem_raw + Lz::e_off);
+    float* sC = reinterpret_cast<float*>(smem_raw + Lz::c_off);
+    _Float16* sA = reinterpret_cast<_Float16*>(smem_raw + Lz::a_off);
+    int* sidx = reinterpret_cast<int*>(smem_raw + Lz::i_off);
+    float* sw = reinterpret_cast<float*>(smem_raw + Lz::w_off);
+    int64_t* soff = reinterpret_cast<int64_t*>(smem_raw + Lz::o_off);
+    __shared__ double red[WAVES];
+    __shared__ int qoff[kMaxOrder + 1];   // slice offsets of the chain stages within a sample
+
+    uint64_t t = *it.t_dev;
+    const int m = it.m;
+    for (int step = 0; step < steps; ++step) {
+        const int n = pick_mode(it.seed, t, N);
+        const int n1 = ring_next(n, N);
+        const int In = d.I[n], Rn = d.R[n], Rn1 = d.R[n1], RR = Rn * Rn1;
+        const int MT = (In + 15) >> 4, CT = (RR + 15) >> 4;
+        const double J = (double)J_of(d, n);
+        int64_t xs[kMaxOrder];                       // replica strides: fiber of mode n contiguous
+        {
+            int64_t s = In;
+            xs[n] = 1;
+            int k = n;
+            for (int q = 1; q < N; ++q) {
+                k = ring_next(k, N);
+                xs[k] = s;
+                s *= d.I[k];
+            }
+        }
+        __syncthreads();   // the previous step is done with qoff
+        if (tid == 0) {
+            int o = 0;
+            for (int q = 0; q < N - 1; ++q) {
+                qoff[q] = o;
+                const int k = (n + 1 + q) % N;
+                o += d.R[k] * d.R[ring_next(k, N)];
+            }
+            qoff[N - 1] = o;
+        }
+        const float* Gn = static_cast<const float*>(it.cores[n]);
+        const _Float16* X = static_cast<const _Float16*>(it.Xrep[n]);
+        // G_n as FP16 A operands for the whole step (K padded with zeros)
+        for (int e = tid; e < kBatchMaxI * kBatchMaxRR; e += NT) {
+            const int row = e / kBatchMaxRR, k = e - row * kBatchMaxRR;
+            sA[row * Lz::SP + k] = (_Float16)((row < In && k < RR) ? Gn[(int64_t)row * RR + k] : 0.f);
+        }
+        f32x4b gacc[GSL];
+#pragma unroll
+        for (int q = 0; q < GSL; ++q) gacc[q] = f32x4b{0.f, 0.f, 0.f, 0.f};
+        double lsum = 0.0;
+        for (int f0 = 0; f0 < m; f0 += CH) {
+            const int nb = min(CH, m - f0);
+            __syncthreads();   // previous chunk done with S, E, indices; qoff written
+            for (int w = tid; w < nb * (N - 1); w += NT) {
+                const int fl = w / (N - 1), q = w - fl * (N - 1);
+                const int k = (n + 1 + q) % N;
+                const uint64_t r = draw_word(it.seed, t, (uint64_t)(f0 + fl), (uint64_t)k, TR_STREAM_IDX);
+                sidx[fl * kMaxOrder + k] = (int)mulhi64(r, (uint64_t)d.I[k]);
+            }
+            __syncthreads();
+            for (int fl = tid; fl < CH; fl += NT) {
+                float ws = 0.f;
+                int64_t off = 0;
+                if (fl < nb) {
+                    double p = 1.0;   // uniform law, multiplied in the chain order
+                    for (int q = 0; q < N - 1; ++q) {
+                        const int k = (n + 1 + q) % N;
+                        p = p * (1.0 / (double)d.I[k]);
+                        off += (int64_t)sidx[fl * kMaxOrder + k] * xs[k];
+                    }
+                    ws = (float)(1.0 / (J * p));
+                }
+                sw[fl] = ws;
+                soff[fl] = off;
+            }
+            // Rows of M_f = G_{n+1}(i) ... G_{n-1}(i), S(f, r + R_n s) = M_f(s, r),
+            // kBatchGroup samples at a time: each slice is staged in LDS
+            // zero-padded to 12 x 12 (element (r, c) at r + 12 c), every load
+            // of the group in flight together; then one thread per (sample,
+            // row s) carries row s of M_f through the chain in registers with
+            // unrolled 12 x 12 products (the padding multiplies zeros).  FP32
+            // throughout, rounded to FP16 once.
+            constexpr int PS = kBatchRank * kBatchRank;                 // padded slice
+            constexpr int PW = (kBatchGroup * (kBatchMaxN - 1) + WAVES - 1) / WAVES;   // slices per wave
+            for (int g0 = 0; g0 < CH; g0 += kBatchGroup) {
+                const int gn = min(kBatchGroup, CH - g0);
+                float v[PW][3];
+#pragma unroll
+                for (int j = 0; j < PW; ++j) {
+                    const int pr = wv + WAVES * j;                       // (sample, stage) pair
+                    const int fl = pr / (N - 1), q = pr - fl * (N - 1);
+                    int k = n + 1 + q;
+                    k = k >= N ? k - N : k;
+                    k = k >= N ? k - N : k;
+                    const bool ok = pr < gn * (N - 1) && g0 + fl < nb;
+                    const int Rk = d.R[k], Rk1 = d.R[k + 1 == N ? 0 : k + 1];
+                    const float* src = static_cast<const float*>(it.cores[k]) +
+                                       (int64_t)(ok ? sidx[(g0 + fl) * kMaxOrder + k] : 0) * Rk * Rk1;
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const int pidx = l + 64 * u, r = pidx % kBatchRank, c = pidx / kBatchRank;
+                        v[j][u] = (ok && pidx < PS && r < Rk && c < Rk1) ? src[r + Rk * c] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < PW; ++j) {
+                    const int pr = wv + WAVES * j;
+                    if (pr < gn * (N - 1)) {
+#pragma unroll
+                        for (int u = 0; u < 3; ++u)
+                            if (l + 64 * u < PS) sC[(size_t)pr * PS + l + 64 * u] = v[j][u];
+                    }
+                }
+                __syncthreads();
+                for (int w = tid; w < gn * Rn1; w += NT) {
+                    const int fl = w / Rn1, s = w - fl * Rn1;
+                    const float* base = sC + (size_t)fl * (N - 1) * PS;
+                    float row[kBatchRank];
+#pragma unroll
+                    for (int c = 0; c < kBatchRank; ++c) row[c] = base[s + kBatchRank * c];
+                    for (int q = 1; q < N - 1; ++q) {
+                        const float4* A4 = reinterpret_cast<const float4*>(base + q * PS);
+                        float nr[kBatchRank];
+#pragma unroll
+                        for (int c = 0; c < kBatchRank; ++c) {
+                            const float4 a0 = A4[3 * c], a1 = A4[3 * c + 1], a2 = A4[3 * c + 2];
+                            nr[c] = row[0] * a0.x + row[1] * a0.y + row[2] * a0.z + row[3] * a0.w +
+                                    row[4] * a1.x + row[5] * a1.y + row[6] * a1.z + row[7] * a1.w +
+                                    row[8] * a2.x + row[9] * a2.y + row[10] * a2.z + row[11] * a2.w;
+                        }
+#pragma unroll
+                        for (int c = 0; c < kBatchRank; ++c) row[c] = nr[c];
+                    }
+                    const int f = g0 + fl;
+#pragma unroll
+                    for (int r = 0; r < kBatchRank; ++r)
+                        if (r < Rn) {
+                            const _Float16 h = (_Float16)(f < nb ? row[r] : 0.f);
+                            sS[f * Lz::SP + r + Rn * s] = h;
+                            sT[(r + Rn * s) * Lz::TP + f] = h;
+                        }
+                }
+                __syncthreads();   // slices consumed before the next group overwrites them
+            }
+            for (int w = tid; w < CH * (kBatchMaxRR - RR); w += NT) {   // K padding of S rows
+                const int fl = w / (kBatchMaxRR - RR), c = RR + w % (kBatchMaxRR - RR);
+                sS[fl * Lz::SP + c] = (_Float16)0.f;
+            }
+            for (int w = tid; w < (16 * CT - RR) * CH; w += NT) {        // column padding of S^T
+                const int c = RR + w / CH, fl = w % CH;
+                sT[c * Lz::TP + fl] = (_Float16)0.f;
+            }
+            __syncthreads();
+            // E = X_F - G_n S^T: wavefront wv takes row tiles wv (+ WAVES),
+            // all sample tiles; FP16 operands, FP32 accumulation.
+#pragma unroll
+            for (int u = 0; u < RTW; ++u) {
+                const int rt = wv + WAVES * u;
+#pragma unroll
+                for (int st = 0; st < CH / 16; ++st) {
+                    f32x4b acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const h8 a = *reinterpret_cast<const h8*>(sA + (16 * rt + lr) * Lz::SP + 32 * ks + 8 * lk);
+                        const h8 b = *reinterpret_cast<const h8*>(sS + (16 * st + lr) * Lz::SP + 32 * ks + 8 * lk);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
+                    }
+                    if (rt < MT) {
+                        const int fl = 16 * st + lr;
+                        const float ws = sw[fl];
+                        const int64_t off = soff[fl];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int i = 16 * rt + 4 * lk + j;
+                            float e = 0.f;
+                            if (i < In && fl < nb) {
+                                e = (float)X[off + i] - acc[j];
+                                lsum += (double)ws * (double)e * (double)e;
+                            }
+                            sE[i * Lz::TP + fl] = (_Float16)(e * ws);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // g += (E D) S: tile T = wv + WAVES q of the MT x CT grid in slot q;
+            // slots past the grid multiply zeros.
+#pragma unroll
+            for (int q = 0; q < GSL; ++q) {
+                const int T = wv + WAVES * q;
+                const bool ok = T < MT * CT;
+                const int rt = ok ? T / CT : 0, ct = ok ? T - (T / CT) * CT : 0;
+#pragma unroll
+                for (int ks = 0; ks < CH / 32; ++ks) {
+                    const int k0 = 32 * ks + 8 * lk;
+                    const h8 a = ok ? *reinterpret_cast<const h8*>(sE + (16 * rt + lr) * Lz::TP + k0) : h8{};
+                    const h8 b = ok ? *reinterpret_cast<const h8*>(sT + (16 * ct + lr) * Lz::TP + k0) : h8{};
+                    gacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, gacc[q], 0, 0, 0);
+                }
+            }
+        }
+        // p = g / m on this wavefront's tiles, then the rule
+        float* G = static_cast<float*>(it.cores[n]);
+        float* A = static_cast<float*>(it.accum[n]);
+        const float invm = 1.f / (float)m;
+        __syncthreads();   // every wavefront has read G_n for this step
+#pragma unroll
+        for (int q = 0; q < GSL; ++q) {
+            const int T = wv + WAVES * q;
+            if (T < MT * CT) {
+                const int rt = T / CT, ct = T - rt * CT;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = 16 * rt + 4 * lk + j, c = 16 * ct + lr;
+                    if (i < In && c < RR)
+                        apply_rule<float>(G, A, (int64_t)i * RR + c, (double)(gacc[q][j] * invm), it.rule, t,
+                                          it.dev_status);
+                }
+            }
+        }
+        // loss estimate sum_f ||e_f||^2 / (2 m p_f); lsum carries 1/(J p_f)
+        const double ls = block_sum(lsum, red);
+        if (tid == 0 && it.loss) *it.loss = ls * J / (2.0 * (double)m);
+        t += 1;
+        __syncthreads();   // the update is visible to the next step's reads (same workgroup)
+    }
+    if (tid == 0) *it.t_dev = t;
+}
+
+size_t batch_lds_bytes(int chunk) { return chunk == 32 ? BatchLds<32>::total : BatchLds<64>::total; }
+
+hipError_t launch_batch_steps(const tr_batch_item* items, int count, int steps, int chunk, int waves, hipStream_t st) {
+#define TRK_BATCH(CH, W)                                                                                  \
+    do {                                                                                                  \
+        const size_t shm = BatchLds<CH>::total;                                                          \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_batch_steps<CH, W>), shm)) return hipErrorInvalidValue; \
+        hipLaunchKernelGGL((k_batch_steps<CH, W>), dim3(count), dim3(64 * W), shm, st, items, steps);      \
+    } while (0)
+    if (chunk == 32 && waves == 4) TRK_BATCH(32, 4);
+    else if (chunk == 32 && waves == 8) TRK_BATCH(32, 8);
+    else if (chunk == 64 && waves == 4) TRK_BATCH(64, 4);
+    else if (chunk == 64 && waves == 8) TRK_BATCH(64, 8);
+    else return hipErrorInvalidValue;
+#undef TRK_BATCH
+    return hipGetLastError();
+}
+
+}  // namespace trk

@@ -136,6 +136,10 @@ hipError_t launch_dist_optimal(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
                                uint64_t* cdf_J, int32_t* status, void* ws, hipStream_t st);
 
 hipError_t launch_bump(uint64_t* t_dev, hipStream_t st);
+
+// a11: batched independent problems.
+size_t batch_lds_bytes(int chunk);
+hipError_t launch_batch_steps(const tr_batch_item* items, int count, int steps, int chunk, int waves, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 
 }  // namespace trk

@@ -114,3 +114,88 @@ class TRSolver:
     @property
     def t(self) -> int:
         return int(self.t_dev.item())
+
+
+class TRBatch:
+    """Many independent problems advanced together by ``tr_batch_run``.
+
+    problems: list of dicts with keys cores (list of FP32 device G_{k(2)}),
+    Xrep (list of FP16 mode-major replicas), I, R, m, rule (L.tr_step),
+    seed.  The object owns the device table, the per-problem step counters,
+    loss estimates and status words."""
+
+    VARIANTS = ((32, 4), (32, 8), (64, 4), (64, 8))
+
+    def __init__(self, problems, device="cuda"):
+        self.count = len(problems)
+        self.problems = problems
+        self.t_dev = torch.zeros(self.count, dtype=torch.int64, device=device)
+        self.loss = torch.zeros(self.count, dtype=torch.float64, device=device)
+        self.status = torch.zeros(self.count, dtype=torch.int32, device=device)
+        self.accum = []
+        items = (L.tr_batch_item * self.count)()
+        for p, pr in enumerate(problems):
+            N = len(pr["I"])
+            it = items[p]
+            it.desc = api.make_desc(pr["I"], pr["R"], torch.float32, torch.float16)
+            rule = pr["rule"]
+            acc = [torch.zeros_like(c) for c in pr["cores"]] if rule.kind == 1 else [None] * N
+            self.accum.append(acc)
+            for k in range(N):
+                it.cores[k] = pr["cores"][k].data_ptr()
+                it.accum[k] = acc[k].data_ptr() if acc[k] is not None else None
+                it.Xrep[k] = pr["Xrep"][k].data_ptr()
+            it.t_dev = self.t_dev.data_ptr() + 8 * p
+            it.loss = self.loss.data_ptr() + 8 * p
+            it.dev_status = self.status.data_ptr() + 4 * p
+            it.m, it.rule, it.seed = pr["m"], rule, pr["seed"]
+        self.items = items
+        self.table = api.workspace(L.lib().tr_batch_table_size(self.count), device)
+        api.check("tr_batch_upload", L.lib().tr_batch_upload(items, self.count, C.c_void_p(self.table.data_ptr()),
+                                                             self.table.numel(), api._stream()))
+        self.chunk, self.waves = 64, 4
+
+    def run(self, steps: int, chunk=None, waves=None):
+        api.check("tr_batch_run", L.lib().tr_batch_run(C.c_void_p(self.table.data_ptr()), self.count, steps,
+                                                       chunk or self.chunk, waves or self.waves, api._stream()))
+
+    def _state(self):
+        cores = [[c.clone() for c in pr["cores"]] for pr in self.problems]
+        acc = [[a.clone() if a is not None else None for a in aa] for aa in self.accum]
+        return cores, acc, self.t_dev.clone(), self.loss.clone(), self.status.clone()
+
+    def _restore(self, st):
+        cores, acc, t, loss, status = st
+        for pr, cs in zip(self.problems, cores):
+            for c, s in zip(pr["cores"], cs):
+                c.copy_(s)
+        for aa, ss in zip(self.accum, acc):
+            for a, s in zip(aa, ss):
+                if a is not None:
+                    a.copy_(s)
+        self.t_dev.copy_(t)
+        self.loss.copy_(loss)
+        self.status.copy_(status)
+
+    def tune(self, steps: int = 3, reps: int = 2):
+        """Time every (chunk, waves) variant on this batch and keep the
+        fastest; the problems' state is restored afterwards.  Returns
+        {variant: ms per step}."""
+        saved = self._state()
+        times = {}
+        for ch, wv in self.VARIANTS:
+            self.run(1, ch, wv)                      # warm-up (module load, caches)
+            torch.cuda.synchronize()
+            best = float("inf")
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                self.run(steps, ch, wv)
+                b.record()
+                torch.cuda.synchronize()
+                best = min(best, a.elapsed_time(b) / steps)
+            times[(ch, wv)] = best
+        self._restore(saved)
+        torch.cuda.synchronize()
+        self.chunk, self.waves = min(times, key=times.get)
+        return times

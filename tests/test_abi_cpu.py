@@ -130,3 +130,43 @@ def test_host_validation_rejects_bad_arguments():
     env = dict(os.environ, HIP_VISIBLE_DEVICES="-1")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_batch_upload_rejects_bad_items_before_any_device_call():
+    """Host validation of tr_batch_upload / tr_batch_run in a child with no
+    GPU visible: every case fails before the copy or the launch."""
+    code = textwrap.dedent(f"""
+        import sys, ctypes as C; sys.path.insert(0, {ROOT!r})
+        import torch
+        from paper_2303_16492_amd import _lib as L, api
+        h = L.lib()
+        def item(I, R, xdt=torch.float16, reps=True, t=True, rule="fixed"):
+            it = L.tr_batch_item()
+            it.desc = api.make_desc(I, R, torch.float32, xdt)
+            for k in range(len(I)):
+                it.cores[k] = 4096 * (k + 1)
+                it.Xrep[k] = 8192 * (k + 1) if reps else None
+            it.t_dev = 256 if t else None
+            it.m, it.rule, it.seed = 16, api.step_rule(rule, alpha=0.1), 1
+            return it
+        table = C.c_void_p(1 << 20)
+        size = h.tr_batch_table_size(1)
+        assert size >= C.sizeof(L.tr_batch_item)
+        def up(it):
+            return h.tr_batch_upload((L.tr_batch_item * 1)(it), 1, table, size, None)
+        assert up(item([8, 9, 10], [2, 3, 2], xdt=torch.float32)) == -3   # X must be FP16
+        assert up(item([8, 9, 200], [2, 3, 2])) == -2                      # I_n above 128
+        assert up(item([8, 9, 10], [13, 3, 2])) == -2                      # R_n above 12
+        assert up(item([8, 9, 10], [2, 3, 2], reps=False)) == -1           # replicas required
+        assert up(item([8, 9, 10], [2, 3, 2], t=False)) == -1              # step counter required
+        assert up(item([8, 9, 10], [2, 3, 2], rule="adagrad")) == -1       # accumulators required
+        assert h.tr_batch_upload((L.tr_batch_item * 1)(item([8, 9, 10], [2, 3, 2])), 1, table, size - 1,
+                                 None) == -5
+        assert h.tr_batch_run(table, 1, 1, 48, 4, None) == -1              # chunk not offered
+        assert h.tr_batch_run(table, 1, 1, 64, 6, None) == -1              # waves not offered
+        assert h.tr_batch_run(C.c_void_p((1 << 20) + 8), 1, 1, 64, 4, None) == -4
+        print("ok")
+    """)
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="-1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
