@@ -19,6 +19,7 @@ import argparse
 import ctypes as C
 import json
 import os
+import re
 import sys
 import time
 
@@ -46,6 +47,8 @@ def parse():
                     help="run the Gram/inverse branch on the main stream too")
     ap.add_argument("--ttt-steps", type=int, default=3000,
                     help="step cap of each time-to-target run (0: skip them)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 20 plain device copies of MIB MiB (counter calibration) and exit")
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="timed steps of the 64-problem batched workload (0: skip it)")
     return ap.parse_args()
@@ -156,6 +159,29 @@ def cpu_baseline(seconds, seed, I, R, kappa, m, alpha):
     return k / dt, k, threads
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scaled-illcond-n3-i400-r10.txt")
+KERNEL_SOURCE = {"k_sweep": "sweep.hip", "k_grad_mfma_f32": "grad_mfma.hip", "k_grad_mixed": "grad_mixed.hip"}
+
+
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes per launch of ``kernel`` from the committed
+    profile summary, or None if the kernel's source changed since."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_2303_16492_amd", "csrc", KERNEL_SOURCE[kernel])
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    for ln in lines:
+        if ln.startswith("#") or "|" not in ln:
+            continue
+        name, _, _, _, nbytes, ksha = [x.strip() for x in ln.split("|")]
+        if re.search(rf"\b{kernel}<", name) and ksha == sha:
+            return int(nbytes)
+    return None
+
+
 def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup):
     """K timed steps of the scaled method in precision ``prec`` from the
     initial cores; per-launch HIP events around the gradient and the
@@ -240,6 +266,16 @@ def main():
     import torch
 
     dev = "cuda:0"
+    if args.copy_probe > 0:
+        # known-size traffic for scaling the FETCH_SIZE / WRITE_SIZE counters
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 20}), flush=True)
+        return
     I, R, kappa, m = 400, 10, 1e4, 4096
     N = 3
     desc, X, true3, init3 = build_problem(args.seed, I, R, kappa, dev)
@@ -263,8 +299,9 @@ def main():
     bytes_alg = I * m * 4 + m * RR * 4 + I * RR * 4  # fibers + sampled rows + core
     peak, unit = PEAK[args.prec]
     g_ach = flops / (main["grad_us"] * 1e-6) / 1e12
+    gkern = "k_grad_mfma_f32" if args.prec == "f32" else "k_grad_mixed"
     grad_roof = {"bound": "mfma", "achieved": round(g_ach, 3), "peak": peak, "unit": unit,
-                 "frac": round(g_ach / peak, 5), "traffic": None,
+                 "frac": round(g_ach / peak, 5), "traffic": measured_traffic(gkern),
                  "kernel": "k_grad_mfma_f32" if args.prec == "f32" else "k_grad_mixed",
                  "kernel_avg_us": round(main["grad_us"], 3), "flops_per_launch": flops,
                  "alg_bytes_per_launch": bytes_alg,
@@ -274,7 +311,7 @@ def main():
         inv_flops = 2.0 * RR ** 3                 # Gauss-Jordan inverse of the RR x RR system
         i_ach = inv_flops / (main["inv_us"] * 1e-6) / 1e12
         roof = {"bound": "mfma", "achieved": round(i_ach, 6), "peak": PEAK["f64"][0], "unit": "TFLOP/s",
-                "frac": round(i_ach / PEAK["f64"][0], 7), "traffic": None, "kernel": "k_sweep",
+                "frac": round(i_ach / PEAK["f64"][0], 7), "traffic": measured_traffic("k_sweep"), "kernel": "k_sweep",
                 "kernel_avg_us": round(main["inv_us"], 3), "flops_per_launch": inv_flops,
                 "note": "one workgroup, 13 dependent 8-pivot steps: bound by its dependency chain"}
 

@@ -491,8 +491,8 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                                        dev_status, st);
             if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, (hipEvent_t)o.ev_join, 0);
             if (e == hipSuccess)
-                e = launch_sweep_apply(d, ms, g, 1, 0, LossParts{}, nullptr, mcores, acc, c->rule, dev_status,
-                                       w + L.upd, L.ul, fused, st);
+                e = launch_sweep_apply(d, ms, g, LossParts{}, nullptr, mcores, acc, c->rule, dev_status, w + L.upd,
+                                       L.ul, fused, st);
         } else {
             if (e == hipSuccess && ev_begin && ev_begin[it]) e = hipEventRecord((hipEvent_t)ev_begin[it], st);
             if (e == hipSuccess)

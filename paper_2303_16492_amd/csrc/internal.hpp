@@ -109,21 +109,18 @@ UpdWs upd_ws_layout(const tr_desc& d);
 hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping,
                                 const void* g, MutPtrs cores, MutPtrs accum, tr_step rule,
                                 int32_t* status, void* ws, const UpdWs& L, hipStream_t st);
-// The same for RR <= 128 through the blocked sweep: g is the fixed-order
-// sum of ``groups`` slices of gsrc (stride gstride; 1 and 0 for a plain g);
-// with lp.part set the loss is written too.
+// The same for RR <= 128 through the blocked sweep (g already reduced).
 bool sweep_supported(const tr_desc& d);
-hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* gsrc,
-                               int groups, int64_t gstride, LossParts lp, double* loss, MutPtrs cores,
-                               MutPtrs accum, tr_step rule, int32_t* status, void* ws, const UpdWs& L,
-                               StepBump step, hipStream_t st);
+hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* g,
+                               double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status, void* ws,
+                               const UpdWs& L, StepBump step, hipStream_t st);
 // The two halves: -(gram + damping I)^{-1} (one workgroup) and the
 // row-parallel p = g (-M^{-1}) with the rule.
 hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const UpdWs& L,
                                 void* ws, int32_t* status, hipStream_t st);
-hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* gsrc, int groups, int64_t gstride,
-                              LossParts lp, double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
-                              void* ws, const UpdWs& L, StepBump step, hipStream_t st);
+hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossParts lp, double* loss, MutPtrs cores,
+                              MutPtrs accum, tr_step rule, int32_t* status, void* ws, const UpdWs& L, StepBump step,
+                              hipStream_t st);
 hipError_t launch_plain_update(const tr_desc& d, ModeSrc ms, const void* g, MutPtrs cores,
                                MutPtrs accum, tr_step rule, int32_t* status, hipStream_t st);
 

@@ -265,13 +265,15 @@ __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const doub
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     double* Vw = Vws[w];
 
-    double tr = 0.0;
-    for (int c = tid; c < RR; c += 256) tr += gram[(int64_t)c * RR + c];
-    const double base = (block_sum(tr, red) + damping * RR) / RR;   // tr(h + damping I) / RR
-
     dbl4 acc[TPW];
     int ok_at = -1;
+    double base = 0.0;   // tr(h + damping I) / RR, needed only once a factorisation has failed
     for (int attempt = 0; attempt < 8; ++attempt) {
+        if (attempt == 1) {
+            double tr = 0.0;
+            for (int c = tid; c < RR; c += 256) tr += gram[(int64_t)c * RR + c];
+            base = (block_sum(tr, red) + damping * RR) / RR;
+        }
         const double eta = attempt == 0 ? damping : damping + pow(10.0, (double)(attempt - 1 - 10)) * base;
 #define TRK_FILL(WV) fill_tiles<NT, WV>(acc, gram, RR, eta)
         TRK_BY_WAVE(TRK_FILL)
@@ -318,20 +320,19 @@ __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const doub
 
 #undef TRK_BY_WAVE
 
-constexpr int kApplyRows = 4;
+constexpr int kApplyRows = 16;
 
-// p = g (-M^{-1}) for kApplyRows rows of g per block, then the rule.  g is
-// the fixed-order sum of ``groups`` partial slices (stride gstride); with
-// lp.part set, block 0 also writes the loss.  Every global load of a block
-// (the inverse, the partial slices, the core and accumulator entries it
-// updates, the factorisation flag) is issued before the first use, so the
-// block waits on memory once.  Thread t owns entries t and t + 256 of the
-// block's rows: it adds their partials and later updates them.  With
+// p = g (-M^{-1}) for 16 rows of g per block, then the rule.  Product on
+// FP64 matrix cores: wavefront w owns the 16 x 16 output tiles of columns
+// 16n.., n = w and w + 4; every operand (the block's rows of g, the
+// columns of -M^{-1} it needs, the core and accumulator entries it updates)
+// is loaded straight from global memory with all loads in flight, K padded
+// with zeros to 128.  With lp.part set, block 0 also writes the loss.  With
 // ``step`` set, the block that finishes last advances the step counter
 // (after every block has read it).
 template <typename TC>
-__global__ __launch_bounds__(256) void k_scaled_apply(tr_desc d, ModeSrc ms, const TC* __restrict__ gsrc, int groups,
-                                                      int64_t gstride, LossParts lp, double* __restrict__ loss,
+__global__ __launch_bounds__(256) void k_scaled_apply(tr_desc d, ModeSrc ms, const TC* __restrict__ g,
+                                                      LossParts lp, double* __restrict__ loss,
                                                       const double* __restrict__ hm, const int* __restrict__ flag,
                                                       MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
                                                       StepBump step) {
@@ -340,87 +341,60 @@ __global__ __launch_bounds__(256) void k_scaled_apply(tr_desc d, ModeSrc ms, con
     resolve_mode(ms, d.N, &t, &n);
     const int In = d.I[n];
     const int RR = d.R[n] * d.R[ring_next(n, d.N)];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4, w = tid >> 6;
     __shared__ double red[4];
     if (blockIdx.x == 0 && lp.part) {
         const double s = loss_parts_sum(lp, In, red);
         if (tid == 0) *loss = s;
     }
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* sH = reinterpret_cast<double*>(smem_raw);    // RR x RR
-    double* sG = sH + (size_t)RR * RR;                    // kApplyRows x RR
+    constexpr int KS = 32;                          // K steps of 4: RR <= 128
     const int r0 = blockIdx.x * kApplyRows;
-    const int rows = max(0, min(kApplyRows, In - r0));
-    const int ne = rows * RR;                             // <= 2 * 256 (RR <= 128)
+    const int NTc = (RR + 15) >> 4;
+    const int fl = *flag;
     TC* G = static_cast<TC*>(cores.p[n]);
     TC* A = static_cast<TC*>(accum.p[n]);
-    const int64_t base = (int64_t)r0 * RR;
-
-    constexpr int HB = 32;                 // RR^2 / 2 / 256 <= 32 pairs per thread
-    constexpr int GB = 32;                 // partial slices fetched together
-    const int fl = *flag;
-    const int tot2 = (RR * RR + 1) >> 1;   // an odd RR^2 reads one pad entry of the workspace
-    const double2* hm2 = reinterpret_cast<const double2*>(hm);
-    double2 hv[HB];
+    // every operand in flight together: one wait on memory per block
+    double a[KS], b[2][KS];                          // g[r0 + lr][4ks + lk], (-M^{-1})[4ks + lk][c]
+    {
+        const int row = r0 + lr;
 #pragma unroll
-    for (int u = 0; u < HB; ++u) {
-        const int e = u * 256 + tid;
-        hv[u] = e < tot2 ? hm2[e] : double2{0.0, 0.0};
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k = 4 * ks + lk;
+            a[ks] = (row < In && k < RR) ? (double)g[(int64_t)row * RR + k] : 0.0;
+        }
     }
-    double gold[2], aold[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int e = tid + 256 * h;
-        gold[h] = e < ne ? (double)G[base + e] : 0.0;
-        aold[h] = (e < ne && rule.kind == 1) ? (double)A[base + e] : 0.0;
+    for (int u = 0; u < 2; ++u) {
+        const int c = 16 * (w + 4 * u) + lr;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k = 4 * ks + lk;
+            b[u][ks] = (k < RR && c < RR) ? hm[(int64_t)k * RR + c] : 0.0;
+        }
     }
-    TC acc[2] = {TC(0), TC(0)};
-    for (int gi = 0; gi < groups; gi += GB) {
-        TC v[2][GB];
+    double gold[2][4], aold[2][4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + 256 * h;
-            const TC* q = gsrc + (int64_t)gi * gstride + base + (e < ne ? e : 0);   // walks the slices
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int u = 0; u < GB; ++u) {
-                v[h][u] = (e < ne && gi + u < groups) ? *q : TC(0);
-                q += gstride;
-            }
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + 4 * j + lk, c = 16 * (w + 4 * u) + lr;
+            const bool in = r < In && c < RR;
+            gold[u][j] = in ? (double)G[(int64_t)r * RR + c] : 0.0;
+            aold[u][j] = (in && rule.kind == 1) ? (double)A[(int64_t)r * RR + c] : 0.0;
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+    for (int u = 0; u < 2; ++u) {
+        const int nt = w + 4 * u;
+        const int c = 16 * nt + lr;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int u = 0; u < GB; ++u)
-                if (gi + u < groups) acc[h] += v[h][u];   // group order
-    }
-    double2* sH2 = reinterpret_cast<double2*>(sH);
+        for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[u][ks], acc, 0, 0, 0);
+        if (fl != 2 && nt < NTc) {   // fl == 2: not positive definite even with damping, core unchanged
 #pragma unroll
-    for (int u = 0; u < HB; ++u) {
-        const int e = u * 256 + tid;
-        if (e < tot2) sH2[e] = hv[u];
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int e = tid + 256 * h;
-        if (e < ne) sG[e] = (double)acc[h];
-    }
-    __syncthreads();
-    if (fl != 2) {   // not positive definite even with damping: core unchanged
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + 256 * h;
-            if (e < ne) {
-                const int r = e / RR, c = e - r * RR;
-                const double* gr = sG + r * RR;
-                double s[4] = {0.0, 0.0, 0.0, 0.0};
-                int k = 0;
-                for (; k + 4 <= RR; k += 4) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) s[j] += gr[k + j] * sH[(k + j) * RR + c];
-                }
-                for (; k < RR; ++k) s[0] += gr[k] * sH[k * RR + c];
-                apply_rule_loaded<TC>(G, A, base + e, gold[h], aold[h], (s[0] + s[1]) + (s[2] + s[3]), rule, t,
-                                      status);
+            for (int j = 0; j < 4; ++j) {
+                const int r = r0 + 4 * j + lk;
+                if (r < In && c < RR)
+                    apply_rule_loaded<TC>(G, A, (int64_t)r * RR + c, gold[u][j], aold[u][j], acc[j], rule, t, status);
             }
         }
     }
@@ -453,35 +427,30 @@ hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* gsrc, int groups, int64_t gstride,
-                              LossParts lp, double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
-                              void* ws, const UpdWs& L, StepBump step, hipStream_t st) {
+hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossParts lp, double* loss, MutPtrs cores,
+                              MutPtrs accum, tr_step rule, int32_t* status, void* ws, const UpdWs& L, StepBump step,
+                              hipStream_t st) {
     const Shape sh = shape_of(d);
     if (sh.maxRR > 128) return hipErrorInvalidValue;
     char* w = static_cast<char*>(ws);
     const double* hm = reinterpret_cast<const double*>(w + L.L_off);
     const int* flag = reinterpret_cast<const int*>(w + L.flag_off);
-    const size_t shm = ((size_t)sh.maxRR * sh.maxRR + (size_t)kApplyRows * sh.maxRR) * 8;
     const dim3 grid((sh.maxI + kApplyRows - 1) / kApplyRows);
-    if (d.core_dtype == TR_F64) {
-        if (!allow_lds(reinterpret_cast<const void*>(&k_scaled_apply<double>), shm)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_scaled_apply<double>, grid, dim3(256), shm, st, d, ms, static_cast<const double*>(gsrc),
-                           groups, gstride, lp, loss, hm, flag, cores, accum, rule, status, step);
-    } else {
-        if (!allow_lds(reinterpret_cast<const void*>(&k_scaled_apply<float>), shm)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_scaled_apply<float>, grid, dim3(256), shm, st, d, ms, static_cast<const float*>(gsrc),
-                           groups, gstride, lp, loss, hm, flag, cores, accum, rule, status, step);
-    }
+    if (d.core_dtype == TR_F64)
+        hipLaunchKernelGGL(k_scaled_apply<double>, grid, dim3(256), 0, st, d, ms, static_cast<const double*>(g), lp,
+                           loss, hm, flag, cores, accum, rule, status, step);
+    else
+        hipLaunchKernelGGL(k_scaled_apply<float>, grid, dim3(256), 0, st, d, ms, static_cast<const float*>(g), lp,
+                           loss, hm, flag, cores, accum, rule, status, step);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* gsrc,
-                               int groups, int64_t gstride, LossParts lp, double* loss, MutPtrs cores, MutPtrs accum,
-                               tr_step rule, int32_t* status, void* ws, const UpdWs& L, StepBump step,
-                               hipStream_t st) {
+hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* g,
+                               double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status, void* ws,
+                               const UpdWs& L, StepBump step, hipStream_t st) {
     hipError_t e = launch_sweep_inverse(d, ms, gram, damping, L, ws, status, st);
     if (e != hipSuccess) return e;
-    return launch_sweep_apply(d, ms, gsrc, groups, gstride, lp, loss, cores, accum, rule, status, ws, L, step, st);
+    return launch_sweep_apply(d, ms, g, LossParts{}, loss, cores, accum, rule, status, ws, L, step, st);
 }
 
 }  // namespace trk

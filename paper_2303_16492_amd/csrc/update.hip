@@ -347,8 +347,8 @@ hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram
                                 MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status, void* ws,
                                 const UpdWs& L, hipStream_t st) {
     if (sweep_supported(d))
-        return launch_sweep_update(d, ms, gram, damping, g, 1, 0, LossParts{}, nullptr, cores, accum, rule, status,
-                                   ws, L, StepBump{}, st);
+        return launch_sweep_update(d, ms, gram, damping, g, nullptr, cores, accum, rule, status, ws, L, StepBump{},
+                                   st);
     const Shape sh = shape_of(d);
     char* w = static_cast<char*>(ws);
     double* Lm = reinterpret_cast<double*>(w + L.L_off);
