@@ -35,7 +35,8 @@ struct BatchLds {
     static constexpr size_t t_off = s_off + (size_t)CH * SP * 2;
     static constexpr size_t e_off = t_off + (size_t)kBatchMaxRR * TP * 2;
     static constexpr size_t c_off = e_off + (size_t)kBatchMaxI * TP * 2;     // staged slices (FP32)
-    static constexpr size_t a_off = c_off + (size_t)kBatchSliceFloats * 4;   // G_n rows (FP16), pitch SP
+    static constexpr size_t m_off = c_off + (size_t)kBatchSliceFloats * 4;   // per-wavefront 16 x 16 product tile
+    static constexpr size_t a_off = m_off + (size_t)16 * 256 * 4;           // G_n rows (FP16), pitch SP
     static constexpr size_t i_off = a_off + (size_t)kBatchMaxI * SP * 2;     // sample indices [CH][8]
     static constexpr size_t w_off = i_off + (size_t)CH * kMaxOrder * 4;      // weights [CH] float
     static constexpr size_t o_off = w_off + (size_t)CH * 4;                  // fiber offsets [CH] int64
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
     _Float16* sE = reinterpret_cast<_Float16*>(smem_raw + Lz::e_off);
     float* sC = reinterpret_cast<float*>(smem_raw + Lz::c_off);
     _Float16* sA = reinterpret_cast<_Float16*>(smem_raw + Lz::a_off);
+    float* sM = reinterpret_cast<float*>(smem_raw + Lz::m_off);
     int* sidx = reinterpret_cast<int*>(smem_raw + Lz::i_off);
     float* sw = reinterpret_cast<float*>(smem_raw + Lz::w_off);
     int64_t* soff = reinterpret_cast<int64_t*>(smem_raw + Lz::o_off);
@@ -178,33 +180,52 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
                     }
                 }
                 __syncthreads();
-                for (int w = tid; w < gn * Rn1; w += NT) {
-                    const int fl = w / Rn1, s = w - fl * Rn1;
+                // chain products on FP32 matrix cores, one wavefront per
+                // sample: M_q = M_{q-1} A_q as a 16 x 16 (zero-padded) tile,
+                // K = 12 in three steps of 4; M_q goes back through this
+                // wavefront's LDS tile to become the next A operand.
+                float* Mw = sM + wv * 256;   // 16 x 16, row-major
+                for (int fl = wv; fl < gn; fl += WAVES) {
                     const float* base = sC + (size_t)fl * (N - 1) * PS;
-                    float row[kBatchRank];
-#pragma unroll
-                    for (int c = 0; c < kBatchRank; ++c) row[c] = base[s + kBatchRank * c];
+                    f32x4b m = {0.f, 0.f, 0.f, 0.f};
                     for (int q = 1; q < N - 1; ++q) {
-                        const float4* A4 = reinterpret_cast<const float4*>(base + q * PS);
-                        float nr[kBatchRank];
+                        const float* Aq = base + q * PS;
+                        f32x4b acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                        for (int c = 0; c < kBatchRank; ++c) {
-                            const float4 a0 = A4[3 * c], a1 = A4[3 * c + 1], a2 = A4[3 * c + 2];
-                            nr[c] = row[0] * a0.x + row[1] * a0.y + row[2] * a0.z + row[3] * a0.w +
-                                    row[4] * a1.x + row[5] * a1.y + row[6] * a1.z + row[7] * a1.w +
-                                    row[8] * a2.x + row[9] * a2.y + row[10] * a2.z + row[11] * a2.w;
+                        for (int ks = 0; ks < 3; ++ks) {
+                            const int kk = 4 * ks + lk;   // K index of this lane
+                            float a;
+                            if (q == 1) a = lr < kBatchRank ? base[lr + kBatchRank * kk] : 0.f;   // slice 0 (row lr)
+                            else a = Mw[lr * 16 + kk];
+                            const float b = lr < kBatchRank ? Aq[kk + kBatchRank * lr] : 0.f;
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
                         }
+                        m = acc;
+                        if (q + 1 < N - 1) {   // D rows 4 lk + j, column lr
+                            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                        for (int c = 0; c < kBatchRank; ++c) row[c] = nr[c];
+                            for (int j = 0; j < 4; ++j) Mw[(4 * lk + j) * 16 + lr] = m[j];
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_s_waitcnt(0xc07f);
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        }
                     }
                     const int f = g0 + fl;
+                    if (N == 2) {   // M_f is slice 0
 #pragma unroll
-                    for (int r = 0; r < kBatchRank; ++r)
-                        if (r < Rn) {
-                            const _Float16 h = (_Float16)(f < nb ? row[r] : 0.f);
-                            sS[f * Lz::SP + r + Rn * s] = h;
-                            sT[(r + Rn * s) * Lz::TP + f] = h;
+                        for (int j = 0; j < 4; ++j) m[j] = (4 * lk + j < kBatchRank && lr < kBatchRank)
+                                                               ? base[(4 * lk + j) + kBatchRank * lr] : 0.f;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int srow = 4 * lk + j, r = lr;   // M_f(srow, r) -> S(f, r + R_n srow)
+                        if (srow < Rn1 && r < Rn) {
+                            const _Float16 h = (_Float16)(f < nb ? m[j] : 0.f);
+                            sS[f * Lz::SP + r + Rn * srow] = h;
+                            sT[(r + Rn * srow) * Lz::TP + f] = h;
                         }
+                    }
                 }
                 __syncthreads();   // slices consumed before the next group overwrites them
             }

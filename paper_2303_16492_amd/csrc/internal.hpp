@@ -64,8 +64,12 @@ __device__ inline double loss_parts_sum(const LossParts& lp, int In, double* red
 }
 
 // Step-counter advance folded into the last kernel of a step: every block
-// counts itself in ``ctr`` once it is done (and so has read the counter);
-// the last one resets ``ctr`` and adds 1 to ``t``.  Disabled when t is null.
+// counts itself in ``ctr`` once it is done; the last one resets ``ctr`` and
+// adds 1 to ``t``.  No fence is needed: a block's read of t has completed
+// before its count (its addresses depend on the mode drawn from t), the
+// counter and t change only through device-scope atomics, and the kernels
+// that read t next start after this kernel has ended.  (An agent-scope fence
+// here would write back the L2 once per block.)  Disabled when t is null.
 struct StepBump {
     uint64_t* t;
     unsigned* ctr;
@@ -74,12 +78,10 @@ __device__ inline void bump_if_last(const StepBump& b) {
     if (!b.t) return;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
         if (atomicAdd(b.ctr, 1u) == nb - 1) {
             atomicExch(b.ctr, 0u);
             atomicAdd(reinterpret_cast<unsigned long long*>(b.t), 1ull);
-            __threadfence();
         }
     }
 }
