@@ -182,23 +182,26 @@ def measured_traffic(kernel):
     return None
 
 
-def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup):
-    """K timed steps of the scaled method in precision ``prec`` from the
-    initial cores; per-launch HIP events around the gradient and the
-    inverse kernels."""
+def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup, G=50, E=200):
+    """The scaled method in precision ``prec`` from the initial cores:
+    (1) E eager steps with HIP events recorded around the gradient and the
+    inverse kernel of every step, on the streams they run on (per-launch
+    kernel durations); (2) K timed steps replayed from a HIP graph of G
+    steps (K / G replays), whose rate is the result."""
     import torch
     from paper_2303_16492_amd import _lib as L
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
     N = 3
+    assert K % G == 0, "--steps must be a multiple of the graph length (50)"
     cores = cores_to_device(init3, torch.float32, dev)
     solver = TRSolver(cores, X, [I] * N, [R] * N, m, law="U", scaled=True, prec=prec,
                       rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
                       overlap=not args.no_overlap)
     solver.run(warmup)
     torch.cuda.synchronize()
-    hip, evs = hip_events(4 * K + 2)
-    arr = lambda j: (C.c_void_p * K)(*[e.value for e in evs[2 + j * K:2 + (j + 1) * K]])
+    hip, evs = hip_events(4 * E + 2)
+    arr = lambda j: (C.c_void_p * E)(*[e.value for e in evs[2 + j * E:2 + (j + 1) * E]])
     gb, ge, ib, ie = arr(0), arr(1), arr(2), arr(3)
     opts = L.tr_run_opts()
     if solver.opts is not None:
@@ -207,24 +210,36 @@ def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup):
     P = lambda a: C.cast(a, C.POINTER(C.c_void_p))
     opts.ev_begin, opts.ev_end, opts.ev_inv_begin, opts.ev_inv_end = P(gb), P(ge), P(ib), P(ie)
     stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
     assert hip.hipEventRecord(evs[0], C.c_void_p(stream.cuda_stream)) == 0
     rc = api.lib().tr_run_ex(C.byref(solver.problem), C.byref(solver.config), C.c_void_p(solver.t_dev.data_ptr()),
-                             K, None, C.c_void_p(solver.status.data_ptr()), C.c_void_p(solver.ws.data_ptr()),
+                             E, None, C.c_void_p(solver.status.data_ptr()), C.c_void_p(solver.ws.data_ptr()),
                              solver.ws.numel(), C.c_void_p(stream.cuda_stream), C.byref(opts))
     assert rc == 0, rc
     assert hip.hipEventRecord(evs[1], C.c_void_p(stream.cuda_stream)) == 0
     torch.cuda.synchronize()
-    total_ms = elapsed_ms(hip, evs[0], evs[1])
-    grad_us = 1e3 * float(np.mean([elapsed_ms(hip, gb[i], ge[i]) for i in range(K)]))
-    inv_us = (1e3 * float(np.mean([elapsed_ms(hip, ib[i], ie[i]) for i in range(K)]))
+    eager_ms = elapsed_ms(hip, evs[0], evs[1]) / E
+    grad_us = 1e3 * float(np.mean([elapsed_ms(hip, gb[i], ge[i]) for i in range(E)]))
+    inv_us = (1e3 * float(np.mean([elapsed_ms(hip, ib[i], ie[i]) for i in range(E)]))
               if solver.opts is not None else None)
+    graph = solver.capture(G)               # one eager warm-up step, then the capture
+    graph.replay()                          # warm-up replay
+    torch.cuda.synchronize()
+    t_before = solver.t
+    assert hip.hipEventRecord(evs[0], C.c_void_p(stream.cuda_stream)) == 0
+    for _ in range(K // G):
+        graph.replay()
+    assert hip.hipEventRecord(evs[1], C.c_void_p(stream.cuda_stream)) == 0
+    torch.cuda.synchronize()
+    total_ms = elapsed_ms(hip, evs[0], evs[1])
+    assert solver.t - t_before == K
     rse = float(solver.rse())
     status = int(solver.status.item())
+    del graph
     for e in evs:
         hip.hipEventDestroy(e)
     del solver
-    return dict(ms_per_step=total_ms / K, grad_us=grad_us, inv_us=inv_us, rse_after=rse, dev_status=status)
+    return dict(ms_per_step=total_ms / K, eager_ms_per_step=eager_ms, grad_us=grad_us, inv_us=inv_us, rse_after=rse,
+                dev_status=status)
 
 
 def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100):
@@ -373,6 +388,10 @@ def main():
                   other: {"steps_per_s": round(1e3 / alt["ms_per_step"], 2), "rse_after": alt["rse_after"],
                           "gradient_us": round(alt["grad_us"], 3),
                           "inverse_us": None if alt["inv_us"] is None else round(alt["inv_us"], 3)}},
+        "timing": "value: K steps replayed from a captured HIP graph of 50 steps (the Gram/inverse branch forks "
+                  "and joins as graph edges); kernel durations: HIP events around every launch of the inverse and "
+                  "gradient kernels over 200 eager steps of the same run, on the streams they run on",
+        "eager_steps_per_s": round(1e3 / main["eager_ms_per_step"], 2),
         "time_to_target": ttt,
         "batched": batched,
         "rse_after": main["rse_after"],
