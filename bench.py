@@ -75,13 +75,18 @@ def elapsed_ms(hip, a, b):
     return float(out.value)
 
 
-def build_problem(seed, I, R, kappa, dev):
+def build_problem(seed, I, R, kappa, dev, kind="illcond"):
+    """Planted 3-way ring at RMS 1 and the initial cores.  kind "illcond":
+    each core's mode-2 unfolding U_n S V^T with singular values geometric
+    from 1 to 1/kappa (second synthetic experiment); kind "gaussian":
+    i.i.d. N(0, 1) cores (first synthetic experiment)."""
     import torch
     import tr_inputs as ti
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import cores_to_device
     N = 3
-    true3 = ti.illcond_cores(seed, N, I, R, kappa)
+    true3 = (ti.illcond_cores(seed, N, I, R, kappa) if kind == "illcond"
+             else ti.gaussian_cores(seed, N, I, R))
     desc = api.make_desc([I] * N, [R] * N, torch.float32)
     tcores = cores_to_device(true3, torch.float32, dev)
     X = api.tr_reconstruct(desc, tcores)
@@ -242,10 +247,10 @@ def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup, G=50, E=200):
                 dev_status=status)
 
 
-def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100):
+def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, cap=None):
     """Wall time from the initial cores until an RSE check reaches
     ``target`` (checks every ``every`` steps count toward the time), capped
-    at args.ttt_steps steps."""
+    at ``cap`` (default args.ttt_steps) steps."""
     import torch
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
@@ -256,8 +261,9 @@ def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100):
     solver.rse()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    cap = args.ttt_steps if cap is None else cap
     steps, rse, hist = 0, float("nan"), []
-    while steps < args.ttt_steps:
+    while steps < cap:
         solver.run(every)
         steps += every
         rse = float(solver.rse())          # synchronises
@@ -270,6 +276,26 @@ def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100):
             "seconds": round(wall, 4) if rse <= target else None, "steps": steps,
             "rse_at_stop": rse, "wall_s_at_stop": round(wall, 4), "rse_every": every,
             "rse_trace": [[s_, float(f"{r_:.4e}")] for s_, r_ in hist[:: max(1, len(hist) // 10)]]}
+
+
+def relerr_timing(desc, cores, X, reps=20):
+    """Mean duration of one RSE evaluation (pack + matrix-core
+    reconstruction against X + fixed-order finish) over ``reps`` calls on
+    the current stream, bracketed by HIP events."""
+    import torch
+    from paper_2303_16492_amd import _lib as L
+    from paper_2303_16492_amd import api
+    ws = api.workspace(L.lib().tr_relerr_workspace_size(C.byref(desc)), X.device)
+    out = torch.zeros(1, dtype=torch.float64, device=X.device)
+    api.tr_relerr(desc, cores, X, rse=out, ws=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        api.tr_relerr(desc, cores, X, rse=out, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps * 1e3, float(out.item())
 
 
 def main():
@@ -308,6 +334,32 @@ def main():
             ttt.append(time_to_target(args, pr, init3, X, I, R, m, dev))
             print(f"[bench] time-to-target {pr}: {ttt[-1]['reached']} after {ttt[-1]['steps']} steps, "
                   f"rse {ttt[-1]['rse_at_stop']:.3e}", file=sys.stderr, flush=True)
+
+    # a9 on its own: one RSE evaluation at 400^3 (X read once, 2 I^3 R^2 FLOP)
+    from paper_2303_16492_amd.driver import cores_to_device
+    rcores = cores_to_device(init3, torch.float32, dev)
+    rse_us, _ = relerr_timing(desc, rcores, X)
+    rflops = 2.0 * I ** 3 * R * R
+    rbytes = 4.0 * I ** 3
+    relerr = {"kernel": "k_recon_mfma (+ k_recon_pack, k_recon_finish)", "us_per_rse": round(rse_us, 2),
+              "flops": rflops, "bytes": rbytes,
+              "mfma_tflops": round(rflops / (rse_us * 1e-6) / 1e12, 2),
+              "mfma_frac": round(rflops / (rse_us * 1e-6) / 1e12 / PEAK["f32"][0], 4),
+              "hbm_gbs": round(rbytes / (rse_us * 1e-6) / 1e9, 1),
+              "hbm_frac": round(rbytes / (rse_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    del rcores
+    print(f"[bench] relerr: {rse_us:.1f} us per RSE", file=sys.stderr, flush=True)
+    planted = []
+    if args.ttt_steps > 0:
+        # The same method on a planted ring with Gaussian cores at the same
+        # size, where the 1e-4 target is within reach of both forms.
+        pdesc, PX, _, pinit = build_problem(args.seed, I, R, kappa, dev, kind="gaussian")
+        for pr in ("f32", "bf16"):
+            planted.append(time_to_target(args, pr, pinit, PX, I, R, m, dev, every=10, cap=1000))
+            print(f"[bench] planted time-to-target {pr}: {planted[-1]['reached']} after {planted[-1]['steps']} "
+                  f"steps, {planted[-1]['wall_s_at_stop']} s, rse {planted[-1]['rse_at_stop']:.3e}",
+                  file=sys.stderr, flush=True)
+        del PX
 
     RR = R * R
     flops = 4.0 * I * m * RR                       # prediction + gradient contractions
@@ -393,6 +445,9 @@ def main():
                   "gradient kernels over 200 eager steps of the same run, on the streams they run on",
         "eager_steps_per_s": round(1e3 / main["eager_ms_per_step"], 2),
         "time_to_target": ttt,
+        "time_to_target_planted": {"workload": "planted-gaussian-n3-i400-r10", "m": m, "law": "uniform",
+                                   "alpha": args.alpha, "runs": planted},
+        "relerr": relerr,
         "batched": batched,
         "rse_after": main["rse_after"],
         "dev_status": main["dev_status"],

@@ -1,13 +1,21 @@
 // a9: full reconstruction X_hat_[1] = G_{1(2)} (G^{!=1}_[2])^T and the RSE of
 // Section 4, ||X_hat - X_true||_F / ||X_true||_F, with FP64 sums.
 //
-// A block owns TJ columns j of X_[1] (paper order: column j is the
-// multi-index of (i_2..i_N), first fastest).  It builds their subchain rows
-// s_j in LDS (chain products, one thread per (column, row of M_j)), then
-// every thread takes rows i_1 = tid, tid + 256, ... and forms the TJ dot
-// products G_{1(2)}(i_1, :) . s_j with G streamed through registers and s_j
-// broadcast from LDS.  X_true is read once, coalesced along i_1.  Per-block
-// FP64 partial sums are added in a fixed order by a second kernel.
+// FP32 cores with R_1 R_2 <= 128 take the matrix-core kernel k_recon_mfma:
+// a block owns 128 columns j of X_[1] (paper order: column j is the
+// multi-index of (i_2..i_N), first fastest), 32 per wavefront.  The block
+// builds their subchain rows s_j in LDS (chain products of lateral slices),
+// each wavefront keeps its 32 rows as the A operand of
+// v_mfma_f32_32x32x2_f32 in registers for the whole kernel, and sweeps the
+// rows i_1 of G_{1(2)} in tiles of 32: the B operand comes pre-packed in
+// lane order (one coalesced 256-byte load per instruction), the 32 x 32
+// result tile is compared with X_true as it leaves the accumulators (each
+// half-wavefront reads 32 consecutive i_1 of one column, 128 bytes), and
+// X_hat is never stored.  X_true is read exactly once.
+//
+// Other cases (FP64, larger ranks) take k_recon: every thread takes rows
+// i_1 = tid, tid + 256, ... and forms TJ dot products with s_j broadcast
+// from LDS.  Per-block FP64 partial sums are added in a fixed order.
 #include "internal.hpp"
 
 namespace trk {
@@ -121,18 +129,232 @@ __global__ __launch_bounds__(256) void k_recon(tr_desc d, Ptrs cores, const TX* 
     (void)want_xx;
 }
 
-__global__ void k_recon_finish(const double* __restrict__ part, int64_t nblocks, double xnorm2, double* rse,
-                               double* sums) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Fixed-order sum of the per-block partials: strided per thread, then the
+// block tree (deterministic for a given block count).
+__global__ __launch_bounds__(256) void k_recon_finish(const double* __restrict__ part, int64_t nblocks,
+                                                      double xnorm2, double* rse, double* sums) {
+    __shared__ double red[4];
     double e = 0.0, q = 0.0;
-    for (int64_t b = 0; b < nblocks; ++b) {
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
         e += part[2 * b];
         q += part[2 * b + 1];
     }
+    e = block_sum(e, red);
+    q = block_sum(q, red);
+    if (threadIdx.x != 0) return;
     if (xnorm2 >= 0.0) q = xnorm2;
     sums[0] = e;
     sums[1] = q;
     *rse = sqrt(e) / sqrt(q);
+}
+
+// ------------------------------------------------------ matrix-core path --
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kRmWaves = 4;                 // wavefronts per block
+constexpr int kRmCols = 32 * kRmWaves;      // columns j per block
+
+// K steps of two (the B operand's per-lane count) for a given R_1 R_2.
+static int recon_kt(int RR) {
+    if (RR <= 16) return 8;
+    if (RR <= 32) return 16;
+    if (RR <= 64) return 32;
+    if (RR <= 100) return 50;
+    if (RR <= 128) return 64;
+    return 0;
+}
+
+static bool recon_mfma_ok(const tr_desc& d) {
+    return d.core_dtype == TR_F32 && (d.x_dtype == TR_F32 || d.x_dtype == TR_F16) &&
+           recon_kt(d.R[0] * d.R[1 % d.N]) > 0;
+}
+
+// G_{1(2)} in the lane order of the B operand of v_mfma_f32_32x32x2_f32:
+// Gpk[(it KT + q) 64 + l] = G(32 it + l % 32, 2 q + l / 32), zero outside.
+__global__ __launch_bounds__(256) void k_recon_pack(tr_desc d, const float* __restrict__ G0, int KT,
+                                                    float* __restrict__ Gpk) {
+    const int I0 = d.I[0], RR = d.R[0] * d.R[1 % d.N];
+    const int nti = (I0 + 31) / 32;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nti * KT * 64) return;
+    const int l = (int)(e & 63);
+    const int64_t u = e >> 6;
+    const int q = (int)(u % KT), it = (int)(u / KT);
+    const int i = 32 * it + (l & 31), k = 2 * q + (l >> 5);
+    Gpk[e] = (i < I0 && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
+}
+
+// MODE 0: per-block sums of (X_hat - X_true)^2 and X_true^2 into part;
+// MODE 1: X_hat written to Xo.  Gpk null: B operand read from G_{1(2)}
+// directly (uncoalesced; used by the one-off reconstruction).
+template <typename TX, int KT, int MODE>
+__global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const float* __restrict__ Gpk,
+                                                    const TX* __restrict__ Xt, TX* __restrict__ Xo,
+                                                    double* __restrict__ part) {
+    constexpr int SP = 2 * KT + 1;          // LDS row pitch of the subchain rows
+    const int N = d.N;
+    const int I0 = d.I[0];
+    const int R0 = d.R[0], R1 = d.R[1 % N];
+    const int RR = R0 * R1;
+    int64_t J = 1;
+    for (int k = 1; k < N; ++k) J *= d.I[k];
+    const int64_t j0 = (int64_t)blockIdx.x * kRmCols;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int64_t* sOff = reinterpret_cast<int64_t*>(smem_raw);          // [kRmCols], -1 past J
+    float* sS = reinterpret_cast<float*>(sOff + kRmCols);          // [kRmCols][SP]
+    const int tid = threadIdx.x;
+    // subchain rows of the block's columns: thread item (column, row s of M_j)
+    for (int e = tid; e < kRmCols * R1; e += blockDim.x) {
+        const int jj = e / R1, s = e - jj * R1;
+        const int64_t j = j0 + jj;
+        float* out = sS + jj * SP + R0 * s;
+        if (j >= J) {
+            for (int r = 0; r < R0; ++r) out[r] = 0.f;
+            if (s == 0) sOff[jj] = -1;
+            continue;
+        }
+        int ik[kMaxOrder];
+        int64_t rem = j, off = 0;
+        for (int k = 1; k < N; ++k) {
+            ik[k] = (int)(rem % d.I[k]);
+            rem /= d.I[k];
+            off += (int64_t)ik[k] * d.x_stride[k];
+        }
+        if (s == 0) sOff[jj] = off;
+        float v[kMaxRank];
+        {
+            const int Rk = d.R[1 % N], Rk1 = d.R[ring_next(1 % N, N)];
+            const float* A = static_cast<const float*>(cores.p[1 % N]) + (int64_t)ik[1] * Rk * Rk1;
+#pragma unroll
+            for (int c = 0; c < kMaxRank; ++c) v[c] = c < Rk1 ? A[s + Rk * c] : 0.f;
+        }
+        for (int k = 2; k < N; ++k) {
+            const int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
+            const float* A = static_cast<const float*>(cores.p[k]) + (int64_t)ik[k] * Rk * Rk1;
+            float w[kMaxRank];
+#pragma unroll
+            for (int c = 0; c < kMaxRank; ++c) {
+                float acc = 0.f;
+                if (c < Rk1) {
+#pragma unroll
+                    for (int r = 0; r < kMaxRank; ++r)
+                        if (r < Rk) acc += v[r] * A[r + Rk * c];
+                }
+                w[c] = acc;
+            }
+#pragma unroll
+            for (int c = 0; c < kMaxRank; ++c) v[c] = w[c];
+        }
+        for (int r = 0; r < R0; ++r) out[r] = v[r];
+    }
+    for (int e = tid; e < kRmCols * (2 * KT - RR); e += blockDim.x) {   // K padding
+        const int jj = e / (2 * KT - RR);
+        sS[jj * SP + RR + (e - jj * (2 * KT - RR))] = 0.f;
+    }
+    __syncthreads();
+
+    const int w = tid >> 6, l = tid & 63, lc = l & 31, lh = l >> 5;
+    // A operand: row 32 w + lc of the block's subchain rows, k = 2 q + lh
+    // (read from LDS at each instruction).  Result row r of this lane is
+    // column 32 w + 8 (r / 4) + 4 lh + r % 4, result column is i_1 = 32 it + lc.
+    const float* arow = sS + (32 * w + lc) * SP + lh;
+    const int64_t* offw = sOff + 32 * w + 4 * lh;
+    const float* G0 = static_cast<const float*>(cores.p[0]);
+    const int64_t xs0 = d.x_stride[0];
+    const int nti = (I0 + 31) / 32;
+    double err = 0.0, xx = 0.0;
+    for (int it = 0; it < nti; ++it) {
+        const int i = 32 * it + lc;
+        const bool iok = i < I0;
+        float b[KT];
+        if (Gpk) {
+            const float* src = Gpk + (int64_t)it * KT * 64 + l;
+#pragma unroll
+            for (int q = 0; q < KT; ++q) b[q] = src[q * 64];
+        } else {
+#pragma unroll
+            for (int q = 0; q < KT; ++q) {
+                const int k = 2 * q + lh;
+                b[q] = (iok && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
+            }
+        }
+        float x[16];
+        if (MODE == 0) {   // issued before the matrix work, consumed after it
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t o = offw[8 * (r >> 2) + (r & 3)];
+                x[r] = (iok && o >= 0) ? Cvt<TX>::to_f32(Xt[o + (int64_t)i * xs0]) : 0.f;
+            }
+        }
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+        for (int q = 0; q < KT; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[2 * q], b[q], acc, 0, 0, 0);
+        if (iok) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t o = offw[8 * (r >> 2) + (r & 3)];
+                if (o < 0) continue;
+                if (MODE == 0) {
+                    const double xd = (double)x[r];
+                    const double df = (double)acc[r] - xd;
+                    err += df * df;
+                    xx += xd * xd;
+                } else {
+                    Xo[o + (int64_t)i * xs0] = from_f64<TX>((double)acc[r]);
+                }
+            }
+        }
+    }
+    if (MODE == 0) {
+        __shared__ double red[4];
+        const double e = block_sum(err, red);
+        const double q = block_sum(xx, red);
+        if (tid == 0) {
+            part[2 * (int64_t)blockIdx.x] = e;
+            part[2 * (int64_t)blockIdx.x + 1] = q;
+        }
+    }
+}
+
+static size_t recon_mfma_shm(int KT) { return (size_t)kRmCols * 8 + (size_t)kRmCols * (2 * KT + 1) * 4; }
+
+static int64_t recon_mfma_blocks(const tr_desc& d) {
+    int64_t J = 1;
+    for (int k = 1; k < d.N; ++k) J *= d.I[k];
+    return (J + kRmCols - 1) / kRmCols;
+}
+
+static size_t recon_pack_bytes(const tr_desc& d) {
+    const int KT = recon_kt(d.R[0] * d.R[1 % d.N]);
+    return (size_t)((d.I[0] + 31) / 32) * KT * 64 * 4;
+}
+
+template <int MODE, typename TX>
+static hipError_t launch_recon_mfma_t(const tr_desc& d, Ptrs cores, const float* Gpk, const TX* Xt, TX* Xo,
+                                      double* part, hipStream_t st) {
+    const int KT = recon_kt(d.R[0] * d.R[1 % d.N]);
+    const dim3 grid((unsigned)recon_mfma_blocks(d)), block(256);
+    const size_t shm = recon_mfma_shm(KT);
+#define TRK_RM(KTV)                                                                                      \
+    case KTV:                                                                                            \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_recon_mfma<TX, KTV, MODE>), shm))               \
+            return hipErrorInvalidConfiguration;                                                         \
+        hipLaunchKernelGGL((k_recon_mfma<TX, KTV, MODE>), grid, block, shm, st, d, cores, Gpk, Xt, Xo, part); \
+        break;
+    switch (KT) {
+        TRK_RM(8)
+        TRK_RM(16)
+        TRK_RM(32)
+        TRK_RM(50)
+        TRK_RM(64)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef TRK_RM
+    return hipGetLastError();
 }
 
 static size_t recon_shm(const tr_desc& d, size_t es) {
@@ -147,14 +369,34 @@ static int64_t recon_blocks(const tr_desc& d) {
     return (J + kReconTJ - 1) / kReconTJ;
 }
 
-size_t relerr_ws_bytes(const tr_desc& d) { return align_up(16) + align_up((size_t)recon_blocks(d) * 16); }
+size_t relerr_ws_bytes(const tr_desc& d) {
+    size_t b = align_up(16) + align_up((size_t)recon_blocks(d) * 16);
+    if (recon_mfma_ok(d)) b += align_up(recon_pack_bytes(d));
+    return b;
+}
 
 hipError_t launch_relerr(const tr_desc& d, Ptrs cores, const void* Xt, double xnorm2, double* rse, void* ws,
                          hipStream_t st) {
-    const int64_t nb = recon_blocks(d);
     char* w = static_cast<char*>(ws);
     double* sums = reinterpret_cast<double*>(w);
     double* part = reinterpret_cast<double*>(w + align_up(16));
+    if (recon_mfma_ok(d)) {
+        float* Gpk = reinterpret_cast<float*>(w + align_up(16) + align_up((size_t)recon_blocks(d) * 16));
+        const int KT = recon_kt(d.R[0] * d.R[1 % d.N]);
+        const int64_t np = (int64_t)((d.I[0] + 31) / 32) * KT * 64;
+        hipLaunchKernelGGL(k_recon_pack, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d,
+                           static_cast<const float*>(cores.p[0]), KT, Gpk);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = d.x_dtype == TR_F32
+                ? launch_recon_mfma_t<0>(d, cores, Gpk, static_cast<const float*>(Xt), (float*)nullptr, part, st)
+                : launch_recon_mfma_t<0>(d, cores, Gpk, static_cast<const __half*>(Xt), (__half*)nullptr, part, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_recon_finish, dim3(1), dim3(256), 0, st, part, recon_mfma_blocks(d), xnorm2, rse,
+                           sums);
+        return hipGetLastError();
+    }
+    const int64_t nb = recon_blocks(d);
     const dim3 grid((unsigned)nb);
     const bool f64 = d.core_dtype == TR_F64;
     const size_t shm = recon_shm(d, f64 ? 8 : 4);
@@ -171,11 +413,17 @@ hipError_t launch_relerr(const tr_desc& d, Ptrs cores, const void* Xt, double xn
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_recon_finish, dim3(1), dim3(64), 0, st, part, nb, xnorm2, rse, sums);
+    hipLaunchKernelGGL(k_recon_finish, dim3(1), dim3(256), 0, st, part, nb, xnorm2, rse, sums);
     return hipGetLastError();
 }
 
 hipError_t launch_reconstruct(const tr_desc& d, Ptrs cores, void* Xo, hipStream_t st) {
+    if (recon_mfma_ok(d)) {
+        return d.x_dtype == TR_F32
+                   ? launch_recon_mfma_t<1>(d, cores, nullptr, (const float*)nullptr, static_cast<float*>(Xo), nullptr, st)
+                   : launch_recon_mfma_t<1>(d, cores, nullptr, (const __half*)nullptr, static_cast<__half*>(Xo), nullptr,
+                                            st);
+    }
     const int64_t nb = recon_blocks(d);
     const dim3 grid((unsigned)nb);
     const bool f64 = d.core_dtype == TR_F64;

@@ -296,6 +296,28 @@ def test_relerr_and_reconstruct_parity(N, I, R, dtype):
     assert abs(rse2 - want) <= 10 * TOL[dtype] * want
 
 
+@pytest.mark.parametrize("xdt", [torch.float32, torch.float16])
+@pytest.mark.parametrize("N,I,R", [(3, [70, 9, 10], [8, 16, 8]), (3, [40, 30, 21], [6, 7, 5]),
+                                   (5, [33, 3, 4, 2, 5], [4, 3, 2, 5, 4]), (3, [1, 130, 1], [3, 4, 2])])
+def test_relerr_matrix_core_shapes(N, I, R, xdt):
+    """FP32 cores through the matrix-core reconstruction at every operand
+    width it has (R_1 R_2 = 128, 42, 16, 6), ragged row tiles (I_1 not a
+    multiple of 32), ragged column blocks (J not a multiple of 128), a single
+    row, and an FP16 target tensor (compared on its rounded values)."""
+    dtype = torch.float32
+    I, R, cores, X, dcores, dX = problem(11, N, I, R, dtype)
+    X = rounded(X, xdt)
+    dX = to_dev(flat_paper(X), xdt)
+    desc = api.make_desc(I, R, dtype, xdt)
+    say("relerr mfma", N, I, R, xdt)
+    rse = float(api.tr_relerr(desc, dcores, dX))
+    want = tr.rse(cores, X)
+    assert abs(rse - want) <= 10 * TOL[dtype] * want, (rse, want)
+    Xh = api.tr_reconstruct(desc, dcores)
+    ref = rounded(tr.full_tensor(cores), xdt)
+    assert rel(Xh.double().cpu().numpy(), flat_paper(ref)) < (TOL[dtype] if xdt == torch.float32 else 1e-3)
+
+
 def test_relerr_zero_at_truth_fp64():
     cores = [rounded(c, torch.float64) for c in ti.gaussian_cores(3, 3, [12, 10, 11], [3, 2, 4])]
     X = tr.full_tensor(cores)
