@@ -93,7 +93,7 @@ constexpr int kMaxM = 1 << 24;
 
 // Workspace plan of tr_run.
 struct RunWs {
-    size_t idx, pF, S, g, gram, idxH, pH, SH, grad, gramws, upd, dist, opt, loss, ctr, total;
+    size_t idx, pF, S, g, gram, idxH, pH, SH, grad, gramws, upd, dist, opt, loss, ctr, mode, total;
     GradWs gl;
     GramWs ml, mlH;
     UpdWs ul;
@@ -130,6 +130,7 @@ static RunWs run_layout(const tr_problem* p, const tr_config* c) {
     L.opt = take(c->law == TR_LAW_OPTIMAL ? dist_opt_ws_bytes(d) : 0);
     L.loss = take(8);
     L.ctr = take(4);
+    L.mode = take(4);
     L.total = o;
     return L;
 }
@@ -440,14 +441,25 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
         for (int k = 0; k < d.N && e == hipSuccess; ++k)
             e = launch_dist(d, ModeSrc{nullptr, 0, k, 0}, false, k, c->law, cores, p->cdf, dev_status,
                             w + L.dist, st);
+    // The Gram, its reduction and the inverse use the mode only for R_n R_{n+1}
+    // and J_n; when every mode has the same ones they take mode 0 and skip
+    // the dependent read of the step counter.
+    bool same_shape = true;
+    for (int k = 1; k < d.N; ++k)
+        same_shape = same_shape && d.R[k] * d.R[(k + 1) % d.N] == d.R[0] * d.R[1 % d.N] && d.I[k] == d.I[0];
+    // The step's first kernel draws its mode from (seed, t) and publishes it;
+    // the later kernels of the step read it instead of drawing it again.
+    int32_t* nslot = reinterpret_cast<int32_t*>(w + L.mode);
     for (int it = 0; it < steps && e == hipSuccess; ++it) {
-        const ModeSrc ms{t_dev, 0, -1, c->seed};
+        const ModeSrc ms_draw{t_dev, 0, -1, c->seed, nullptr, nslot};
+        const ModeSrc ms{t_dev, 0, -2, c->seed, nslot, nullptr};
+        const ModeSrc ms_shape = same_shape ? ModeSrc{nullptr, 0, 0, c->seed} : ms;
         double* loss = loss_out ? loss_out + it : lossw;
         if (c->law == TR_LAW_OPTIMAL)
-            e = launch_dist_optimal(d, ms, cores, xs_paper, p->cdf_J, dev_status, w + L.opt, st);
+            e = launch_dist_optimal(d, ms_draw, cores, xs_paper, p->cdf_J, dev_status, w + L.opt, st);
         if (e == hipSuccess)
-            e = launch_sample_subchain(d, ms, c->m, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr, TR_STREAM_IDX,
-                                       cores, idx, pF, S, true, true, st);
+            e = launch_sample_subchain(d, ms_draw, c->m, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr,
+                                       TR_STREAM_IDX, cores, idx, pF, S, true, true, st);
         // Scaled steps (RR <= 128) with a second stream: the Gram, its
         // reduction and the inverse need only the draws, so they run on
         // ``hs``; the gradient waits for the Gram's group sums (it is not
@@ -469,16 +481,17 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                     e = launch_sample_subchain(d, ms, c->m_H, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr,
                                                TR_STREAM_H, cores, idxH, pH, SH, true, true, hs);
                     if (e == hipSuccess)
-                        e = launch_gram(d, ms, SH, pH, c->m_H, gram, w + L.gramws, L.mlH, hs,
+                        e = launch_gram(d, ms_shape, SH, pH, c->m_H, gram, w + L.gramws, L.mlH, hs,
                                         fork ? (hipEvent_t)o.ev_gram : nullptr);
                 } else {
-                    e = launch_gram(d, ms, S, pF, c->m, gram, w + L.gramws, L.ml, hs,
+                    e = launch_gram(d, ms_shape, S, pF, c->m, gram, w + L.gramws, L.ml, hs,
                                     fork ? (hipEvent_t)o.ev_gram : nullptr);
                 }
             }
             if (e == hipSuccess && o.ev_inv_begin && o.ev_inv_begin[it])
                 e = hipEventRecord((hipEvent_t)o.ev_inv_begin[it], hs);
-            if (e == hipSuccess) e = launch_sweep_inverse(d, ms, gram, c->damping, L.ul, w + L.upd, dev_status, hs);
+            if (e == hipSuccess)
+                e = launch_sweep_inverse(d, ms_shape, gram, c->damping, L.ul, w + L.upd, dev_status, hs);
             if (e == hipSuccess && o.ev_inv_end && o.ev_inv_end[it]) e = hipEventRecord((hipEvent_t)o.ev_inv_end[it], hs);
             if (e == hipSuccess && fork) e = hipEventRecord((hipEvent_t)o.ev_join, hs);
             if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, (hipEvent_t)o.ev_gram, 0);

@@ -82,14 +82,18 @@ __device__ inline int cdf_pick(const uint64_t* __restrict__ cdf, int len, uint64
 struct ModeSrc {
     const uint64_t* t_dev;   // if non-null, t = *t_dev
     uint64_t t;
-    int32_t n;               // if < 0, n = pick_mode(seed, t, N)
+    int32_t n;               // >= 0: this mode; -1: pick_mode(seed, t, N); -2: *n_dev
     uint64_t seed;
+    const int32_t* n_dev;    // the mode of the step, published by its first kernel (n == -2)
+    int32_t* n_pub;          // n == -1: where the step's first kernel publishes the mode it drew
 };
 
+// The two loads (step counter, published mode) are independent, so a
+// kernel that needs both waits for one memory round trip.
 __device__ inline void resolve_mode(const ModeSrc& ms, int N, uint64_t* t, int* n) {
     const uint64_t tt = ms.t_dev ? *ms.t_dev : ms.t;
     *t = tt;
-    *n = ms.n >= 0 ? ms.n : pick_mode(ms.seed, tt, N);
+    *n = ms.n >= 0 ? ms.n : (ms.n == -2 ? *ms.n_dev : pick_mode(ms.seed, tt, N));
 }
 
 struct Ptrs {

@@ -222,26 +222,37 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
             off += (int64_t)ik[k] * d.x_stride[k];
         }
         if (s == 0) sOff[jj] = off;
+        // Loads are unconditional (indices clamped into the slice) so that a
+        // whole slice row or column is in flight at once; entries past the
+        // ranks are masked after the load.
         float v[kMaxRank];
         {
             const int Rk = d.R[1 % N], Rk1 = d.R[ring_next(1 % N, N)];
             const float* A = static_cast<const float*>(cores.p[1 % N]) + (int64_t)ik[1] * Rk * Rk1;
+            const int last = Rk * Rk1 - 1;
 #pragma unroll
-            for (int c = 0; c < kMaxRank; ++c) v[c] = c < Rk1 ? A[s + Rk * c] : 0.f;
+            for (int c = 0; c < kMaxRank; ++c) {
+                const float a = A[min(s + Rk * c, last)];
+                v[c] = c < Rk1 ? a : 0.f;
+            }
         }
         for (int k = 2; k < N; ++k) {
             const int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
             const float* A = static_cast<const float*>(cores.p[k]) + (int64_t)ik[k] * Rk * Rk1;
+            const int last = Rk * Rk1 - 1;
             float w[kMaxRank];
 #pragma unroll
-            for (int c = 0; c < kMaxRank; ++c) {
-                float acc = 0.f;
-                if (c < Rk1) {
+            for (int c = 0; c < kMaxRank; ++c) w[c] = 0.f;
+            for (int c = 0; c < Rk1; ++c) {
+                float col[kMaxRank];
 #pragma unroll
-                    for (int r = 0; r < kMaxRank; ++r)
-                        if (r < Rk) acc += v[r] * A[r + Rk * c];
-                }
-                w[c] = acc;
+                for (int r = 0; r < kMaxRank; ++r) col[r] = A[min(r + Rk * c, last)];
+                float acc = 0.f;
+#pragma unroll
+                for (int r = 0; r < kMaxRank; ++r) acc += r < Rk ? v[r] * col[r] : 0.f;
+#pragma unroll
+                for (int q = 0; q < kMaxRank; ++q)
+                    if (q == c) w[q] = acc;
             }
 #pragma unroll
             for (int c = 0; c < kMaxRank; ++c) v[c] = w[c];
@@ -280,11 +291,14 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
             }
         }
         float x[16];
-        if (MODE == 0) {   // issued before the matrix work, consumed after it
+        if (MODE == 0) {   // issued before the matrix work, consumed after it;
+                           // unconditional (clamped in bounds), masked after
+            const int64_t ic = iok ? i : I0 - 1;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t o = offw[8 * (r >> 2) + (r & 3)];
-                x[r] = (iok && o >= 0) ? Cvt<TX>::to_f32(Xt[o + (int64_t)i * xs0]) : 0.f;
+                const float xv = Cvt<TX>::to_f32(Xt[(o >= 0 ? o : 0) + ic * xs0]);
+                x[r] = (iok && o >= 0) ? xv : 0.f;
             }
         }
         f32x16 acc;

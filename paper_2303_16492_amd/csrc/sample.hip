@@ -24,6 +24,7 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    if (ms.n_pub && blockIdx.x == 0 && threadIdx.x == 0) *ms.n_pub = n;
     const int N = d.N, tid = threadIdx.x;
     const int n1 = ring_next(n, N);
     const int Rn = d.R[n], Rn1 = d.R[n1], RR = Rn * Rn1;

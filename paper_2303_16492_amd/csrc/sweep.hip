@@ -12,15 +12,23 @@
 // same fallback ladder eta + 10^(k-10) tr(h)/RR, k = 0..6.
 //
 // The matrix lives in FP64 matrix-core accumulators: 16 x 16 tiles of the
-// lower triangle spread over four wavefronts (one per SIMD), so each block
-// step moves only the eight pivot rows through LDS.  With U~ the pivot
-// columns minus the selector E and V~ = U~^T, one block step is the single
-// rank-8 update
+// lower triangle spread over three update wavefronts (tile columns u, 5 - u
+// and 6 + u for wavefront u), so each block step moves only the eight pivot
+// rows through LDS.  With U~ the pivot columns minus the selector E and
+// V~ = U~^T, one block step is the single rank-8 update
 //     M <- M - U~ B V~ - 2 E E^T,    B = (M_PP)^{-1},
 // which gives -B on the pivot block, B M_PQ on its rows, M_QP B on its
-// columns and M_QQ - M_QP B M_PQ elsewhere: the classical sweep.  Every
-// wavefront factors the 8 x 8 pivot block itself (Cholesky, its inverse,
-// then B), so the only barrier per step publishes the next pivot rows.
+// columns and M_QQ - M_QP B M_PQ elsewhere: the classical sweep.  The
+// -2 E E^T term only moves the diagonal of that step's pivot block, which
+// no later step reads, so it is applied once at the end.
+//
+// The fourth wavefront owns no tiles: it works one block ahead.  During
+// step q it forms pivot block q+1 as it will be after step q (the Schur
+// complement D - C^T B C of the block as published before step q, C the
+// pivot rows of step q at its columns) and sweeps that 8 x 8 block in
+// registers, so the pivot inverse of every step after the first is ready
+// when the step starts.  One barrier per step publishes the next pivot
+// rows, the next pivot inverse and its verdict together.
 #include "internal.hpp"
 
 namespace trk {
@@ -28,92 +36,94 @@ namespace trk {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSweepWaves = 4;
+constexpr int kFactorWave = 3;
 
-// Lower 16 x 16 tiles (rt >= ct) of an NT x NT tiling.  Wavefront w owns
-// tile columns w and 2W-1-w, which balances the triangle: for NT = 7 or 8
-// every wavefront holds the same number of tiles.  Slot k of wavefront w
-// holds tile (w + k, w) for k < n1, and tile (NT - TPW + k, 2W-1-w) for the
-// last n2 slots; every coordinate is a compile-time constant.
-template <int NT>
-struct SweepTiles {
-    static constexpr int W = kSweepWaves;
-    static constexpr int NP = 16 * NT;
-    static constexpr int n1(int w) { return NT - w > 0 ? NT - w : 0; }
-    static constexpr int n2(int w) { return NT - (2 * W - 1 - w) > 0 ? NT - (2 * W - 1 - w) : 0; }
-    static constexpr int max_count() {
-        int m = 0;
-        for (int w = 0; w < W; ++w) m = n1(w) + n2(w) > m ? n1(w) + n2(w) : m;
-        return m;
-    }
-    static constexpr int TPW = max_count();
-};
-
-// Slot k of wavefront wv: tile (slot_rt, slot_ct), or no tile.
-template <int NT>
-__host__ __device__ constexpr bool slot_first(int wv, int k) { return k < SweepTiles<NT>::n1(wv); }
-template <int NT>
-__host__ __device__ constexpr bool slot_second(int wv, int k) {
-    return !slot_first<NT>(wv, k) && k >= SweepTiles<NT>::TPW - SweepTiles<NT>::n2(wv);
+// Tile columns of update wavefront u = 0, 1, 2: u, 5 - u and 6 + u (those
+// below NT).  Slot k of a wavefront walks its columns top to bottom, the
+// diagonal tile first; every coordinate is a compile-time constant.
+__host__ __device__ constexpr int col_of(int wv, int m) {
+    return wv >= kFactorWave ? 99 : (m == 0 ? wv : (m == 1 ? 5 - wv : 6 + wv));
 }
 template <int NT>
-__host__ __device__ constexpr bool slot_ok(int wv, int k) { return slot_first<NT>(wv, k) || slot_second<NT>(wv, k); }
+__host__ __device__ constexpr int ncol(int wv, int m) { return NT - col_of(wv, m) > 0 ? NT - col_of(wv, m) : 0; }
 template <int NT>
-__host__ __device__ constexpr int slot_rt(int wv, int k) {
-    return slot_first<NT>(wv, k) ? wv + k : (slot_second<NT>(wv, k) ? NT - SweepTiles<NT>::TPW + k : 0);
+__host__ __device__ constexpr int tiles_of(int wv) { return ncol<NT>(wv, 0) + ncol<NT>(wv, 1) + ncol<NT>(wv, 2); }
+template <int NT>
+__host__ __device__ constexpr int tpw() {
+    int m = 1;
+    for (int w = 0; w < kSweepWaves; ++w) m = tiles_of<NT>(w) > m ? tiles_of<NT>(w) : m;
+    return m;
+}
+// which of the wavefront's columns slot k is in (0, 1, 2), or 3 for none
+template <int NT>
+__host__ __device__ constexpr int s_m(int wv, int k) {
+    return k < ncol<NT>(wv, 0) ? 0
+                               : (k < ncol<NT>(wv, 0) + ncol<NT>(wv, 1) ? 1 : (k < tiles_of<NT>(wv) ? 2 : 3));
 }
 template <int NT>
-__host__ __device__ constexpr int slot_ct(int wv, int k) {
-    return slot_first<NT>(wv, k) ? wv : (slot_second<NT>(wv, k) ? 2 * kSweepWaves - 1 - wv : 0);
+__host__ __device__ constexpr bool s_ok(int wv, int k) { return s_m<NT>(wv, k) < 3; }
+template <int NT>
+__host__ __device__ constexpr int s_first(int wv, int m) {
+    return m == 0 ? 0 : (m == 1 ? ncol<NT>(wv, 0) : ncol<NT>(wv, 0) + ncol<NT>(wv, 1));
+}
+template <int NT>
+__host__ __device__ constexpr int s_ct(int wv, int k) { return s_ok<NT>(wv, k) ? col_of(wv, s_m<NT>(wv, k)) : 0; }
+template <int NT>
+__host__ __device__ constexpr int s_rt(int wv, int k) {
+    return s_ok<NT>(wv, k) ? col_of(wv, s_m<NT>(wv, k)) + k - s_first<NT>(wv, s_m<NT>(wv, k)) : 0;
 }
 
 __device__ __forceinline__ int tri8(int i) { return (i * (i + 1)) >> 1; }
 
-// Pivot block of step q (rows 8q.., read from the published pivot rows,
-// which carry -1 on the pivot diagonal): Cholesky factor L, then
-// V = L^{-1} over it, column by column (column j of V needs rows of L from
-// column j on only).  Lane 0 stores V packed by rows (tri8(i) + j) into Vw.
-// Every wavefront runs this same code on the same LDS data, so every
-// wavefront reaches the same verdict.  Returns false on a pivot that is not
-// positive.
-__device__ __forceinline__ bool pivot_chol_inv(const double* __restrict__ Vt, int NP, int q, double* Vw) {
-    double L[8][8];
+// 1/p in FP64: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - p y) (each squares the relative error).
+__device__ __forceinline__ double rcp_nr(double p) {
+    double y = __builtin_amdgcn_rcp(p);
+    double e = __builtin_fma(-p, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-p, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+// Symmetric sweep of the 8 x 8 SPD block D8 (row-major) in registers:
+// -D8^{-1}, lower triangle packed by rows (tri8(i) + j) into Bw by lane 0.
+// Every lane runs the same arithmetic on the same data.  False on a pivot
+// that is not positive (or not finite).
+__device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw) {
+    double a[8][8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < i; ++j) L[i][j] = Vt[i * NP + 8 * q + j];
-        L[i][i] = Vt[i * NP + 8 * q + i] + 1.0;
-    }
+        for (int j = 0; j <= i; ++j) a[i][j] = D8[i * 8 + j];
     bool good = true;
-    double r[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const double dj = L[j][j];
-        good = good && (dj > 0.0) && isfinite(dj);
-        r[j] = rsqrt(dj);
+    for (int k = 0; k < 8; ++k) {
+        const double p = a[k][k];
+        good = good && (p > 0.0) && isfinite(p);
+        const double dk = rcp_nr(p);
+        double col[8], c[8];
 #pragma unroll
-        for (int i = j + 1; i < 8; ++i) L[i][j] *= r[j];
-#pragma unroll
-        for (int k = j + 1; k < 8; ++k)
-#pragma unroll
-            for (int i = k; i < 8; ++i) L[i][k] -= L[i][j] * L[k][j];
-    }
-    double (&V)[8][8] = L;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-#pragma unroll
-        for (int i = j + 1; i < 8; ++i) {
-            double s = L[i][j] * r[j];
-#pragma unroll
-            for (int k = j + 1; k < i; ++k) s += L[i][k] * V[k][j];
-            V[i][j] = -r[i] * s;
+        for (int i = 0; i < 8; ++i) {
+            col[i] = i > k ? a[i][k] : (i < k ? a[k][i] : 0.0);
+            c[i] = col[i] * dk;
         }
-        V[j][j] = r[j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                if (i != k && j != k) a[i][j] = __builtin_fma(-c[i], col[j], a[i][j]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i > k) a[i][k] = c[i];
+            if (i < k) a[k][i] = c[i];
+        }
+        a[k][k] = -dk;
     }
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
 #pragma unroll
-            for (int j = 0; j <= i; ++j) Vw[tri8(i) + j] = V[i][j];
+            for (int j = 0; j <= i; ++j) Bw[tri8(i) + j] = a[i][j];
     }
     return good;
 }
@@ -123,14 +133,14 @@ __device__ __forceinline__ bool pivot_chol_inv(const double* __restrict__ Vt, in
 // the pivot tile row come from the tiles left of the diagonal; entries right
 // of it from the column of tiles below (M is symmetric).
 template <int NT, int WV>
-__device__ __forceinline__ void publish_rows(const dbl4 (&acc)[SweepTiles<NT>::TPW], int q, double* Vt) {
-    constexpr int NP = SweepTiles<NT>::NP;
+__device__ __forceinline__ void publish_rows(const dbl4 (&acc)[tpw<NT>()], int q, double* Vt) {
+    constexpr int NP = 16 * NT;
     const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
     const int tq = q >> 1, hq = q & 1;
 #pragma unroll
-    for (int k = 0; k < SweepTiles<NT>::TPW; ++k) {
-        if (!slot_ok<NT>(WV, k)) continue;
-        const int rt = slot_rt<NT>(WV, k), ct = slot_ct<NT>(WV, k);
+    for (int k = 0; k < tpw<NT>(); ++k) {
+        if (!s_ok<NT>(WV, k)) continue;
+        const int rt = s_rt<NT>(WV, k), ct = s_ct<NT>(WV, k);
         if (rt == tq) {
 #pragma unroll
             for (int jj = 0; jj < 2; ++jj) {
@@ -146,104 +156,229 @@ __device__ __forceinline__ void publish_rows(const dbl4 (&acc)[SweepTiles<NT>::T
     }
 }
 
-// One block step on this wavefront's tiles: Z = V^T (V V~) on its two tile
-// columns (rows 8..15 of each product are zero; D rows 0-3 and 4-7 are the
-// B operands of the two K = 4 steps), then acc -= U~ Z and -2 on the swept
-// diagonal.
-template <int NT, int WV>
-__device__ __forceinline__ void update_tiles(dbl4 (&acc)[SweepTiles<NT>::TPW], const double* __restrict__ V, const double* __restrict__ Vw,
-                                             int q) {
-    using T = SweepTiles<NT>;
-    constexpr int NP = T::NP, TPW = T::TPW;
-    constexpr int c1 = WV, c2 = 2 * kSweepWaves - 1 - WV;
-    constexpr bool has2 = T::n2(WV) > 0;
+// The 8 x 8 pivot block q (plain M_PP, row-major) from its diagonal tile.
+__device__ __forceinline__ void publish_d8(const dbl4& a, int q, double* D8) {
     const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
-    double a1[2], a2[2], v1[2], v2[2];
+    const int hq = q & 1;
+    if ((lc >> 3) == hq) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const double v = hq ? a[2 + jj] : a[jj];
+            D8[(4 * jj + lr) * 8 + (lc - 8 * hq)] = v;
+        }
+    }
+}
+
+struct SweepZ {
+    dbl4 z[3];
+};
+
+// Z = B V~ for the wavefront's tile columns (rows 8..15 of each product are
+// zero), with B = M_PP^{-1} = -(packed Bw).
+template <int NT, int WV>
+__device__ __forceinline__ SweepZ compute_z(const double* __restrict__ Vt, const double* __restrict__ Bw) {
+    constexpr int NP = 16 * NT;
+    const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
+    double a1[2], v[3][2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int j = 4 * s + lr;
-        a1[s] = (lc < 8 && j <= lc) ? Vw[tri8(lc) + j] : 0.0;   // V[lc][j]
-        a2[s] = (lc < 8 && lc <= j) ? Vw[tri8(j) + lc] : 0.0;   // V[j][lc]
-        v1[s] = V[j * NP + 16 * c1 + lc];
-        v2[s] = has2 ? V[j * NP + 16 * c2 + lc] : 0.0;
+        const int hi = j > lc ? j : lc, lo = j > lc ? lc : j;
+        a1[s] = lc < 8 ? -Bw[tri8(hi & 7) + (lo & 7)] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][s] = ncol<NT>(WV, m) > 0 ? Vt[j * NP + 16 * col_of(WV, m) + lc] : 0.0;
     }
-    double ua[TPW][2];
-#pragma unroll
-    for (int k = 0; k < TPW; ++k)
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-            ua[k][s] = slot_ok<NT>(WV, k) ? -V[(4 * s + lr) * NP + 16 * slot_rt<NT>(WV, k) + lc] : 0.0;
     const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
-    dbl4 t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[0], v1[0], zero, 0, 0, 0);
-    dbl4 t2 = zero;
-    if constexpr (has2) t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[0], v2[0], zero, 0, 0, 0);
-    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[1], v1[1], t1, 0, 0, 0);
-    if constexpr (has2) t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[1], v2[1], t2, 0, 0, 0);
-    dbl4 z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[0], t1[0], zero, 0, 0, 0);
-    dbl4 z2 = zero;
-    if constexpr (has2) z2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[0], t2[0], zero, 0, 0, 0);
-    z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[1], t1[1], z1, 0, 0, 0);
-    if constexpr (has2) z2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[1], t2[1], z2, 0, 0, 0);
+    SweepZ z{{zero, zero, zero}};
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int m = 0; m < 3; ++m)
+        if (ncol<NT>(WV, m) > 0) z.z[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[0], v[m][0], zero, 0, 0, 0);
 #pragma unroll
-        for (int k = 0; k < TPW; ++k)
-            if (slot_ok<NT>(WV, k))
-                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[k][s], slot_first<NT>(WV, k) ? z1[s] : z2[s], acc[k],
-                                                              0, 0, 0);
-    const int tq = q >> 1, hq = q & 1;
-    const bool lane_diag = (lc >> 3) == hq && lr == (lc & 3);
+    for (int m = 0; m < 3; ++m)
+        if (ncol<NT>(WV, m) > 0) z.z[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[1], v[m][1], z.z[m], 0, 0, 0);
+    return z;
+}
+
+// a - U~ Z on the tile in tile row rt.
+template <int NT>
+__device__ __forceinline__ dbl4 update_tile(const dbl4& a, const double* __restrict__ Vt, const dbl4& zz, int rt) {
+    constexpr int NP = 16 * NT;
+    const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
+    double ua[2];
 #pragma unroll
-    for (int k = 0; k < TPW; ++k) {
-        if (slot_ok<NT>(WV, k) && slot_rt<NT>(WV, k) == slot_ct<NT>(WV, k) && tq == slot_rt<NT>(WV, k)) {
+    for (int s = 0; s < 2; ++s) ua[s] = -Vt[(4 * s + lr) * NP + 16 * rt + lc];
+    const dbl4 r = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], zz[0], a, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(ua[1], zz[1], r, 0, 0, 0);
+}
+
+// Pivot block q+1 after step q from the block D as published before step q:
+// Dn = D - C^T B C with C the pivot rows of step q at the block's columns
+// (Schur complement), on the matrix cores.
+template <int NT>
+__device__ __forceinline__ void next_pivot_block(const double* __restrict__ Vt, const double* __restrict__ Bw,
+                                                 const double* __restrict__ D, int q, double* Dn) {
+    constexpr int NP = 16 * NT;
+    const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
+    double a1[2], c[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[k][j] -= (lane_diag && j == (lc >> 2)) ? 2.0 : 0.0;
-        }
+    for (int s = 0; s < 2; ++s) {
+        const int j = 4 * s + lr;
+        const int hi = j > lc ? j : lc, lo = j > lc ? lc : j;
+        a1[s] = lc < 8 ? -Bw[tri8(hi & 7) + (lo & 7)] : 0.0;
+        c[s] = lc < 8 ? Vt[j * NP + 8 * (q + 1) + (lc & 7)] : 0.0;
+    }
+    double dv[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) dv[j] = D[(4 * j + lr) * 8 + (lc & 7)];
+    const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
+    dbl4 w = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[0], c[0], zero, 0, 0, 0);
+    w = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[1], c[1], w, 0, 0, 0);
+    dbl4 r = __builtin_amdgcn_mfma_f64_16x16x4f64(c[0], w[0], zero, 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f64_16x16x4f64(c[1], w[1], r, 0, 0, 0);
+    if (lc < 8) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) Dn[(4 * j + lr) * 8 + lc] = dv[j] - r[j];
     }
 }
 
+// h + eta I into the wavefront's tiles (identity on the padding), every
+// load issued before any use (indices clamped in bounds, masked after).
 template <int NT, int WV>
-__device__ __forceinline__ void fill_tiles(dbl4 (&acc)[SweepTiles<NT>::TPW], const double* __restrict__ gram, int RR,
+__device__ __forceinline__ void fill_tiles(dbl4 (&acc)[tpw<NT>()], const double* __restrict__ gram, int RR,
                                            double eta) {
     const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
+    double g[tpw<NT>()][4];
 #pragma unroll
-    for (int k = 0; k < SweepTiles<NT>::TPW; ++k) {   // every load issued before any use
-        const int rt = slot_rt<NT>(WV, k), ct = slot_ct<NT>(WV, k);
+    for (int k = 0; k < tpw<NT>(); ++k) {
+        const int rt = s_rt<NT>(WV, k), ct = s_ct<NT>(WV, k);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = 16 * rt + 4 * j + lr, c = 16 * ct + lc;
-            const bool in = slot_ok<NT>(WV, k) && r < RR && c < RR;
-            const double g = in ? gram[(int64_t)r * RR + c] : 0.0;
-            acc[k][j] = g + (r == c ? (r < RR ? eta : 1.0) : 0.0);
+            const int rc = r < RR ? r : RR - 1, cc = c < RR ? c : RR - 1;
+            g[k][j] = s_ok<NT>(WV, k) ? gram[(int64_t)rc * RR + cc] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < tpw<NT>(); ++k) {
+        const int rt = s_rt<NT>(WV, k), ct = s_ct<NT>(WV, k);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = 16 * rt + 4 * j + lr, c = 16 * ct + lc;
+            const bool in = r < RR && c < RR;
+            acc[k][j] = (in ? g[k][j] : 0.0) + (r == c ? (r < RR ? eta : 1.0) : 0.0);
         }
     }
 }
 
+// -M^{-1} into hm (both triangles), with the deferred -2 on the diagonal.
 template <int NT, int WV>
-__device__ __forceinline__ void store_tiles(const dbl4 (&acc)[SweepTiles<NT>::TPW], double* __restrict__ hm, int RR) {
+__device__ __forceinline__ void store_tiles(const dbl4 (&acc)[tpw<NT>()], double* __restrict__ hm, int RR) {
     const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
 #pragma unroll
-    for (int k = 0; k < SweepTiles<NT>::TPW; ++k) {
-        if (!slot_ok<NT>(WV, k)) continue;
-        const int rt = slot_rt<NT>(WV, k), ct = slot_ct<NT>(WV, k);
+    for (int k = 0; k < tpw<NT>(); ++k) {
+        if (!s_ok<NT>(WV, k)) continue;
+        const int rt = s_rt<NT>(WV, k), ct = s_ct<NT>(WV, k);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = 16 * rt + 4 * j + lr, c = 16 * ct + lc;
             if (r < RR && c < RR) {
-                hm[(int64_t)r * RR + c] = acc[k][j];
+                hm[(int64_t)r * RR + c] = acc[k][j] - (r == c ? 2.0 : 0.0);
                 if (rt != ct) hm[(int64_t)c * RR + r] = acc[k][j];
             }
         }
     }
 }
 
-#define TRK_BY_WAVE(CALL)                       \
-    switch (w) {                                \
-        case 0: CALL(0); break;                 \
-        case 1: CALL(1); break;                 \
-        case 2: CALL(2); break;                 \
-        default: CALL(3); break;                \
+struct SweepShared {
+    double Vt[2][8 * 128];   // pivot rows of step q, by q & 1
+    double Bw[2][40];        // packed -B of step q, by q & 1
+    double D8[2][64];        // pivot block q+1 as published before step q, by (q + 1) & 1
+    double Dn[64];           // the factor wavefront's pivot block after the update
+    double red[kSweepWaves];
+    int good[2];             // verdict of the factorisation of step q's pivot block, by q & 1
+};
+
+// One wavefront's part of the sweep with the fallback ladder.  Returns the
+// attempt that succeeded, or -1.  Every wavefront passes the same barriers
+// and reads the same verdicts, so every wavefront returns the same value.
+template <int NT, int WV>
+__device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int RR, double damping,
+                                          double* __restrict__ hm, SweepShared& sh) {
+    const int npiv = (RR + 7) >> 3;
+    dbl4 acc[tpw<NT>()];
+    double base = 0.0;   // tr(h + damping I) / RR, needed only once a factorisation has failed
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        if (attempt == 1) {
+            double tr = 0.0;
+            for (int c = threadIdx.x; c < RR; c += blockDim.x) tr += gram[(int64_t)c * RR + c];
+            base = (block_sum(tr, sh.red) + damping * RR) / RR;
+        }
+        const double eta = attempt == 0 ? damping : damping + pow(10.0, (double)(attempt - 1 - 10)) * base;
+        __syncthreads();   // the previous attempt's readers are done with the shared buffers
+        if (WV == kFactorWave) {
+            // pivot blocks 0 and 1 of h + eta I straight from memory
+            const int l = threadIdx.x & 63;
+            const int u = l >> 3, v = l & 7;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int r = 8 * b + u, c = 8 * b + v;
+                const int rc = r < RR ? r : RR - 1, cc = c < RR ? c : RR - 1;
+                const double gv = gram[(int64_t)rc * RR + cc];
+                const double x = (r < RR && c < RR ? gv : 0.0) + (r == c ? (r < RR ? eta : 1.0) : 0.0);
+                if (b == 0) sh.Dn[u * 8 + v] = x;
+                else sh.D8[1][u * 8 + v] = x;
+            }
+            // this wavefront's LDS stores complete before its own reads
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const bool g = sweep8(sh.Dn, sh.Bw[0]);
+            if ((threadIdx.x & 63) == 0) sh.good[0] = g ? 1 : 0;
+        } else {
+            fill_tiles<NT, WV>(acc, gram, RR, eta);
+            publish_rows<NT, WV>(acc, 0, sh.Vt[0]);
+        }
+        __syncthreads();
+        bool good = sh.good[0] != 0;
+        for (int q = 0; q < npiv && good; ++q) {
+            const double* Vt = sh.Vt[q & 1];
+            const bool more = q + 1 < npiv;
+            if (WV == kFactorWave) {
+                if (more) {
+                    next_pivot_block<NT>(Vt, sh.Bw[q & 1], sh.D8[(q + 1) & 1], q, sh.Dn);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const bool g = sweep8(sh.Dn, sh.Bw[(q + 1) & 1]);
+                    if ((threadIdx.x & 63) == 0) sh.good[(q + 1) & 1] = g ? 1 : 0;
+                }
+            } else {
+                const SweepZ z = compute_z<NT, WV>(Vt, sh.Bw[q & 1]);
+#pragma unroll
+                for (int k = 0; k < tpw<NT>(); ++k)
+                    if (s_ok<NT>(WV, k)) acc[k] = update_tile<NT>(acc[k], Vt, z.z[s_m<NT>(WV, k)], s_rt<NT>(WV, k));
+                if (more) publish_rows<NT, WV>(acc, q + 1, sh.Vt[(q + 1) & 1]);
+                if (q + 2 < npiv) {
+                    // pivot block q+2 as it stands after this step
+                    const int t2 = (q + 2) >> 1;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+                        if (ncol<NT>(WV, m) > 0 && t2 == col_of(WV, m))
+                            publish_d8(acc[s_first<NT>(WV, m)], q + 2, sh.D8[(q + 2) & 1]);
+                }
+            }
+            __syncthreads();
+            if (more) good = sh.good[(q + 1) & 1] != 0;
+        }
+        if (good) {
+            if (WV != kFactorWave) store_tiles<NT, WV>(acc, hm, RR);
+            return attempt;
+        }
     }
+    return -1;
+}
 
 // -(gram + eta I)^{-1} into hm (RR x RR, row-major, both triangles), with
 // the fallback ladder; flag: 0 ok, 1 damped, 2 failed.  256 threads.
@@ -251,74 +386,26 @@ template <int NT>
 __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const double* __restrict__ gram,
                                                double damping, double* __restrict__ hm, int* __restrict__ flag,
                                                int32_t* status) {
-    using T = SweepTiles<NT>;
-    constexpr int NP = T::NP, TPW = T::TPW;
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
     const int RR = d.R[n] * d.R[ring_next(n, d.N)];
-    const int npiv = (RR + 7) >> 3;
-    __shared__ __align__(16) double Vt[2][8 * NP];
-    __shared__ __align__(16) double Vws[kSweepWaves][40];
-    __shared__ double red[kSweepWaves];
-    const int tid = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    double* Vw = Vws[w];
-
-    dbl4 acc[TPW];
-    int ok_at = -1;
-    double base = 0.0;   // tr(h + damping I) / RR, needed only once a factorisation has failed
-    for (int attempt = 0; attempt < 8; ++attempt) {
-        if (attempt == 1) {
-            double tr = 0.0;
-            for (int c = tid; c < RR; c += 256) tr += gram[(int64_t)c * RR + c];
-            base = (block_sum(tr, red) + damping * RR) / RR;
-        }
-        const double eta = attempt == 0 ? damping : damping + pow(10.0, (double)(attempt - 1 - 10)) * base;
-#define TRK_FILL(WV) fill_tiles<NT, WV>(acc, gram, RR, eta)
-        TRK_BY_WAVE(TRK_FILL)
-#undef TRK_FILL
-        __syncthreads();   // the previous attempt's readers are done with Vt
-#define TRK_PUB0(WV) publish_rows<NT, WV>(acc, 0, Vt[0])
-        TRK_BY_WAVE(TRK_PUB0)
-#undef TRK_PUB0
-        bool good = true;
-        for (int q = 0; q < npiv; ++q) {
-            __syncthreads();
-            const double* V = Vt[q & 1];
-            good = pivot_chol_inv(V, NP, q, Vw);
-            if (!good) break;   // the same in every wavefront: same data, same code
-            // lane 0's stores of V reach LDS before any lane reads them (the
-            // LDS instructions of one wavefront complete in order)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#define TRK_UPD(WV)                                                              \
-    update_tiles<NT, WV>(acc, V, Vw, q);                                         \
-    if (q + 1 < npiv) publish_rows<NT, WV>(acc, q + 1, Vt[(q + 1) & 1])
-            TRK_BY_WAVE(TRK_UPD)
-#undef TRK_UPD
-        }
-        if (good) {
-            ok_at = attempt;
-            break;
-        }
+    __shared__ SweepShared sh;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int ok_at;
+    switch (w) {
+        case 0: ok_at = sweep_wave<NT, 0>(gram, RR, damping, hm, sh); break;
+        case 1: ok_at = sweep_wave<NT, 1>(gram, RR, damping, hm, sh); break;
+        case 2: ok_at = sweep_wave<NT, 2>(gram, RR, damping, hm, sh); break;
+        default: ok_at = sweep_wave<NT, 3>(gram, RR, damping, hm, sh); break;
     }
-    if (ok_at >= 0) {
-#define TRK_STORE(WV) store_tiles<NT, WV>(acc, hm, RR)
-        TRK_BY_WAVE(TRK_STORE)
-#undef TRK_STORE
-    }
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         const int fl = ok_at < 0 ? 2 : (ok_at > 0 ? 1 : 0);
         *flag = fl;
         if (fl == 1) set_status(status, TR_DEV_DAMPED);
         if (fl == 2) set_status(status, TR_DEV_NOT_SPD);
     }
 }
-
-#undef TRK_BY_WAVE
 
 constexpr int kApplyRows = 16;
 
@@ -411,8 +498,17 @@ hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram
     double* hm = reinterpret_cast<double*>(w + L.L_off);
     int* flag = reinterpret_cast<int*>(w + L.flag_off);
     const int nt = (sh.maxRR + 15) / 16;
-#define TRK_SWEEP(NTV) \
-    hipLaunchKernelGGL(k_sweep<NTV>, dim3(1), dim3(256), 0, st, d, ms, gram, damping, hm, flag, status)
+    // The workgroup also reserves the rest of the CU's LDS, which no other
+    // workgroup can then share: the sweep is one dependency chain, and
+    // waves of a concurrent kernel (the gradient, on the other stream) on
+    // its SIMDs would stretch every link of it.
+    constexpr size_t kCuLds = 160 * 1024;
+    const size_t reserve = (kCuLds - sizeof(SweepShared)) & ~(size_t)1023;
+#define TRK_SWEEP(NTV)                                                                                          \
+    do {                                                                                                        \
+        const size_t dyn = allow_lds(reinterpret_cast<const void*>(&k_sweep<NTV>), reserve) ? reserve : 0;     \
+        hipLaunchKernelGGL(k_sweep<NTV>, dim3(1), dim3(256), dyn, st, d, ms, gram, damping, hm, flag, status); \
+    } while (0)
     switch (nt) {
         case 1: TRK_SWEEP(1); break;
         case 2: TRK_SWEEP(2); break;
