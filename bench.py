@@ -247,6 +247,33 @@ def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup, G=50, E=200):
                 dev_status=status)
 
 
+def plain_rate(args, prec, init3, X, I, R, m, dev, K, G=50):
+    """Steps/s of the plain method (TR-BRSGD, AdaGrad step) in precision
+    ``prec`` on the same workload: draws, subchain, gradient, update; here
+    the gradient kernel is on the critical path of every step.  K steps
+    replayed from a HIP graph of G steps."""
+    import torch
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    N = 3
+    solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law="U", scaled=False,
+                      prec=prec, rule=api.step_rule("adagrad", eta=1e-3), seed=args.seed)
+    solver.run(args.warmup)
+    graph = solver.capture(G)
+    graph.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(K // G):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / K
+    status = int(solver.status.item())
+    del graph, solver
+    return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "dev_status": status}
+
+
 def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, cap=None):
     """Wall time from the initial cores until an RSE check reaches
     ``target`` (checks every ``every`` steps count toward the time), capped
@@ -328,6 +355,8 @@ def main():
     other = "bf16" if args.prec == "f32" else "f32"
     alt = timed_run(args, other, init3, X, I, R, m, dev, K, args.warmup)
     print(f"[bench] {other}: {alt['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+    plain = {pr: plain_rate(args, pr, init3, X, I, R, m, dev, K) for pr in ("f32", "bf16")}
+    print(f"[bench] plain method: {plain}", file=sys.stderr, flush=True)
     ttt = []
     if args.ttt_steps > 0:
         for pr in ("f32", "bf16"):
@@ -444,6 +473,7 @@ def main():
                   "and joins as graph edges); kernel durations: HIP events around every launch of the inverse and "
                   "gradient kernels over 200 eager steps of the same run, on the streams they run on",
         "eager_steps_per_s": round(1e3 / main["eager_ms_per_step"], 2),
+        "forms_plain_method": plain,
         "time_to_target": ttt,
         "time_to_target_planted": {"workload": "planted-gaussian-n3-i400-r10", "m": m, "law": "uniform",
                                    "alpha": args.alpha, "runs": planted},

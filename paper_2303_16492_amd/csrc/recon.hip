@@ -185,9 +185,18 @@ __global__ __launch_bounds__(256) void k_recon_pack(tr_desc d, const float* __re
     Gpk[e] = (i < I0 && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
 }
 
+// Order 3 builds a block's rows from LDS when its columns touch at most this
+// many slices of the last core (true whenever I_2 >= 32).
+constexpr int kRmMaxOuter = 8;
+
 // MODE 0: per-block sums of (X_hat - X_true)^2 and X_true^2 into part;
 // MODE 1: X_hat written to Xo.  Gpk null: B operand read from G_{1(2)}
 // directly (uncoalesced; used by the one-off reconstruction).
+//
+// Work split: the block's 128 columns are four column tiles of 32; the
+// (row tile, column tile) pairs are taken in row-tile-major order, and each
+// wavefront takes a contiguous quarter of them (exactly ceil(I_1/32) pairs
+// each), so it loads a B fragment only when its row tile changes.
 template <typename TX, int KT, int MODE>
 __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const float* __restrict__ Gpk,
                                                     const TX* __restrict__ Xt, TX* __restrict__ Xo,
@@ -203,61 +212,116 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int64_t* sOff = reinterpret_cast<int64_t*>(smem_raw);          // [kRmCols], -1 past J
     float* sS = reinterpret_cast<float*>(sOff + kRmCols);          // [kRmCols][SP]
+    float* sP = sS + kRmCols * SP;                                  // order 3: slices of the last core
     const int tid = threadIdx.x;
-    // subchain rows of the block's columns: thread item (column, row s of M_j)
-    for (int e = tid; e < kRmCols * R1; e += blockDim.x) {
-        const int jj = e / R1, s = e - jj * R1;
-        const int64_t j = j0 + jj;
-        float* out = sS + jj * SP + R0 * s;
-        if (j >= J) {
-            for (int r = 0; r < R0; ++r) out[r] = 0.f;
-            if (s == 0) sOff[jj] = -1;
-            continue;
+
+    // Order 3: column j = i_2 + I_2 i_3 has subchain row M_j = G_2(i_2) G_3(i_3);
+    // the block's columns span few i_3, whose slices are staged in LDS, and
+    // each item (column, row s of M_j) loads one row of G_2(i_2).
+    const int I1 = d.I[1 % N];
+    const int64_t jl = (j0 + kRmCols < J ? j0 + kRmCols : J) - 1;
+    const int o_lo = N == 3 ? (int)(j0 / I1) : 0;
+    const int n_outer = N == 3 && j0 < J ? (int)(jl / I1) - o_lo + 1 : 0;
+    const bool staged = N == 3 && n_outer <= kRmMaxOuter;
+    if (staged) {
+        const int R2 = d.R[2];                       // slices of core 3: R_3 x R_1 (R_{N+1} = R_1)
+        const int RR2 = R2 * R0;
+        const float* G2 = static_cast<const float*>(cores.p[2]);
+        for (int e = tid; e < n_outer * RR2; e += blockDim.x) sP[e] = G2[(int64_t)o_lo * RR2 + e];
+        for (int e = tid; e < kRmCols; e += blockDim.x) {
+            const int64_t j = j0 + e;
+            sOff[e] = j < J ? (j % I1) * d.x_stride[1] + (j / I1) * d.x_stride[2] : -1;
         }
-        int ik[kMaxOrder];
-        int64_t rem = j, off = 0;
-        for (int k = 1; k < N; ++k) {
-            ik[k] = (int)(rem % d.I[k]);
-            rem /= d.I[k];
-            off += (int64_t)ik[k] * d.x_stride[k];
-        }
-        if (s == 0) sOff[jj] = off;
-        // Loads are unconditional (indices clamped into the slice) so that a
-        // whole slice row or column is in flight at once; entries past the
-        // ranks are masked after the load.
+        __syncthreads();
+        const float* G1 = static_cast<const float*>(cores.p[1]);
+        const int RR1 = R1 * R2, last = RR1 - 1;
+        const int total = kRmCols * R1;
+        auto load_row = [&](int e, float (&v)[kMaxRank]) {   // row s of G_2(i_2), clamped in bounds
+            const int jj = e / R1, s = e - jj * R1;
+            const int64_t j = j0 + jj < J ? j0 + jj : J - 1;
+            const float* A = G1 + (j % I1) * RR1;
+#pragma unroll
+            for (int c = 0; c < kMaxRank; ++c) v[c] = A[min(s + R1 * c, last)];
+        };
         float v[kMaxRank];
-        {
-            const int Rk = d.R[1 % N], Rk1 = d.R[ring_next(1 % N, N)];
-            const float* A = static_cast<const float*>(cores.p[1 % N]) + (int64_t)ik[1] * Rk * Rk1;
-            const int last = Rk * Rk1 - 1;
+        if (tid < total) load_row(tid, v);
+        for (int e = tid; e < total; e += blockDim.x) {
+            float vn[kMaxRank];
+            if (e + (int)blockDim.x < total) load_row(e + blockDim.x, vn);   // next item's row in flight
+            const int jj = e / R1, s = e - jj * R1;
+            const int64_t j = j0 + jj;
+            float* out = sS + jj * SP + R0 * s;
+            if (j >= J) {
+                for (int r = 0; r < R0; ++r) out[r] = 0.f;
+            } else {
+                const float* P = sP + ((int)(j / I1) - o_lo) * R2 * R0;
+                for (int r = 0; r < R0; ++r) {
+                    float acc = 0.f;
 #pragma unroll
-            for (int c = 0; c < kMaxRank; ++c) {
-                const float a = A[min(s + Rk * c, last)];
-                v[c] = c < Rk1 ? a : 0.f;
-            }
-        }
-        for (int k = 2; k < N; ++k) {
-            const int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
-            const float* A = static_cast<const float*>(cores.p[k]) + (int64_t)ik[k] * Rk * Rk1;
-            const int last = Rk * Rk1 - 1;
-            float w[kMaxRank];
-#pragma unroll
-            for (int c = 0; c < kMaxRank; ++c) w[c] = 0.f;
-            for (int c = 0; c < Rk1; ++c) {
-                float col[kMaxRank];
-#pragma unroll
-                for (int r = 0; r < kMaxRank; ++r) col[r] = A[min(r + Rk * c, last)];
-                float acc = 0.f;
-#pragma unroll
-                for (int r = 0; r < kMaxRank; ++r) acc += r < Rk ? v[r] * col[r] : 0.f;
-#pragma unroll
-                for (int q = 0; q < kMaxRank; ++q)
-                    if (q == c) w[q] = acc;
+                    for (int c = 0; c < kMaxRank; ++c)
+                        if (c < R2) acc += v[c] * P[c + R2 * r];
+                    out[r] = acc;
+                }
             }
 #pragma unroll
-            for (int c = 0; c < kMaxRank; ++c) v[c] = w[c];
+            for (int c = 0; c < kMaxRank; ++c) v[c] = vn[c];
         }
-        for (int r = 0; r < R0; ++r) out[r] = v[r];
+    } else {
+        // any order: thread item (column, row s of M_j) through the chain of
+        // slice products.  Loads are unconditional (indices clamped into the
+        // slice) so that a whole slice row or column is in flight at once;
+        // entries past the ranks are masked after the load.
+        for (int e = tid; e < kRmCols * R1; e += blockDim.x) {
+            const int jj = e / R1, s = e - jj * R1;
+            const int64_t j = j0 + jj;
+            float* out = sS + jj * SP + R0 * s;
+            if (j >= J) {
+                for (int r = 0; r < R0; ++r) out[r] = 0.f;
+                if (s == 0) sOff[jj] = -1;
+                continue;
+            }
+            int ik[kMaxOrder];
+            int64_t rem = j, off = 0;
+            for (int k = 1; k < N; ++k) {
+                ik[k] = (int)(rem % d.I[k]);
+                rem /= d.I[k];
+                off += (int64_t)ik[k] * d.x_stride[k];
+            }
+            if (s == 0) sOff[jj] = off;
+            float v[kMaxRank];
+            {
+                const int Rk = d.R[1 % N], Rk1 = d.R[ring_next(1 % N, N)];
+                const float* A = static_cast<const float*>(cores.p[1 % N]) + (int64_t)ik[1] * Rk * Rk1;
+                const int last = Rk * Rk1 - 1;
+#pragma unroll
+                for (int c = 0; c < kMaxRank; ++c) {
+                    const float a = A[min(s + Rk * c, last)];
+                    v[c] = c < Rk1 ? a : 0.f;
+                }
+            }
+            for (int k = 2; k < N; ++k) {
+                const int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
+                const float* A = static_cast<const float*>(cores.p[k]) + (int64_t)ik[k] * Rk * Rk1;
+                const int last = Rk * Rk1 - 1;
+                float w[kMaxRank];
+#pragma unroll
+                for (int c = 0; c < kMaxRank; ++c) w[c] = 0.f;
+                for (int c = 0; c < Rk1; ++c) {
+                    float col[kMaxRank];
+#pragma unroll
+                    for (int r = 0; r < kMaxRank; ++r) col[r] = A[min(r + Rk * c, last)];
+                    float acc = 0.f;
+#pragma unroll
+                    for (int r = 0; r < kMaxRank; ++r) acc += r < Rk ? v[r] * col[r] : 0.f;
+#pragma unroll
+                    for (int q = 0; q < kMaxRank; ++q)
+                        if (q == c) w[q] = acc;
+                }
+#pragma unroll
+                for (int c = 0; c < kMaxRank; ++c) v[c] = w[c];
+            }
+            for (int r = 0; r < R0; ++r) out[r] = v[r];
+        }
     }
     for (int e = tid; e < kRmCols * (2 * KT - RR); e += blockDim.x) {   // K padding
         const int jj = e / (2 * KT - RR);
@@ -266,30 +330,33 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
     __syncthreads();
 
     const int w = tid >> 6, l = tid & 63, lc = l & 31, lh = l >> 5;
-    // A operand: row 32 w + lc of the block's subchain rows, k = 2 q + lh
-    // (read from LDS at each instruction).  Result row r of this lane is
-    // column 32 w + 8 (r / 4) + 4 lh + r % 4, result column is i_1 = 32 it + lc.
-    const float* arow = sS + (32 * w + lc) * SP + lh;
-    const int64_t* offw = sOff + 32 * w + 4 * lh;
+    // Result row r of this lane within column tile ct is column
+    // 32 ct + 8 (r / 4) + 4 lh + r % 4; its result column is i_1 = 32 it + lc.
     const float* G0 = static_cast<const float*>(cores.p[0]);
     const int64_t xs0 = d.x_stride[0];
     const int nti = (I0 + 31) / 32;
     double err = 0.0, xx = 0.0;
-    for (int it = 0; it < nti; ++it) {
+    float b[KT];
+    int it_loaded = -1;
+    for (int pr = w * nti; pr < (w + 1) * nti; ++pr) {
+        const int it = pr >> 2, ct = pr & 3;
         const int i = 32 * it + lc;
         const bool iok = i < I0;
-        float b[KT];
-        if (Gpk) {
-            const float* src = Gpk + (int64_t)it * KT * 64 + l;
+        if (it != it_loaded) {   // B fragment of row tile it, kept across its column tiles
+            it_loaded = it;
+            if (Gpk) {
+                const float* src = Gpk + (int64_t)it * KT * 64 + l;
 #pragma unroll
-            for (int q = 0; q < KT; ++q) b[q] = src[q * 64];
-        } else {
+                for (int q = 0; q < KT; ++q) b[q] = src[q * 64];
+            } else {
 #pragma unroll
-            for (int q = 0; q < KT; ++q) {
-                const int k = 2 * q + lh;
-                b[q] = (iok && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
+                for (int q = 0; q < KT; ++q) {
+                    const int k = 2 * q + lh;
+                    b[q] = (iok && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
+                }
             }
         }
+        const int64_t* offw = sOff + 32 * ct + 4 * lh;
         float x[16];
         if (MODE == 0) {   // issued before the matrix work, consumed after it;
                            // unconditional (clamped in bounds), masked after
@@ -301,6 +368,7 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
                 x[r] = (iok && o >= 0) ? xv : 0.f;
             }
         }
+        const float* arow = sS + (32 * ct + lc) * SP + lh;
         f32x16 acc;
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.f;
@@ -333,7 +401,9 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
     }
 }
 
-static size_t recon_mfma_shm(int KT) { return (size_t)kRmCols * 8 + (size_t)kRmCols * (2 * KT + 1) * 4; }
+static size_t recon_mfma_shm(int KT) {
+    return (size_t)kRmCols * 8 + (size_t)kRmCols * (2 * KT + 1) * 4 + (size_t)kRmMaxOuter * kMaxRR * 4;
+}
 
 static int64_t recon_mfma_blocks(const tr_desc& d) {
     int64_t J = 1;

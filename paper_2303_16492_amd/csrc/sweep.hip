@@ -417,7 +417,9 @@ constexpr int kApplyRows = 16;
 // with zeros to 128.  With lp.part set, block 0 also writes the loss.  With
 // ``step`` set, the block that finishes last advances the step counter
 // (after every block has read it).
-template <typename TC>
+// SHAPE0: every mode has the same I_n and R_n R_{n+1}, so the loads of g and
+// -M^{-1} are issued before the step's mode has arrived.
+template <typename TC, bool SHAPE0>
 __global__ __launch_bounds__(256) void k_scaled_apply(tr_desc d, ModeSrc ms, const TC* __restrict__ g,
                                                       LossParts lp, double* __restrict__ loss,
                                                       const double* __restrict__ hm, const int* __restrict__ flag,
@@ -426,8 +428,9 @@ __global__ __launch_bounds__(256) void k_scaled_apply(tr_desc d, ModeSrc ms, con
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
-    const int In = d.I[n];
-    const int RR = d.R[n] * d.R[ring_next(n, d.N)];
+    const int ns = SHAPE0 ? 0 : n;
+    const int In = d.I[ns];
+    const int RR = d.R[ns] * d.R[ring_next(ns, d.N)];
     const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4, w = tid >> 6;
     __shared__ double red[4];
     if (blockIdx.x == 0 && lp.part) {
@@ -532,12 +535,20 @@ hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossP
     const double* hm = reinterpret_cast<const double*>(w + L.L_off);
     const int* flag = reinterpret_cast<const int*>(w + L.flag_off);
     const dim3 grid((sh.maxI + kApplyRows - 1) / kApplyRows);
-    if (d.core_dtype == TR_F64)
-        hipLaunchKernelGGL(k_scaled_apply<double>, grid, dim3(256), 0, st, d, ms, static_cast<const double*>(g), lp,
-                           loss, hm, flag, cores, accum, rule, status, step);
-    else
-        hipLaunchKernelGGL(k_scaled_apply<float>, grid, dim3(256), 0, st, d, ms, static_cast<const float*>(g), lp,
-                           loss, hm, flag, cores, accum, rule, status, step);
+    bool same = true;
+    for (int k = 1; k < d.N; ++k)
+        same = same && d.I[k] == d.I[0] && d.R[k] * d.R[(k + 1) % d.N] == d.R[0] * d.R[1 % d.N];
+#define TRK_APPLY(TC, S0)                                                                                   \
+    hipLaunchKernelGGL((k_scaled_apply<TC, S0>), grid, dim3(256), 0, st, d, ms, static_cast<const TC*>(g), lp, \
+                       loss, hm, flag, cores, accum, rule, status, step)
+    if (d.core_dtype == TR_F64) {
+        if (same) TRK_APPLY(double, true);
+        else TRK_APPLY(double, false);
+    } else {
+        if (same) TRK_APPLY(float, true);
+        else TRK_APPLY(float, false);
+    }
+#undef TRK_APPLY
     return hipGetLastError();
 }
 
