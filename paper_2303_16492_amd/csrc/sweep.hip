@@ -85,46 +85,50 @@ __device__ __forceinline__ double rcp_nr(double p) {
     return __builtin_fma(y, e, y);
 }
 
-// Symmetric sweep of the 8 x 8 SPD block D8 (row-major) in registers:
-// -D8^{-1}, lower triangle packed by rows (tri8(i) + j) into Bw by lane 0.
-// Every lane runs the same arithmetic on the same data.  False on a pivot
-// that is not positive (or not finite).
+// Symmetric sweep of the 8 x 8 SPD block D8 (row-major, both triangles):
+// -D8^{-1}, lower triangle packed by rows (tri8(i) + j) into Bw.  Lane
+// 8 i + j of the wavefront holds entry (i, j).  Pivot k takes a_kk from its
+// lane and column k (c_x = entry (max(x, k), min(x, k)), lower triangle) by
+// lane permutes, then every lane updates its own entry:
+//     a_ij -= (c_i / a_kk) c_j,  a_ik <- c_i / a_kk,  a_kj <- c_j / a_kk,
+//     a_kk <- -1 / a_kk,
+// the classical symmetric sweep.  Only lower-triangle entries are read, so
+// the lanes of the lower triangle compute exactly the operations of the
+// sequential algorithm on that triangle.  False on a pivot that is not
+// positive (or not finite); every lane reaches the same verdict.
+__device__ __forceinline__ double permute_lane(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int K>
+__device__ __forceinline__ void sweep8_pivot(double& a, bool& good, int i, int j) {
+    const double p = readlane_f64(a, 9 * K);
+    const double ci = permute_lane(a, i > K ? 8 * i + K : 8 * K + i);
+    const double cj = permute_lane(a, j > K ? 8 * j + K : 8 * K + j);
+    good = good && (p > 0.0) && isfinite(p);
+    const double dk = rcp_nr(p);
+    if (i != K && j != K) a = __builtin_fma(-(ci * dk), cj, a);
+    else if (i != K) a = ci * dk;
+    else if (j != K) a = cj * dk;
+    else a = -dk;
+}
+
 __device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw) {
-    double a[8][8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j) a[i][j] = D8[i * 8 + j];
+    const int l = threadIdx.x & 63, i = l >> 3, j = l & 7;
+    double a = D8[i * 8 + j];
     bool good = true;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double p = a[k][k];
-        good = good && (p > 0.0) && isfinite(p);
-        const double dk = rcp_nr(p);
-        double col[8], c[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            col[i] = i > k ? a[i][k] : (i < k ? a[k][i] : 0.0);
-            c[i] = col[i] * dk;
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j <= i; ++j)
-                if (i != k && j != k) a[i][j] = __builtin_fma(-c[i], col[j], a[i][j]);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            if (i > k) a[i][k] = c[i];
-            if (i < k) a[k][i] = c[i];
-        }
-        a[k][k] = -dk;
-    }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j <= i; ++j) Bw[tri8(i) + j] = a[i][j];
-    }
+    sweep8_pivot<0>(a, good, i, j);
+    sweep8_pivot<1>(a, good, i, j);
+    sweep8_pivot<2>(a, good, i, j);
+    sweep8_pivot<3>(a, good, i, j);
+    sweep8_pivot<4>(a, good, i, j);
+    sweep8_pivot<5>(a, good, i, j);
+    sweep8_pivot<6>(a, good, i, j);
+    sweep8_pivot<7>(a, good, i, j);
+    if (j <= i) Bw[tri8(i) + j] = a;
     return good;
 }
 
