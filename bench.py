@@ -274,17 +274,18 @@ def plain_rate(args, prec, init3, X, I, R, m, dev, K, G=50):
     return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "dev_status": status}
 
 
-def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, cap=None):
+def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, cap=None, scaled=True, alpha=None):
     """Wall time from the initial cores until an RSE check reaches
     ``target`` (checks every ``every`` steps count toward the time), capped
-    at ``cap`` (default args.ttt_steps) steps."""
+    at ``cap`` (default args.ttt_steps) steps; the scaled method (default)
+    or the plain one, fixed step ``alpha`` (default args.alpha)."""
     import torch
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
     N = 3
-    solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law="U", scaled=True,
-                      prec=prec, rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
-                      overlap=not args.no_overlap)
+    solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law="U", scaled=scaled,
+                      prec=prec, rule=api.step_rule("fixed", alpha=args.alpha if alpha is None else alpha),
+                      seed=args.seed, overlap=not args.no_overlap)
     solver.rse()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -378,7 +379,7 @@ def main():
               "hbm_frac": round(rbytes / (rse_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
     del rcores
     print(f"[bench] relerr: {rse_us:.1f} us per RSE", file=sys.stderr, flush=True)
-    planted = []
+    planted, planted_plain = [], []
     if args.ttt_steps > 0:
         # The same method on a planted ring with Gaussian cores at the same
         # size, where the 1e-4 target is within reach of both forms.
@@ -388,6 +389,14 @@ def main():
             print(f"[bench] planted time-to-target {pr}: {planted[-1]['reached']} after {planted[-1]['steps']} "
                   f"steps, {planted[-1]['wall_s_at_stop']} s, rse {planted[-1]['rse_at_stop']:.3e}",
                   file=sys.stderr, flush=True)
+        # The plain method (the gradient on every step's critical path), fixed
+        # step 1.0, RSE every 250 steps.
+        for pr in ("f32", "bf16"):
+            planted_plain.append(time_to_target(args, pr, pinit, PX, I, R, m, dev, every=250, cap=20000,
+                                                scaled=False, alpha=1.0))
+            print(f"[bench] planted plain-method time-to-target {pr}: {planted_plain[-1]['reached']} after "
+                  f"{planted_plain[-1]['steps']} steps, {planted_plain[-1]['wall_s_at_stop']} s, "
+                  f"rse {planted_plain[-1]['rse_at_stop']:.3e}", file=sys.stderr, flush=True)
         del PX
 
     RR = R * R
@@ -409,7 +418,10 @@ def main():
         roof = {"bound": "mfma", "achieved": round(i_ach, 6), "peak": PEAK["f64"][0], "unit": "TFLOP/s",
                 "frac": round(i_ach / PEAK["f64"][0], 7), "traffic": measured_traffic("k_sweep"), "kernel": "k_sweep",
                 "kernel_avg_us": round(main["inv_us"], 3), "flops_per_launch": inv_flops,
-                "note": "one workgroup, 13 dependent 8-pivot steps: bound by its dependency chain"}
+                "one_cu_peak": round(PEAK["f64"][0] / 256, 4),
+                "one_cu_frac": round(i_ach / (PEAK["f64"][0] / 256), 4),
+                "note": "one workgroup on one CU (by design: the inverse is a chain of 13 dependent 8-pivot "
+                        "steps); one_cu_frac is against that CU's share of the FP64 peak"}
 
     batched = None
     if args.batch_steps > 0:
@@ -475,8 +487,13 @@ def main():
         "eager_steps_per_s": round(1e3 / main["eager_ms_per_step"], 2),
         "forms_plain_method": plain,
         "time_to_target": ttt,
-        "time_to_target_planted": {"workload": "planted-gaussian-n3-i400-r10", "m": m, "law": "uniform",
-                                   "alpha": args.alpha, "runs": planted},
+        "time_to_target_planted": {"workload": "planted-gaussian-n3-i400-r10", "method": "scaled", "m": m,
+                                   "law": "uniform", "alpha": args.alpha, "runs": planted},
+        "time_to_target_planted_plain": {"workload": "planted-gaussian-n3-i400-r10", "method": "plain", "m": m,
+                                         "law": "uniform", "alpha": 1.0, "runs": planted_plain,
+                                         "mixed_speedup": (round(planted_plain[0]["seconds"] / planted_plain[1]["seconds"], 4)
+                                                           if len(planted_plain) == 2 and planted_plain[0]["reached"]
+                                                           and planted_plain[1]["reached"] else None)},
         "relerr": relerr,
         "batched": batched,
         "rse_after": main["rse_after"],

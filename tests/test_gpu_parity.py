@@ -201,6 +201,30 @@ def test_scaled_update_parity(dtype, damping):
         assert int(st) == sref == 0
 
 
+@pytest.mark.parametrize("R", [[2, 2, 2], [4, 5, 3], [6, 6, 6], [7, 8, 7], [9, 9, 9], [11, 11, 11], [8, 16, 8]])
+def test_scaled_update_every_sweep_width(R):
+    """The blocked sweep at every tile count it is built for (R_n R_{n+1} from
+    4 to 128: one to eight 16 x 16 tile columns, one to sixteen 8-pivot
+    blocks, a partial last block), each mode of the ring, FP32 cores."""
+    dtype = torch.float32
+    I = [2 * max(R) + 5, 2 * max(R) + 4, 2 * max(R) + 3]
+    I, R, cores, X, dcores, dX = problem(21, 3, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+    for n in range(3):
+        RRn = R[n] * R[(n + 1) % 3]
+        m = 6 * RRn + 17
+        say("sweep width", R, "mode", n, "RR", RRn)
+        idx, pF = api.tr_sample(desc, 8, n, n, m)
+        S = api.tr_subchain(desc, n, dcores, idx, m)
+        g, loss, gram = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, L.TR_PREC_F32, want_gram=True)
+        core = dcores[n].clone()
+        st = api.tr_update(desc, n, core, g, gram=gram, rule=api.step_rule("fixed", alpha=0.7), t=0)
+        p, sref = brsgd.scaled_direction(g.double().cpu().numpy(), gram.cpu().numpy())
+        assert int(st) == sref == 0
+        cond = np.linalg.cond(gram.cpu().numpy())
+        assert rel(core.cpu().numpy(), unfold(cores[n]) + 0.7 * p) < max(TOL[dtype], 1e-15 * cond), cond
+
+
 def test_scaled_update_large_gram_global_memory_path():
     """RR = 144: the factorisation and the solves run from global memory."""
     dtype = torch.float32
