@@ -171,3 +171,63 @@ def test_trajectory_tracks_oracle_and_tuner_restores_state():
 
 def unfold_back(G2, Rk, Rk1):
     return np.ascontiguousarray(G2.reshape(G2.shape[0], Rk1, Rk).transpose(2, 0, 1))
+
+
+def test_full_batch_step_at_bench_configuration():
+    """The 64-problem workload the benchmark times (orders 3-5, sizes 16-128,
+    ranks 3-12, FP16 tensors, m = 1024, AdaGrad) in its launch configuration
+    (chunks of 64 samples, eight wavefronts): one step of all problems; the
+    smallest problem of each order is checked against the oracle, every
+    problem advances its counter with no device flag raised."""
+    inst = ti.batched_instances(0)
+    sampled = {}
+    for N in (3, 4, 5):
+        p = min((q for q, b in enumerate(inst) if b.N == N), key=lambda q: int(np.prod(inst[q].I)))
+        sampled[p] = None
+    m, eta = 1024, 0.05
+    probs, host = [], {}
+    for p, b in enumerate(inst):
+        rule = api.step_rule("adagrad", eta=eta)
+        if p in sampled:
+            (X, init, _), = build([b], m, rule_kind="adagrad", eta=eta)[1]
+            desc = api.make_desc(b.I, b.R, torch.float32, torch.float16)
+            dX = to_dev(flat_paper(X), torch.float16)
+            reps = [api.tr_x_replicate(desc, dX, n) for n in range(b.N)]
+            cores = [to_dev(unfold(c), torch.float32) for c in init]
+            host[p] = (X, init, b)
+        else:   # not checked against the oracle: a noise-free planted tensor built on the device
+            d32 = api.make_desc(b.I, b.R, torch.float32, torch.float32)
+            d16 = api.make_desc(b.I, b.R, torch.float32, torch.float16)
+            true = [to_dev(unfold(c), torch.float32) for c in ti.gaussian_cores(b.seed, b.N, b.I, b.R)]
+            X16 = api.tr_reconstruct(d32, true).half()
+            sig = (float(X16.float().pow(2).mean()) / float(np.prod(b.R))) ** (1.0 / (2 * b.N))
+            cores = [to_dev(unfold(c), torch.float32) for c in ti.gaussian_cores(b.seed + 1, b.N, b.I, b.R, scale=sig)]
+            reps = [api.tr_x_replicate(d16, X16, n) for n in range(b.N)]
+            del X16
+        probs.append(dict(cores=cores, Xrep=reps, I=b.I, R=b.R, m=m, rule=rule, seed=b.seed))
+    B = TRBatch(probs)
+    say("full batch step, sampled problems", sorted(sampled))
+    B.run(1, chunk=64, waves=8)
+    torch.cuda.synchronize()
+    assert B.t_dev.cpu().tolist() == [1] * len(inst)
+    assert int(B.status.max()) == 0
+    for p in sorted(sampled):
+        X, init, b = host[p]
+        (st, losses), = oracle_steps([host[p]], m, 1, "adagrad", eta=eta)
+        for k in range(b.N):
+            got = probs[p]["cores"][k].cpu().numpy().astype(np.float64)
+            want, base = unfold(st.cores[k]), unfold(init[k])
+            if np.linalg.norm(want - base) == 0:
+                assert np.array_equal(got, base), (p, k)
+                continue
+            # AdaGrad's first step is eta * sign(p) entrywise: an entry whose
+            # direction is below the 16-bit products' rounding may take the
+            # other sign; the rest must agree to the FP32 rounding of the sum.
+            dg, dw = got - base, want - base
+            flip = np.sign(dg) != np.sign(dw)
+            assert flip.mean() < 2e-3, (p, k, flip.mean())
+            assert rel(np.where(flip, 0.0, dg), np.where(flip, 0.0, dw)) < TOL16, (p, k)
+        assert abs(float(B.loss[p]) - losses[-1]) <= TOL16 * abs(losses[-1]), p
+    for pr in probs:
+        for c in pr["cores"]:
+            assert bool(torch.isfinite(c).all())

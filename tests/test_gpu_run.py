@@ -219,3 +219,15 @@ def test_overlapped_branch_equals_serial_bitwise(m_H):
     assert torch.equal(la, lb)
     for a, b in zip(ca, cb):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("law", ["U", "E", "L", "O"])
+def test_adagrad_run_each_law_at_full_size(law):
+    """The four-law workload at its full size: order 4, 64 per mode, ranks 5,
+    40 dB noise, FP32, m = 512, AdaGrad; a few whole steps on the GPU against
+    the FP64 oracle."""
+    say("run law full size", law)
+    sol, st, X = _run_both(4, 64, 5, torch.float32, 512, law, False, "adagrad", 6, eta=0.05)
+    assert sol.t == 6 and int(sol.status.item()) == st.status
+    for k in range(4):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-4, (law, k)
