@@ -281,7 +281,8 @@ hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, cons
 // FP64 from the stored S.  Blocks take the lower-triangular 32 x 32 tiles
 // of the RR x RR output times groups of samples: a block fetches its
 // samples' S columns and weights in one batch (FP32 S stays FP32 in LDS),
-// then each thread accumulates a 2 x 2 block.  A second kernel adds the
+// then each wavefront accumulates one 16 x 16 quadrant of the tile on the
+// FP64 matrix cores.  A second kernel adds the
 // groups in a fixed order and mirrors the lower triangle.
 
 constexpr int kGramT = 32;
@@ -318,8 +319,13 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
     const double wbase = 1.0 / ((double)m * (double)J_of(d, n));
     const int per = (m + groups - 1) / groups;
     const int fb = blockIdx.y * per, fe = min(m, fb + per);
-    const int tr_ = (tid >> 4) * 2, tc = (tid & 15) * 2;
-    double acc[2][2] = {};
+    // wavefront w computes the 16 x 16 quadrant (qr, qc) of the tile on the
+    // FP64 matrix cores, K = 4 samples per instruction (lane l: A[l % 16][l / 16],
+    // B[l / 16][l % 16], D[4 j + l / 16][l % 16])
+    const int w = tid >> 6, l = tid & 63, lc = l & 15, lk = l >> 4;
+    const int qr = w >> 1, qc = w & 1;
+    typedef double gd4 __attribute__((ext_vector_type(4)));
+    gd4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int f0 = fb; f0 < fe; f0 += kGramF) {
         __syncthreads();
         {   // every load of the chunk issued before any LDS store
@@ -345,24 +351,19 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
         }
         __syncthreads();
         const int nf = min(kGramF, fe - f0);
-        for (int f = 0; f < nf; ++f) {
-            const double w = sw[f];
-            const double a0 = (double)sA[f][tr_] * w, a1 = (double)sA[f][tr_ + 1] * w;
-            const double b0 = (double)sB[f][tc], b1 = (double)sB[f][tc + 1];
-            acc[0][0] += a0 * b0;
-            acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0;
-            acc[1][1] += a1 * b1;
+        for (int q = 0; q < nf; q += 4) {   // rows past nf were staged as zeros with weight 0
+            const int f = q + lk;
+            const double a = (double)sA[f][16 * qr + lc] * sw[f];
+            const double b = (double)sB[f][16 * qc + lc];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
     }
     double* out = part + (int64_t)blockIdx.y * maxRR2;
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int c = c0 + tr_ + u, e = e0 + tc + v;
-            if (c < RR && e < RR) out[(int64_t)c * RR + e] = acc[u][v];
-        }
+    for (int j = 0; j < 4; ++j) {
+        const int c = c0 + 16 * qr + 4 * j + lk, e = e0 + 16 * qc + lc;
+        if (c < RR && e < RR) out[(int64_t)c * RR + e] = acc[j];
+    }
     (void)tiles_max;
 }
 
@@ -401,8 +402,9 @@ GramWs gram_ws_layout(const tr_desc& d, int m) {
     const Shape sh = shape_of(d);
     const int tpd = (sh.maxRR + kGramT - 1) / kGramT;
     L.tiles = tpd * (tpd + 1) / 2;
-    // about 320 blocks, at least 16 samples per group
-    int groups = (320 + L.tiles - 1) / L.tiles;
+    // at most one block per CU (256), so that every block runs in the first
+    // and only round; at least 16 samples per group
+    int groups = 256 / L.tiles;
     const int gmax = (m + 15) / 16;
     groups = groups > gmax ? gmax : groups;
     groups = groups < 1 ? 1 : groups;
