@@ -12,10 +12,11 @@ namespace trk {
 // probabilities are multiplied per sample in the order n+1, ..., n-1.
 // Phase 2: the N-1 core slices of every sample are copied to LDS in one
 // batch (a slice G_k(i) is row i of G_k(2): R_k R_{k+1} contiguous values).
-// Phase 3: the chain products M <- M G_k(i_k), one output entry per thread
-// at a time, the last product written straight to S[f][r + R_n s] = M_f(s, r)
-// (consecutive threads, consecutive columns).  Products accumulate in the
-// core dtype with the inner index ascending.
+// Phase 3: the chain products M <- M G_k(i_k), the last product written
+// straight to S[f][r + R_n s] = M_f(s, r): for FP32 cores one wavefront per
+// sample on the matrix cores; for FP64 one output entry per thread at a time
+// (consecutive threads, consecutive columns), accumulated in FP64 with the
+// inner index ascending.
 template <typename TC>
 __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, int m, int SB, CdfPtrs cdf,
                                                          const uint64_t* __restrict__ cdf_J, int stream_tag,
@@ -165,6 +166,54 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
         }
         return;
     }
+    if constexpr (sizeof(TC) == 4) {
+        // FP32: one wavefront per sample (samples wv, wv + 4, ...): M <- M A_q
+        // as a zero-padded 16 x 16 tile on the matrix cores (K = R_k in four
+        // steps of 4); an intermediate M goes back through the wavefront's
+        // LDS tile to become the next A operand.  Operand layouts of
+        // v_mfma_f32_16x16x4_f32 (lane l): A[l % 16][l / 16], B[l / 16][l % 16],
+        // D[4 (l / 16) + j][l % 16].
+        typedef float sf4 __attribute__((ext_vector_type(4)));
+        const int wv = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+        // product tiles after the slices (and after the FP64 path's product
+        // buffers, which exist for N > 3 only)
+        float* Mw = reinterpret_cast<float*>(bufA + (N > 3 ? 2 * (size_t)SB * P2 : 0)) + wv * 256;
+        for (int fl = wv; fl < nb; fl += (int)(blockDim.x >> 6)) {
+            const float* base = reinterpret_cast<const float*>(sl) + (size_t)fl * per;
+            sf4 mv = {0.f, 0.f, 0.f, 0.f};
+            for (int q = 1; q < N - 1; ++q) {
+                const int k = (n + 1 + q) % N, Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
+                const float* Aq = base + soff[q];
+                sf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int kk = 4 * ks + lk;
+                    float a;
+                    if (q == 1) a = (lr < Rn1 && kk < Rk) ? base[lr + Rn1 * kk] : 0.f;   // first slice, row lr
+                    else a = Mw[lr * 16 + kk];
+                    const float b = (kk < Rk && lr < Rk1) ? Aq[kk + Rk * lr] : 0.f;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+                }
+                mv = acc;
+                if (q + 1 < N - 1) {   // D rows 4 lk + j, column lr
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) Mw[(4 * lk + j) * 16 + lr] = mv[j];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {   // S(f, r + R_n s) = M_f(s, r), s = 4 lk + j, r = lr
+                const int srow = 4 * lk + j;
+                if (srow < Rn1 && lr < Rn)
+                    S[(int64_t)(f0 + fl) * RR + lr + Rn * srow] = sok[fl] ? (TC)mv[j] : TC(NAN);
+            }
+        }
+        return;
+    }
     const TC* Mc = nullptr;     // current product; null: the first slice
     int cols = d.R[ring_next(n1, N)];
     for (int q = 1; q < N - 1; ++q) {
@@ -200,7 +249,7 @@ static int sample_block(const tr_desc& d, const Shape& sh, size_t es, size_t* ld
     int SB = (int)((48 * 1024) / need);
     SB = SB < 1 ? 1 : (SB > 16 ? 16 : SB);
     *lds = (size_t)SB * kMaxOrder * 12 + (size_t)((SB + 3) & ~3) * 4 + 16 +
-           ((size_t)SB * per + (size_t)SB * prod) * es;
+           ((size_t)SB * per + (size_t)SB * prod) * es + (es == 4 ? 4 * 256 * 4 : 0);   // FP32: product tiles
     return SB;
 }
 
