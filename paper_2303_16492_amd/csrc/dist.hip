@@ -60,7 +60,7 @@ __global__ __launch_bounds__(1024) void k_dist_euclid(tr_desc d, ModeSrc ms, int
     const TC* G = static_cast<const TC*>(cores.p[k]);
     uint64_t* w = static_cast<uint64_t*>(cdf_out.p[k]);
     double* rn = reinterpret_cast<double*>(w);   // row norms staged in the output
-    double loc = 0.0;
+    double loc = 0.0;   // this thread's rows, then a fixed-order block sum
     for (int i = threadIdx.x; i < Ik; i += blockDim.x) {
         double s = 0.0;
         for (int c = 0; c < RR; ++c) {
@@ -68,17 +68,10 @@ __global__ __launch_bounds__(1024) void k_dist_euclid(tr_desc d, ModeSrc ms, int
             s += v * v;
         }
         rn[i] = s;
+        loc += s;
     }
-    __syncthreads();
-    __shared__ double tot_s;
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < Ik; ++i) s += rn[i];
-        tot_s = s;
-    }
-    __syncthreads();
-    const double tot = tot_s;
-    (void)loc;
+    __shared__ double red[16];
+    const double tot = block_sum(loc, red);
     if (!(tot > 0.0) || !isfinite(tot)) {
         if (threadIdx.x == 0) set_status(status, TR_DEV_ZERO_DIST);
         write_uniform_weights(w, Ik);
@@ -161,6 +154,172 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
     block_scan_u64(w, Ik);
 }
 
+// The same law for R_k R_{k+1} <= 128 with the factor kept in LDS (one
+// block of 1024 threads): (1) the lower triangle of A = G^T G, rows of G
+// staged through LDS in chunks, every entry summed over i ascending; (2)
+// right-looking Cholesky A = L L^T; (3) L^{-1} in place, column by column
+// from the last (column j below the diagonal is -(1/L_jj) L22^{-1} L(j+1:, j)
+// with L22^{-1} already formed); (4) l_i = ||L^{-1} g_i||^2, the rows of G
+// staged again, each row's RR entries of L^{-1} g_i split over a group of
+// threads and their squares summed by a shuffle reduction.
+constexpr int kLevThreads = 1024;
+
+static int lev_chunk_rows(int RR, int es) {
+    // the block scan's 8 KiB and a few words of static LDS come on top
+    const int budget = 160 * 1024 - 8192 - 1024 - RR * RR * 8 - RR * 8;
+    int cr = budget / (RR * es);
+    cr = cr > 64 ? 64 : cr;
+    return cr < 1 ? 1 : cr;
+}
+
+template <typename TC>
+__global__ __launch_bounds__(kLevThreads) void k_dist_leverage_lds(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
+                                                                  Ptrs cores, MutPtrs cdf_out, int32_t* status,
+                                                                  int CR) {
+    uint64_t t;
+    int k = k_fixed;
+    if (use_mode) resolve_mode(ms, d.N, &t, &k);
+    const int Ik = d.I[k];
+    const int RR = d.R[k] * d.R[ring_next(k, d.N)];
+    const TC* G = static_cast<const TC*>(cores.p[k]);
+    uint64_t* w = static_cast<uint64_t*>(cdf_out.p[k]);
+    double* lev = reinterpret_cast<double*>(w);
+    const int tid = threadIdx.x;
+    if (Ik <= RR) {   // full row rank taken: every leverage score is 1
+        write_uniform_weights(w, Ik);
+        block_scan_u64(w, Ik);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sA = reinterpret_cast<double*>(smem_raw);   // RR x RR, column-major, lower triangle
+    double* scol = sA + RR * RR;                         // [RR]
+    TC* sG = reinterpret_cast<TC*>(scol + RR);          // [CR][RR], rows of G in the core dtype
+    __shared__ int bad;
+
+    // (1) Gram, lower triangle; entry q of the column-major lower triangle is
+    // (a, b), a >= b, accumulated in place over the chunks of rows
+    const int ntri = RR * (RR + 1) / 2;
+    auto tri = [&](int q, int& ra, int& cb) {
+        // column: the largest c with c RR - c (c - 1) / 2 <= q
+        const double t2 = 2.0 * RR + 1.0;
+        int c = (int)((t2 - sqrt(t2 * t2 - 8.0 * q)) * 0.5);
+        c = c < 0 ? 0 : (c >= RR ? RR - 1 : c);
+        while (c > 0 && c * RR - c * (c - 1) / 2 > q) --c;
+        while (c + 1 < RR && (c + 1) * RR - (c + 1) * c / 2 <= q) ++c;
+        cb = c;
+        ra = c + (q - (c * RR - c * (c - 1) / 2));
+    };
+    for (int q = tid; q < ntri; q += kLevThreads) {
+        int ra, cb;
+        tri(q, ra, cb);
+        sA[ra + RR * cb] = 0.0;
+    }
+    for (int r0 = 0; r0 < Ik; r0 += CR) {
+        const int nr = min(CR, Ik - r0);
+        __syncthreads();
+        for (int e = tid; e < nr * RR; e += kLevThreads) sG[e] = G[(int64_t)r0 * RR + e];
+        __syncthreads();
+        for (int q = tid; q < ntri; q += kLevThreads) {
+            int ra, cb;
+            tri(q, ra, cb);
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four chains hide the LDS latency
+            int r = 0;
+            for (; r + 3 < nr; r += 4) {
+                s0 += (double)sG[r * RR + ra] * (double)sG[r * RR + cb];
+                s1 += (double)sG[(r + 1) * RR + ra] * (double)sG[(r + 1) * RR + cb];
+                s2 += (double)sG[(r + 2) * RR + ra] * (double)sG[(r + 2) * RR + cb];
+                s3 += (double)sG[(r + 3) * RR + ra] * (double)sG[(r + 3) * RR + cb];
+            }
+            for (; r < nr; ++r) s0 += (double)sG[r * RR + ra] * (double)sG[r * RR + cb];
+            sA[ra + RR * cb] += (s0 + s1) + (s2 + s3);
+        }
+    }
+    if (tid == 0) bad = 0;
+    // (2) Cholesky
+    for (int j = 0; j < RR; ++j) {
+        __syncthreads();
+        const double djj = sA[j + RR * j];
+        if (!(djj > 0.0) || !isfinite(djj)) {
+            if (tid == 0) bad = 1;
+            break;
+        }
+        const double ljj = sqrt(djj);
+        __syncthreads();
+        for (int i = j + tid; i < RR; i += kLevThreads) sA[i + RR * j] = i == j ? ljj : sA[i + RR * j] / ljj;
+        __syncthreads();
+        const int wd = RR - j - 1;
+        for (int e = tid; e < wd * wd; e += kLevThreads) {
+            const int i = j + 1 + e % wd, c = j + 1 + e / wd;
+            if (c <= i) sA[i + RR * c] -= sA[i + RR * j] * sA[c + RR * j];
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) set_status(status, TR_DEV_NOT_SPD);
+        write_uniform_weights(w, Ik);
+        block_scan_u64(w, Ik);
+        return;
+    }
+    // (3) L^{-1} in place
+    for (int j = RR - 1; j >= 0; --j) {
+        for (int i = j + 1 + tid; i < RR; i += kLevThreads) scol[i] = sA[i + RR * j];
+        __syncthreads();
+        const double dj = 1.0 / sA[j + RR * j];
+        double x = 0.0;
+        const int i = j + 1 + tid;
+        if (i < RR) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int c = j + 1;
+            for (; c + 3 <= i; c += 4) {
+                s0 += sA[i + RR * c] * scol[c];
+                s1 += sA[i + RR * (c + 1)] * scol[c + 1];
+                s2 += sA[i + RR * (c + 2)] * scol[c + 2];
+                s3 += sA[i + RR * (c + 3)] * scol[c + 3];
+            }
+            for (; c <= i; ++c) s0 += sA[i + RR * c] * scol[c];
+            x = -dj * ((s0 + s1) + (s2 + s3));
+        }
+        __syncthreads();
+        if (i < RR) sA[i + RR * j] = x;
+        if (tid == 0) sA[j + RR * j] = dj;
+    }
+    __syncthreads();
+    // (4) leverage scores, TPR threads per row
+    int TPR = 8;   // threads per row: rows per round = 1024 / TPR <= CR (CR >= 16 for RR <= 128)
+    while (TPR < 64 && TPR * CR < kLevThreads) TPR <<= 1;
+    const int RPB = kLevThreads / TPR;
+    for (int r0 = 0; r0 < Ik; r0 += RPB) {
+        const int nr = min(RPB, Ik - r0);
+        __syncthreads();
+        for (int e = tid; e < nr * RR; e += kLevThreads) sG[e] = G[(int64_t)r0 * RR + e];
+        __syncthreads();
+        const int rl = tid / TPR, sub = tid - rl * TPR;
+        double s2 = 0.0;
+        if (rl < nr) {
+            const TC* g = sG + rl * RR;
+            for (int j = sub; j < RR; j += TPR) {
+                double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+                int c = 0;
+                for (; c + 3 <= j; c += 4) {
+                    v0 += sA[j + RR * c] * (double)g[c];
+                    v1 += sA[j + RR * (c + 1)] * (double)g[c + 1];
+                    v2 += sA[j + RR * (c + 2)] * (double)g[c + 2];
+                    v3 += sA[j + RR * (c + 3)] * (double)g[c + 3];
+                }
+                for (; c <= j; ++c) v0 += sA[j + RR * c] * (double)g[c];
+                const double v = (v0 + v1) + (v2 + v3);
+                s2 += v * v;
+            }
+        }
+        for (int o = TPR >> 1; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+        if (rl < nr && sub == 0) lev[r0 + rl] = s2;
+    }
+    __syncthreads();
+    for (int i = tid; i < Ik; i += kLevThreads) w[i] = quantize(lev[i] / (double)RR);
+    __syncthreads();
+    block_scan_u64(w, Ik);
+}
+
 size_t dist_ws_bytes(const tr_desc& d, int law) {
     const Shape sh = shape_of(d);
     return law == TR_LAW_LEVERAGE ? align_up((size_t)sh.maxRR * sh.maxRR * 8) : 256;
@@ -178,6 +337,20 @@ hipError_t launch_dist(const tr_desc& d, ModeSrc ms, bool use_mode, int k, int l
         else
             hipLaunchKernelGGL(k_dist_euclid<float>, dim3(1), dim3(1024), 0, st, d, ms, (int)use_mode, k, cores,
                                out, status);
+    } else if (law == TR_LAW_LEVERAGE && shape_of(d).maxRR <= 128) {
+        const int RR = use_mode ? shape_of(d).maxRR : d.R[k] * d.R[(k + 1) % d.N];
+        const int es = f64 ? 8 : 4;
+        const int CR = lev_chunk_rows(RR, es);
+        const size_t shm = (size_t)RR * RR * 8 + (size_t)RR * 8 + (size_t)CR * RR * es;
+#define TRK_LEV(TC)                                                                                         \
+    do {                                                                                                    \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_dist_leverage_lds<TC>), shm)) return hipErrorInvalidValue; \
+        hipLaunchKernelGGL(k_dist_leverage_lds<TC>, dim3(1), dim3(kLevThreads), shm, st, d, ms, (int)use_mode, k,  \
+                           cores, out, status, CR);                                                         \
+    } while (0)
+        if (f64) TRK_LEV(double);
+        else TRK_LEV(float);
+#undef TRK_LEV
     } else if (law == TR_LAW_LEVERAGE) {
         double* A = static_cast<double*>(ws);
         if (f64)

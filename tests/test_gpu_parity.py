@@ -289,6 +289,23 @@ def test_product_laws_parity(dtype, law):
         assert int(st) == 0
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("I,R", [([400, 30, 20], [10, 10, 10]), ([300, 20, 40], [8, 16, 8]),
+                                 ([130, 50, 9], [7, 11, 3])])
+def test_leverage_law_wide_cores(I, R, dtype):
+    """The leverage law where the factor stays in LDS (R_k R_{k+1} up to 128),
+    including a core with I_k < R_k R_{k+1} (uniform by the closed form)."""
+    I, R, cores, X, dcores, dX = problem(17, 3, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+    for k in range(3):
+        say("leverage law", I, R, dtype, k)
+        cdf, st = api.tr_dist(desc, k, L.TR_LAW_LEVERAGE, dcores[k])
+        w = np.diff(np.concatenate([[0], cdf.cpu().numpy().astype(np.uint64)]))
+        wref = sampling.quantize(sampling.dist_leverage(cores[k]))
+        assert np.max(np.abs(w.astype(np.int64) - wref.astype(np.int64))) <= 64
+        assert int(st) == 0
+
+
 def test_optimal_law_parity():
     dtype = torch.float64
     I, R, cores, X, dcores, dX = problem(8, 3, [9, 7, 8], [2, 3, 2], dtype)
