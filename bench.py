@@ -274,6 +274,33 @@ def plain_rate(args, prec, init3, X, I, R, m, dev, K, G=50):
     return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "dev_status": status}
 
 
+def law_rate(args, law, init3, X, I, R, m, dev, K, G=50):
+    """Steps/s of the scaled FP32 step with fibers drawn under ``law`` (E or
+    L), including the refresh of the updated core's law after every step;
+    K steps replayed from a HIP graph of G steps."""
+    import torch
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    N = 3
+    solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law=law, scaled=True,
+                      prec="f32", rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
+                      overlap=not args.no_overlap)
+    solver.run(10)
+    graph = solver.capture(G)
+    graph.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(K // G):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / K
+    status = int(solver.status.item())
+    del graph, solver
+    return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "dev_status": status}
+
+
 def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, cap=None, scaled=True, alpha=None):
     """Wall time from the initial cores until an RSE check reaches
     ``target`` (checks every ``every`` steps count toward the time), capped
@@ -357,6 +384,8 @@ def main():
     alt = timed_run(args, other, init3, X, I, R, m, dev, K, args.warmup)
     print(f"[bench] {other}: {alt['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
     plain = {pr: plain_rate(args, pr, init3, X, I, R, m, dev, K) for pr in ("f32", "bf16")}
+    laws = {lw: law_rate(args, lw, init3, X, I, R, m, dev, 500) for lw in ("E", "L")}
+    print(f"[bench] scaled step under the Euclidean and leverage laws: {laws}", file=sys.stderr, flush=True)
     print(f"[bench] plain method: {plain}", file=sys.stderr, flush=True)
     ttt = []
     if args.ttt_steps > 0:
@@ -431,7 +460,8 @@ def main():
         B, insts = build_batch(args.seed, dev)
         torch.cuda.synchronize()
         tune = B.tune(steps=3, reps=2)
-        print(f"[bench] batch tuned: {tune} -> chunk {B.chunk}, waves {B.waves}", file=sys.stderr, flush=True)
+        print(f"[bench] batch tuned: {tune} -> chunk {B.chunk}, waves {B.waves}, splits {B.splits}",
+              file=sys.stderr, flush=True)
         B.run(2)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -443,8 +473,8 @@ def main():
         batched = {"workload": "batched-64-planted-fp16", "problems": B.count, "m": 1024,
                    "steps": args.batch_steps, "ms_per_batch_step": round(ms, 5),
                    "problem_steps_per_s": round(B.count * 1e3 / ms, 1),
-                   "tiles": {"chunk": B.chunk, "waves": B.waves},
-                   "tuner_ms_per_step": {f"{c}x{w}": round(v, 5) for (c, w), v in tune.items()},
+                   "tiles": {"chunk": B.chunk, "waves": B.waves, "splits": B.splits},
+                   "tuner_ms_per_step": {f"{c}x{w}x{sp}": round(v, 5) for (c, w, sp), v in tune.items()},
                    "precision": "fp16 matrix cores, fp32 accumulation, fp64 loss",
                    "mean_loss_estimate": float(B.loss.mean()), "dev_status_or": int(B.status.max())}
         print(f"[bench] batch: {ms * 1e3:.1f} us per step of all 64 problems", file=sys.stderr, flush=True)
@@ -486,6 +516,7 @@ def main():
                   "gradient kernels over 200 eager steps of the same run, on the streams they run on",
         "eager_steps_per_s": round(1e3 / main["eager_ms_per_step"], 2),
         "forms_plain_method": plain,
+        "forms_laws": laws,
         "time_to_target": ttt,
         "time_to_target_planted": {"workload": "planted-gaussian-n3-i400-r10", "method": "scaled", "m": m,
                                    "law": "uniform", "alpha": args.alpha, "runs": planted},

@@ -384,6 +384,19 @@ tr_status tr_batch_upload(const tr_batch_item* items, int32_t count, void* table
 tr_status tr_batch_run(const void* table, int32_t count, int32_t steps, int32_t chunk, int32_t waves,
                        tr_stream_t stream);
 
+/* The same steps with every problem's samples split over ``splits``
+ * workgroups (1..16): per step one launch computes the partial gradients
+ * and loss sums of all (problem, share) pairs into ``ws`` and a second adds
+ * the shares in share order and takes each problem's step, so a batch of
+ * fewer problems than compute units still fills the device.  The draws,
+ * hence the sampled fibers, are those of tr_batch_run; only the order in
+ * which the gradient's FP32 partial sums are added differs.  ``ws``:
+ * caller-allocated device workspace of tr_batch_split_workspace_size bytes,
+ * 256-byte aligned, contents not preserved.  Graph-capturable. */
+size_t tr_batch_split_workspace_size(int32_t count, int32_t splits);
+tr_status tr_batch_run_split(const void* table, int32_t count, int32_t steps, int32_t chunk, int32_t waves,
+                             int32_t splits, void* ws, size_t ws_bytes, tr_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

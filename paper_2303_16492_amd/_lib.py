@@ -136,6 +136,8 @@ _SIGS = {
     "tr_batch_table_size": (SZ, [I32]),
     "tr_batch_upload": (I32, [C.POINTER(tr_batch_item), I32, VP, SZ, VP]),
     "tr_batch_run": (I32, [VP, I32, I32, I32, I32, VP]),
+    "tr_batch_split_workspace_size": (SZ, [I32, I32]),
+    "tr_batch_run_split": (I32, [VP, I32, I32, I32, I32, I32, VP, SZ, VP]),
     "tr_entry_fwd": (I32, [PDESC, PVP, VP, VP, I32, VP, VP, VP, SZ, VP]),
     "tr_entry_bwd": (I32, [PDESC, PVP, VP, VP, I32, F64, VP, PVP, VP, SZ, VP]),
     "tr_entry_workspace_size": (SZ, [PDESC, I32]),

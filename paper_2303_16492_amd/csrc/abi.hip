@@ -574,6 +574,24 @@ tr_status tr_batch_upload(const tr_batch_item* items, int32_t count, void* table
                                      (hipStream_t)stream));
 }
 
+size_t tr_batch_split_workspace_size(int32_t count, int32_t splits) {
+    if (count < 1 || count > 65535 || splits < 1 || splits > 16) return 0;
+    return batch_split_ws_bytes(count, splits);
+}
+
+tr_status tr_batch_run_split(const void* table, int32_t count, int32_t steps, int32_t chunk, int32_t waves,
+                             int32_t splits, void* ws, size_t ws_bytes, tr_stream_t stream) {
+    if (!table || count < 1 || count > 65535 || steps < 0) return TR_E_ARG;
+    if (!((chunk == 32 || chunk == 64) && (waves == 4 || waves == 8))) return TR_E_ARG;
+    if (splits < 1 || splits > 16) return TR_E_ARG;
+    if (!aligned(table, 256)) return TR_E_ALIGN;
+    if (!ws || ws_bytes < batch_split_ws_bytes(count, splits)) return TR_E_WORKSPACE;
+    if (!aligned(ws, 256)) return TR_E_ALIGN;
+    if (steps == 0) return TR_OK;
+    return hip_status(launch_batch_split(static_cast<const tr_batch_item*>(table), count, steps, chunk, waves, splits,
+                                         ws, (hipStream_t)stream));
+}
+
 tr_status tr_batch_run(const void* table, int32_t count, int32_t steps, int32_t chunk, int32_t waves,
                        tr_stream_t stream) {
     if (!table || count < 1 || count > 65535 || steps < 0) return TR_E_ARG;

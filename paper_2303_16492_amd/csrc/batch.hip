@@ -43,8 +43,18 @@ struct BatchLds {
     static constexpr size_t total = o_off + (size_t)CH * 8 + 64;
 };
 
-template <int CH, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item* __restrict__ items, int steps) {
+// SPLIT: one step of one sample range: workgroup b takes problem b / splits
+// and the b % splits-th share of its chunks of samples, and writes its
+// partial gradient (FP32, g[i * RR + c] at gpart + b * gstride) and its
+// partial loss sum (lpart[b]) instead of updating the core; k_batch_apply
+// then adds the shares and takes the step.  Otherwise workgroup b owns
+// problem b for all ``steps`` steps.
+template <int CH, int WAVES, bool SPLIT>
+__global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item* __restrict__ items, int steps,
+                                                            int splits, float* __restrict__ gpart,
+                                                            double* __restrict__ lpart, int64_t gstride) {
+    const int prob = SPLIT ? (int)blockIdx.x / splits : (int)blockIdx.x;
+    const int share = SPLIT ? (int)blockIdx.x - prob * splits : 0;
     using Lz = BatchLds<CH>;
     constexpr int NT = 64 * WAVES;
     constexpr int RTW = 8 / WAVES;                           // row tiles of E per wavefront
@@ -55,7 +65,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
     // dependent load per use.
     __shared__ __align__(16) tr_batch_item it;
     {
-        const int* src = reinterpret_cast<const int*>(items + blockIdx.x);
+        const int* src = reinterpret_cast<const int*>(items + prob);
         int* dst = reinterpret_cast<int*>(&it);
         for (int i = threadIdx.x; i < (int)(sizeof(tr_batch_item) / 4); i += blockDim.x) dst[i] = src[i];
         __syncthreads();
@@ -116,7 +126,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
 #pragma unroll
         for (int q = 0; q < GSL; ++q) gacc[q] = f32x4b{0.f, 0.f, 0.f, 0.f};
         double lsum = 0.0;
-        for (int f0 = 0; f0 < m; f0 += CH) {
+        int fbeg = 0, fend = m;
+        if (SPLIT) {   // this workgroup's share of the chunks
+            const int nch = (m + CH - 1) / CH, cps = (nch + splits - 1) / splits;
+            fbeg = min(m, share * cps * CH);
+            fend = min(m, (share + 1) * cps * CH);
+        }
+        for (int f0 = fbeg; f0 < fend; f0 += CH) {
             const int nb = min(CH, m - f0);
             __syncthreads();   // previous chunk done with S, E, indices; qoff written
             for (int w = tid; w < nb * (N - 1); w += NT) {
@@ -286,6 +302,24 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
                 }
             }
         }
+        if (SPLIT) {   // hand the partial sums to k_batch_apply
+            float* gp = gpart + (int64_t)blockIdx.x * gstride;
+#pragma unroll
+            for (int q = 0; q < GSL; ++q) {
+                const int T = wv + WAVES * q;
+                if (T < MT * CT) {
+                    const int rt = T / CT, ct = T - rt * CT;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = 16 * rt + 4 * lk + j, c = 16 * ct + lr;
+                        if (i < In && c < RR) gp[(int64_t)i * RR + c] = gacc[q][j];
+                    }
+                }
+            }
+            const double ls = block_sum(lsum, red);
+            if (tid == 0) lpart[blockIdx.x] = ls;
+            return;
+        }
         // p = g / m on this wavefront's tiles, then the rule
         float* G = static_cast<float*>(it.cores[n]);
         float* A = static_cast<float*>(it.accum[n]);
@@ -314,14 +348,79 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
     if (tid == 0) *it.t_dev = t;
 }
 
+// The step of problem p after a split gradient: g = sum of the shares in
+// share order, p = g / m (the sign of the direction folded in, as in the
+// unsplit kernel), the rule on the core, the loss estimate, t + 1.
+__global__ __launch_bounds__(256) void k_batch_apply(const tr_batch_item* __restrict__ items, int splits,
+                                                     const float* __restrict__ gpart,
+                                                     const double* __restrict__ lpart, int64_t gstride) {
+    const tr_batch_item& it = items[blockIdx.x];
+    const tr_desc& d = it.desc;
+    const uint64_t t = *it.t_dev;
+    const int N = d.N;
+    const int n = pick_mode(it.seed, t, N);
+    const int In = d.I[n], RR = d.R[n] * d.R[ring_next(n, N)];
+    const int m = it.m;
+    const float invm = 1.f / (float)m;
+    float* G = static_cast<float*>(it.cores[n]);
+    float* A = static_cast<float*>(it.accum[n]);
+    const float* gp = gpart + (int64_t)blockIdx.x * splits * gstride;
+    for (int e = threadIdx.x; e < In * RR; e += blockDim.x) {
+        float g = 0.f;
+        for (int q = 0; q < splits; ++q) g += gp[(int64_t)q * gstride + e];
+        apply_rule<float>(G, A, e, (double)(g * invm), it.rule, t, it.dev_status);
+    }
+    if (threadIdx.x == 0) {
+        double ls = 0.0;
+        for (int q = 0; q < splits; ++q) ls += lpart[(int64_t)blockIdx.x * splits + q];
+        if (it.loss) *it.loss = ls * (double)J_of(d, n) / (2.0 * (double)m);
+    }
+    __syncthreads();   // every thread has read t
+    if (threadIdx.x == 0) *it.t_dev = t + 1;
+}
+
 size_t batch_lds_bytes(int chunk) { return chunk == 32 ? BatchLds<32>::total : BatchLds<64>::total; }
+
+size_t batch_split_ws_bytes(int count, int splits) {
+    return align_up((size_t)count * splits * kBatchMaxI * kBatchMaxRR * 4) + align_up((size_t)count * splits * 8);
+}
+
+hipError_t launch_batch_split(const tr_batch_item* items, int count, int steps, int chunk, int waves, int splits,
+                              void* ws, hipStream_t st) {
+    const int64_t gstride = (int64_t)kBatchMaxI * kBatchMaxRR;
+    float* gpart = static_cast<float*>(ws);
+    double* lpart = reinterpret_cast<double*>(static_cast<char*>(ws) +
+                                              align_up((size_t)count * splits * gstride * 4));
+#define TRK_BSPLIT(CH, W)                                                                                   \
+    do {                                                                                                    \
+        const size_t shm = BatchLds<CH>::total;                                                            \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_batch_steps<CH, W, true>), shm))                  \
+            return hipErrorInvalidValue;                                                                    \
+        hipLaunchKernelGGL((k_batch_steps<CH, W, true>), dim3(count * splits), dim3(64 * W), shm, st, items, 1, \
+                           splits, gpart, lpart, gstride);                                                  \
+    } while (0)
+    for (int s = 0; s < steps; ++s) {
+        if (chunk == 32 && waves == 4) TRK_BSPLIT(32, 4);
+        else if (chunk == 32 && waves == 8) TRK_BSPLIT(32, 8);
+        else if (chunk == 64 && waves == 4) TRK_BSPLIT(64, 4);
+        else if (chunk == 64 && waves == 8) TRK_BSPLIT(64, 8);
+        else return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_batch_apply, dim3(count), dim3(256), 0, st, items, splits, gpart, lpart, gstride);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+#undef TRK_BSPLIT
+    return hipSuccess;
+}
 
 hipError_t launch_batch_steps(const tr_batch_item* items, int count, int steps, int chunk, int waves, hipStream_t st) {
 #define TRK_BATCH(CH, W)                                                                                  \
     do {                                                                                                  \
         const size_t shm = BatchLds<CH>::total;                                                          \
-        if (!allow_lds(reinterpret_cast<const void*>(&k_batch_steps<CH, W>), shm)) return hipErrorInvalidValue; \
-        hipLaunchKernelGGL((k_batch_steps<CH, W>), dim3(count), dim3(64 * W), shm, st, items, steps);      \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_batch_steps<CH, W, false>), shm)) return hipErrorInvalidValue; \
+        hipLaunchKernelGGL((k_batch_steps<CH, W, false>), dim3(count), dim3(64 * W), shm, st, items, steps, 1,   \
+                           nullptr, nullptr, (int64_t)0);                                                 \
     } while (0)
     if (chunk == 32 && waves == 4) TRK_BATCH(32, 4);
     else if (chunk == 32 && waves == 8) TRK_BATCH(32, 8);

@@ -139,6 +139,9 @@ hipError_t launch_bump(uint64_t* t_dev, hipStream_t st);
 // a11: batched independent problems.
 size_t batch_lds_bytes(int chunk);
 hipError_t launch_batch_steps(const tr_batch_item* items, int count, int steps, int chunk, int waves, hipStream_t st);
+size_t batch_split_ws_bytes(int count, int splits);
+hipError_t launch_batch_split(const tr_batch_item* items, int count, int steps, int chunk, int waves, int splits,
+                              void* ws, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 
 }  // namespace trk

@@ -125,6 +125,7 @@ class TRBatch:
     loss estimates and status words."""
 
     VARIANTS = ((32, 4), (32, 8), (64, 4), (64, 8))
+    SPLITS = (1, 4)
 
     def __init__(self, problems, device="cuda"):
         self.count = len(problems)
@@ -153,11 +154,25 @@ class TRBatch:
         self.table = api.workspace(L.lib().tr_batch_table_size(self.count), device)
         api.check("tr_batch_upload", L.lib().tr_batch_upload(items, self.count, C.c_void_p(self.table.data_ptr()),
                                                              self.table.numel(), api._stream()))
-        self.chunk, self.waves = 64, 4
+        self.chunk, self.waves, self.splits = 64, 4, 1
+        self.split_ws = {}
 
-    def run(self, steps: int, chunk=None, waves=None):
-        api.check("tr_batch_run", L.lib().tr_batch_run(C.c_void_p(self.table.data_ptr()), self.count, steps,
-                                                       chunk or self.chunk, waves or self.waves, api._stream()))
+    def run(self, steps: int, chunk=None, waves=None, splits=None):
+        """``steps`` steps of every problem; splits > 1 spreads each problem's
+        samples over that many workgroups (two launches per step)."""
+        chunk, waves = chunk or self.chunk, waves or self.waves
+        splits = splits or self.splits
+        if splits == 1:
+            api.check("tr_batch_run", L.lib().tr_batch_run(C.c_void_p(self.table.data_ptr()), self.count, steps,
+                                                           chunk, waves, api._stream()))
+            return
+        if splits not in self.split_ws:
+            self.split_ws[splits] = api.workspace(L.lib().tr_batch_split_workspace_size(self.count, splits),
+                                                  self.table.device)
+        ws = self.split_ws[splits]
+        api.check("tr_batch_run_split", L.lib().tr_batch_run_split(
+            C.c_void_p(self.table.data_ptr()), self.count, steps, chunk, waves, splits, C.c_void_p(ws.data_ptr()),
+            ws.numel(), api._stream()))
 
     def _state(self):
         cores = [[c.clone() for c in pr["cores"]] for pr in self.problems]
@@ -178,24 +193,25 @@ class TRBatch:
         self.status.copy_(status)
 
     def tune(self, steps: int = 3, reps: int = 2):
-        """Time every (chunk, waves) variant on this batch and keep the
-        fastest; the problems' state is restored afterwards.  Returns
+        """Time every (chunk, waves, splits) variant on this batch and keep
+        the fastest; the problems' state is restored afterwards.  Returns
         {variant: ms per step}."""
         saved = self._state()
         times = {}
-        for ch, wv in self.VARIANTS:
-            self.run(1, ch, wv)                      # warm-up (module load, caches)
-            torch.cuda.synchronize()
-            best = float("inf")
-            for _ in range(reps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                self.run(steps, ch, wv)
-                b.record()
+        for sp in self.SPLITS:
+            for ch, wv in self.VARIANTS:
+                self.run(1, ch, wv, sp)                  # warm-up (module load, caches)
                 torch.cuda.synchronize()
-                best = min(best, a.elapsed_time(b) / steps)
-            times[(ch, wv)] = best
+                best = float("inf")
+                for _ in range(reps):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    self.run(steps, ch, wv, sp)
+                    b.record()
+                    torch.cuda.synchronize()
+                    best = min(best, a.elapsed_time(b) / steps)
+                times[(ch, wv, sp)] = best
         self._restore(saved)
         torch.cuda.synchronize()
-        self.chunk, self.waves = min(times, key=times.get)
+        self.chunk, self.waves, self.splits = min(times, key=times.get)
         return times

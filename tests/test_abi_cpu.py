@@ -165,6 +165,14 @@ def test_batch_upload_rejects_bad_items_before_any_device_call():
         assert h.tr_batch_run(table, 1, 1, 48, 4, None) == -1              # chunk not offered
         assert h.tr_batch_run(table, 1, 1, 64, 6, None) == -1              # waves not offered
         assert h.tr_batch_run(C.c_void_p((1 << 20) + 8), 1, 1, 64, 4, None) == -4
+        wsz = h.tr_batch_split_workspace_size(1, 4)
+        assert wsz > 0 and h.tr_batch_split_workspace_size(1, 17) == 0
+        ws = C.c_void_p(1 << 24)
+        assert h.tr_batch_run_split(table, 1, 1, 64, 4, 0, ws, wsz, None) == -1       # splits 1..16
+        assert h.tr_batch_run_split(table, 1, 1, 64, 4, 17, ws, wsz, None) == -1
+        assert h.tr_batch_run_split(table, 1, 1, 48, 4, 4, ws, wsz, None) == -1       # chunk not offered
+        assert h.tr_batch_run_split(table, 1, 1, 64, 4, 4, ws, wsz - 1, None) == -5   # workspace too small
+        assert h.tr_batch_run_split(table, 1, 1, 64, 4, 4, C.c_void_p((1 << 24) + 8), wsz, None) == -4
         print("ok")
     """)
     env = dict(os.environ, HIP_VISIBLE_DEVICES="-1")

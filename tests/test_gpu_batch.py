@@ -65,13 +65,14 @@ def oracle_steps(host, m, steps, rule_kind="fixed", alpha=0.05, eta=0.02):
     return outs
 
 
+@pytest.mark.parametrize("splits", [1, 4])
 @pytest.mark.parametrize("rule_kind", ["fixed", "adagrad"])
-def test_one_step_matches_oracle(rule_kind):
+def test_one_step_matches_oracle(rule_kind, splits):
     inst = small_instances(1, 6, big=True)
     probs, host = build(inst, m=100, rule_kind=rule_kind)
     B = TRBatch(probs)
-    say("batch one step", rule_kind, [b.N for b in inst])
-    B.run(1)
+    say("batch one step", rule_kind, splits, [b.N for b in inst])
+    B.run(1, splits=splits)
     torch.cuda.synchronize()
     ref = oracle_steps(host, 100, 1, rule_kind)
     assert B.t_dev.cpu().tolist() == [1] * len(inst)
@@ -88,18 +89,19 @@ def test_one_step_matches_oracle(rule_kind):
         assert abs(float(B.loss[p]) - losses[-1]) <= TOL16 * abs(losses[-1])
 
 
-def test_each_problem_equals_itself_alone():
+@pytest.mark.parametrize("splits", [1, 4])
+def test_each_problem_equals_itself_alone(splits):
     inst = small_instances(2, 5)
     probs, _ = build(inst, m=70, rule_kind="adagrad")
     B = TRBatch(probs)
-    B.run(4)
+    B.run(4, splits=splits)
     torch.cuda.synchronize()
     together = [[c.clone() for c in pr["cores"]] for pr in probs]
     assert all(bool(torch.isfinite(c).all()) for cs in together for c in cs)
     for p, b in enumerate(inst):
         solo, _ = build([b], m=70, rule_kind="adagrad")
         S = TRBatch(solo)
-        S.run(4)
+        S.run(4, splits=splits)
         torch.cuda.synchronize()
         say("solo", p)
         for a, c in zip(together[p], solo[0]["cores"]):
@@ -109,10 +111,10 @@ def test_each_problem_equals_itself_alone():
 def test_tile_variants_agree():
     inst = small_instances(3, 4)
     outs = []
-    for ch, wv in TRBatch.VARIANTS:
+    for (ch, wv), sp in [(v, 1) for v in TRBatch.VARIANTS] + [(v, 4) for v in TRBatch.VARIANTS]:
         probs, _ = build(inst, m=96)
         B = TRBatch(probs)
-        B.run(3, ch, wv)
+        B.run(3, ch, wv, sp)
         torch.cuda.synchronize()
         outs.append([[c.cpu().numpy() for c in pr["cores"]] for pr in probs])
     for other in outs[1:]:
@@ -121,15 +123,18 @@ def test_tile_variants_agree():
                 assert rel(b, a) < 1e-5
 
 
-def test_graph_replay_equals_eager_bitwise():
+@pytest.mark.parametrize("splits", [1, 4])
+def test_graph_replay_equals_eager_bitwise(splits):
     inst = small_instances(4, 4)
     pa, _ = build(inst, m=64, rule_kind="adagrad")
     A = TRBatch(pa)
+    A.splits = splits
     A.run(6)
     torch.cuda.synchronize()
     assert all(bool(torch.isfinite(c).all()) for x in pa for c in x["cores"])
     pb, _ = build(inst, m=64, rule_kind="adagrad")
     Bb = TRBatch(pb)
+    Bb.splits = splits
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -173,10 +178,12 @@ def unfold_back(G2, Rk, Rk1):
     return np.ascontiguousarray(G2.reshape(G2.shape[0], Rk1, Rk).transpose(2, 0, 1))
 
 
-def test_full_batch_step_at_bench_configuration():
+@pytest.mark.parametrize("splits", [1, 4])
+def test_full_batch_step_at_bench_configuration(splits):
     """The 64-problem workload the benchmark times (orders 3-5, sizes 16-128,
     ranks 3-12, FP16 tensors, m = 1024, AdaGrad) in its launch configuration
-    (chunks of 64 samples, eight wavefronts): one step of all problems; the
+    (chunks of 64 samples, eight wavefronts, each problem's samples on one or
+    four workgroups): one step of all problems; the
     smallest problem of each order is checked against the oracle, every
     problem advances its counter with no device flag raised."""
     inst = ti.batched_instances(0)
@@ -207,7 +214,7 @@ def test_full_batch_step_at_bench_configuration():
         probs.append(dict(cores=cores, Xrep=reps, I=b.I, R=b.R, m=m, rule=rule, seed=b.seed))
     B = TRBatch(probs)
     say("full batch step, sampled problems", sorted(sampled))
-    B.run(1, chunk=64, waves=8)
+    B.run(1, chunk=64, waves=8, splits=splits)
     torch.cuda.synchronize()
     assert B.t_dev.cpu().tolist() == [1] * len(inst)
     assert int(B.status.max()) == 0
