@@ -48,9 +48,18 @@ def _torch_lib_dir() -> str | None:
         return None
 
 
+# Per-source code-generation options.  sweep.hip: the FP64 matrix-core
+# accumulators of the one-workgroup inverse are selected in ordinary vector
+# registers (the VGPR form of the MFMA instructions), which removes the
+# copies between accumulation and vector registers from every block step.
+PER_SOURCE = {
+    "sweep.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *PER_SOURCE.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -110,10 +110,9 @@ __device__ __forceinline__ void sweep8_pivot(double& a, bool& good, int i, int j
     const double cj = permute_lane(a, j > K ? 8 * j + K : 8 * K + j);
     good = good && (p > 0.0) && isfinite(p);
     const double dk = rcp_nr(p);
-    if (i != K && j != K) a = __builtin_fma(-(ci * dk), cj, a);
-    else if (i != K) a = ci * dk;
-    else if (j != K) a = cj * dk;
-    else a = -dk;
+    const double ti = ci * dk, tj = cj * dk;
+    const double up = __builtin_fma(-ti, cj, a);
+    a = (i != K) ? ((j != K) ? up : ti) : ((j != K) ? tj : -dk);   // selects, no branches
 }
 
 __device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw) {
@@ -132,15 +131,17 @@ __device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw
     return good;
 }
 
-// Pivot rows of block q of the current matrix, minus the selector, into
-// Vt[u][c] = M(8q + u, c) - [c == 8q + u] for every column c < NP.  Rows of
-// the pivot tile row come from the tiles left of the diagonal; entries right
-// of it from the column of tiles below (M is symmetric).
-template <int NT, int WV>
+// Pivot rows of block q = 2 tq + HQ of the current matrix, minus the
+// selector, into Vt[u][c] = M(8q + u, c) - [c == 8q + u] for every column
+// c < NP.  Rows of the pivot tile row come from the tiles left of the
+// diagonal; entries right of it from the column of tiles below (M is
+// symmetric).  The half HQ of the tile is a compile-time constant, so every
+// register index is static; only the tile-row tests (uniform) branch.
+template <int NT, int WV, int HQ>
 __device__ __forceinline__ void publish_rows(const dbl4 (&acc)[tpw<NT>()], int q, double* Vt) {
     constexpr int NP = 16 * NT;
     const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
-    const int tq = q >> 1, hq = q & 1;
+    const int tq = q >> 1;
 #pragma unroll
     for (int k = 0; k < tpw<NT>(); ++k) {
         if (!s_ok<NT>(WV, k)) continue;
@@ -148,28 +149,27 @@ __device__ __forceinline__ void publish_rows(const dbl4 (&acc)[tpw<NT>()], int q
         if (rt == tq) {
 #pragma unroll
             for (int jj = 0; jj < 2; ++jj) {
-                const double v = hq ? acc[k][2 + jj] : acc[k][jj];
+                const double v = acc[k][2 * HQ + jj];
                 const int u = 4 * jj + lr, c = 16 * ct + lc;
-                Vt[u * NP + c] = v - (c == 8 * q + u ? 1.0 : 0.0);
+                // the selector lies in the diagonal tile only: c == 8q + u there is lc == 8 HQ + u
+                Vt[u * NP + c] = ct == tq ? v - (lc == 8 * HQ + u ? 1.0 : 0.0) : v;
             }
-        } else if (ct == tq && rt > tq && (lc >> 3) == hq) {
-            const int u = lc - 8 * hq;
+        } else if (ct == tq && rt > tq && (lc >> 3) == HQ) {
+            const int u = lc - 8 * HQ;
 #pragma unroll
             for (int j = 0; j < 4; ++j) Vt[u * NP + 16 * rt + 4 * j + lr] = acc[k][j];
         }
     }
 }
 
-// The 8 x 8 pivot block q (plain M_PP, row-major) from its diagonal tile.
-__device__ __forceinline__ void publish_d8(const dbl4& a, int q, double* D8) {
+// The 8 x 8 pivot block 2 t + HQ (plain M_PP, row-major) from its diagonal
+// tile t.
+template <int HQ>
+__device__ __forceinline__ void publish_d8(const dbl4& a, double* D8) {
     const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
-    const int hq = q & 1;
-    if ((lc >> 3) == hq) {
+    if ((lc >> 3) == HQ) {
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-            const double v = hq ? a[2 + jj] : a[jj];
-            D8[(4 * jj + lr) * 8 + (lc - 8 * hq)] = v;
-        }
+        for (int jj = 0; jj < 2; ++jj) D8[(4 * jj + lr) * 8 + (lc - 8 * HQ)] = a[2 * HQ + jj];
     }
 }
 
@@ -302,6 +302,44 @@ struct SweepShared {
     int good[2];             // verdict of the factorisation of step q's pivot block, by q & 1
 };
 
+// Block step q of one wavefront, ending at the step's barrier; HQ = q & 1
+// is a compile-time constant (the half of a tile that holds the pivot rows,
+// and the parity of the double-buffered shared arrays).  Update wavefronts
+// apply the step to their tiles and publish the next pivot rows; the factor
+// wavefront forms pivot block q+1 as it will be after step q and sweeps it.
+// Returns the verdict on pivot block q + 1 (true after the last step).
+template <int NT, int WV, int HQ>
+__device__ __forceinline__ bool sweep_step(dbl4 (&acc)[tpw<NT>()], SweepShared& sh, int q, int npiv) {
+    const double* Vt = sh.Vt[HQ];
+    const bool more = q + 1 < npiv;
+    if (WV == kFactorWave) {
+        if (more) {
+            next_pivot_block<NT>(Vt, sh.Bw[HQ], sh.D8[HQ ^ 1], q, sh.Dn);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const bool g = sweep8(sh.Dn, sh.Bw[HQ ^ 1]);
+            if ((threadIdx.x & 63) == 0) sh.good[HQ ^ 1] = g ? 1 : 0;
+        }
+    } else {
+        const SweepZ z = compute_z<NT, WV>(Vt, sh.Bw[HQ]);
+#pragma unroll
+        for (int k = 0; k < tpw<NT>(); ++k)
+            if (s_ok<NT>(WV, k)) acc[k] = update_tile<NT>(acc[k], Vt, z.z[s_m<NT>(WV, k)], s_rt<NT>(WV, k));
+        if (more) publish_rows<NT, WV, HQ ^ 1>(acc, q + 1, sh.Vt[HQ ^ 1]);
+        if (q + 2 < npiv) {
+            // pivot block q+2 (same parity) as it stands after this step
+            const int t2 = (q + 2) >> 1;
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                if (ncol<NT>(WV, m) > 0 && t2 == col_of(WV, m)) publish_d8<HQ>(acc[s_first<NT>(WV, m)], sh.D8[HQ]);
+        }
+    }
+    __syncthreads();
+    return more ? sh.good[HQ ^ 1] != 0 : true;
+}
+
 // One wavefront's part of the sweep with the fallback ladder.  Returns the
 // attempt that succeeded, or -1.  Every wavefront passes the same barriers
 // and reads the same verdicts, so every wavefront returns the same value.
@@ -341,40 +379,14 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
             if ((threadIdx.x & 63) == 0) sh.good[0] = g ? 1 : 0;
         } else {
             fill_tiles<NT, WV>(acc, gram, RR, eta);
-            publish_rows<NT, WV>(acc, 0, sh.Vt[0]);
+            publish_rows<NT, WV, 0>(acc, 0, sh.Vt[0]);
         }
         __syncthreads();
+        // block steps in pairs (even q, then odd q)
         bool good = sh.good[0] != 0;
-        for (int q = 0; q < npiv && good; ++q) {
-            const double* Vt = sh.Vt[q & 1];
-            const bool more = q + 1 < npiv;
-            if (WV == kFactorWave) {
-                if (more) {
-                    next_pivot_block<NT>(Vt, sh.Bw[q & 1], sh.D8[(q + 1) & 1], q, sh.Dn);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_s_waitcnt(0xc07f);
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const bool g = sweep8(sh.Dn, sh.Bw[(q + 1) & 1]);
-                    if ((threadIdx.x & 63) == 0) sh.good[(q + 1) & 1] = g ? 1 : 0;
-                }
-            } else {
-                const SweepZ z = compute_z<NT, WV>(Vt, sh.Bw[q & 1]);
-#pragma unroll
-                for (int k = 0; k < tpw<NT>(); ++k)
-                    if (s_ok<NT>(WV, k)) acc[k] = update_tile<NT>(acc[k], Vt, z.z[s_m<NT>(WV, k)], s_rt<NT>(WV, k));
-                if (more) publish_rows<NT, WV>(acc, q + 1, sh.Vt[(q + 1) & 1]);
-                if (q + 2 < npiv) {
-                    // pivot block q+2 as it stands after this step
-                    const int t2 = (q + 2) >> 1;
-#pragma unroll
-                    for (int m = 0; m < 3; ++m)
-                        if (ncol<NT>(WV, m) > 0 && t2 == col_of(WV, m))
-                            publish_d8(acc[s_first<NT>(WV, m)], q + 2, sh.D8[(q + 2) & 1]);
-                }
-            }
-            __syncthreads();
-            if (more) good = sh.good[(q + 1) & 1] != 0;
+        for (int q = 0; q < npiv && good; q += 2) {
+            good = sweep_step<NT, WV, 0>(acc, sh, q, npiv);
+            if (good && q + 1 < npiv) good = sweep_step<NT, WV, 1>(acc, sh, q + 1, npiv);
         }
         if (good) {
             if (WV != kFactorWave) store_tiles<NT, WV>(acc, hm, RR);
@@ -413,82 +425,94 @@ __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const doub
 
 constexpr int kApplyRows = 16;
 
-// p = g (-M^{-1}) for 16 rows of g per block, then the rule.  Product on
-// FP64 matrix cores: wavefront w owns the 16 x 16 output tiles of columns
-// 16n.., n = w and w + 4; every operand (the block's rows of g, the
-// columns of -M^{-1} it needs, the core and accumulator entries it updates)
-// is loaded straight from global memory with all loads in flight, K padded
-// with zeros to 128.  With lp.part set, block 0 also writes the loss.  With
-// ``step`` set, the block that finishes last advances the step counter
-// (after every block has read it).
+// p = g (-M^{-1}), then the rule: one wavefront per block, one 16 x 16 tile
+// of p per block (rows 16 blockIdx.x.., columns 16 blockIdx.y..), so the
+// product spreads over as many CUs as there are tiles.  The tile is one
+// chain of FP64 matrix-core steps over K in fours (K = R_n R_{n+1} <= 128);
+// every operand (the tile's rows of g, its columns of -M^{-1}, the core and
+// accumulator entries it updates) is loaded straight from global memory
+// with all loads in flight.  With lp.part set, block (0, 0) also writes the
+// loss.  With ``step`` set, the block that finishes last advances the step
+// counter (after every block has read it).
 // SHAPE0: every mode has the same I_n and R_n R_{n+1}, so the loads of g and
 // -M^{-1} are issued before the step's mode has arrived.
 template <typename TC, bool SHAPE0>
-__global__ __launch_bounds__(256) void k_scaled_apply(tr_desc d, ModeSrc ms, const TC* __restrict__ g,
-                                                      LossParts lp, double* __restrict__ loss,
-                                                      const double* __restrict__ hm, const int* __restrict__ flag,
-                                                      MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
-                                                      StepBump step) {
+__global__ __launch_bounds__(64) void k_scaled_apply(tr_desc d, ModeSrc ms, const TC* __restrict__ g,
+                                                     LossParts lp, double* __restrict__ loss,
+                                                     const double* __restrict__ hm, const int* __restrict__ flag,
+                                                     MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
+                                                     StepBump step) {
     uint64_t t;
-    int n;
-    resolve_mode(ms, d.N, &t, &n);
+    int n = 0;
+    if (!SHAPE0) resolve_mode(ms, d.N, &t, &n);
     const int ns = SHAPE0 ? 0 : n;
     const int In = d.I[ns];
     const int RR = d.R[ns] * d.R[ring_next(ns, d.N)];
-    const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4, w = tid >> 6;
+    const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
     __shared__ double red[4];
-    if (blockIdx.x == 0 && lp.part) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && lp.part) {
         const double s = loss_parts_sum(lp, In, red);
-        if (tid == 0) *loss = s;
+        if (l == 0) *loss = s;
     }
     constexpr int KS = 32;                          // K steps of 4: RR <= 128
-    const int r0 = blockIdx.x * kApplyRows;
-    const int NTc = (RR + 15) >> 4;
-    const int fl = *flag;
-    TC* G = static_cast<TC*>(cores.p[n]);
-    TC* A = static_cast<TC*>(accum.p[n]);
-    // every operand in flight together: one wait on memory per block
-    double a[KS], b[2][KS];                          // g[r0 + lr][4ks + lk], (-M^{-1})[4ks + lk][c]
-    {
-        const int row = r0 + lr;
+    const int r0 = blockIdx.x * kApplyRows, c = 16 * blockIdx.y + lr;
+    if (r0 < In && 16 * (int)blockIdx.y < RR) {
+        // Loads at clamped (in-bounds) indices, masked afterwards: no load
+        // sits behind a branch, so all of them are in flight together (with
+        // SHAPE0 the ones that do not need the mode go before its read).
+        double a[KS], b[KS];                        // g[r0 + lr][4ks + lk], (-M^{-1})[4ks + lk][c]
+        const int row = r0 + lr, rowc = row < In ? row : In - 1, cc = c < RR ? c : RR - 1;
+        TC ga[KS];
+        double hb[KS];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const int k = 4 * ks + lk;
-            a[ks] = (row < In && k < RR) ? (double)g[(int64_t)row * RR + k] : 0.0;
+            const int k = 4 * ks + lk, kc = k < RR ? k : RR - 1;
+            if (4 * ks < RR) {   // uniform
+                ga[ks] = g[(int64_t)rowc * RR + kc];
+                hb[ks] = hm[(int64_t)kc * RR + cc];
+            }
         }
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int c = 16 * (w + 4 * u) + lr;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int k = 4 * ks + lk;
-            b[u][ks] = (k < RR && c < RR) ? hm[(int64_t)k * RR + c] : 0.0;
-        }
-    }
-    double gold[2][4], aold[2][4];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
+        const int fl = *flag;
+        if (SHAPE0) resolve_mode(ms, d.N, &t, &n);
+        TC* G = static_cast<TC*>(cores.p[n]);
+        TC* A = static_cast<TC*>(accum.p[n]);
+        TC gv[4], av[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int r = r0 + 4 * j + lk, c = 16 * (w + 4 * u) + lr;
-            const bool in = r < In && c < RR;
-            gold[u][j] = in ? (double)G[(int64_t)r * RR + c] : 0.0;
-            aold[u][j] = (in && rule.kind == 1) ? (double)A[(int64_t)r * RR + c] : 0.0;
+            const int r = r0 + 4 * j + lk, rc = r < In ? r : In - 1;
+            gv[j] = G[(int64_t)rc * RR + cc];
+            av[j] = TC(0);
+        }
+        if (rule.kind == 1) {   // uniform; the accumulator exists only for AdaGrad
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = r0 + 4 * j + lk, rc = r < In ? r : In - 1;
+                av[j] = A[(int64_t)rc * RR + cc];
+            }
         }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int nt = w + 4 * u;
-        const int c = 16 * nt + lr;
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k = 4 * ks + lk;
+            a[ks] = (4 * ks < RR && row < In && k < RR) ? (double)ga[ks] : 0.0;
+            b[ks] = (4 * ks < RR && k < RR && c < RR) ? hb[ks] : 0.0;
+        }
+        double gold[4], aold[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool in = r0 + 4 * j + lk < In && c < RR;
+            gold[j] = in ? (double)gv[j] : 0.0;
+            aold[j] = in ? (double)av[j] : 0.0;
+        }
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[u][ks], acc, 0, 0, 0);
-        if (fl != 2 && nt < NTc) {   // fl == 2: not positive definite even with damping, core unchanged
+        for (int ks = 0; ks < KS; ++ks)
+            if (4 * ks < RR) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+        if (fl != 2) {   // fl == 2: not positive definite even with damping, core unchanged
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int r = r0 + 4 * j + lk;
                 if (r < In && c < RR)
-                    apply_rule_loaded<TC>(G, A, (int64_t)r * RR + c, gold[u][j], aold[u][j], acc[j], rule, t, status);
+                    apply_rule_loaded<TC>(G, A, (int64_t)r * RR + c, gold[j], aold[j], acc[j], rule, t, status);
             }
         }
     }
@@ -538,12 +562,12 @@ hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossP
     char* w = static_cast<char*>(ws);
     const double* hm = reinterpret_cast<const double*>(w + L.L_off);
     const int* flag = reinterpret_cast<const int*>(w + L.flag_off);
-    const dim3 grid((sh.maxI + kApplyRows - 1) / kApplyRows);
+    const dim3 grid((sh.maxI + kApplyRows - 1) / kApplyRows, (sh.maxRR + 15) / 16);
     bool same = true;
     for (int k = 1; k < d.N; ++k)
         same = same && d.I[k] == d.I[0] && d.R[k] * d.R[(k + 1) % d.N] == d.R[0] * d.R[1 % d.N];
 #define TRK_APPLY(TC, S0)                                                                                   \
-    hipLaunchKernelGGL((k_scaled_apply<TC, S0>), grid, dim3(256), 0, st, d, ms, static_cast<const TC*>(g), lp, \
+    hipLaunchKernelGGL((k_scaled_apply<TC, S0>), grid, dim3(64), 0, st, d, ms, static_cast<const TC*>(g), lp, \
                        loss, hm, flag, cores, accum, rule, status, step)
     if (d.core_dtype == TR_F64) {
         if (same) TRK_APPLY(double, true);
