@@ -124,31 +124,36 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
     }
     if (!do_subchain) return;
 
-    // Phase 2: slices of every sample, all loads in flight together.
+    // Phase 2: slices of every sample, all loads in flight together.  Thread
+    // w of a pass owns value w of every sample's slices (its slice q, mode k
+    // and offset are the same for all samples), so the loads of the pass
+    // are one per sample at a row taken from LDS: the row is clamped to 0
+    // for a rejected caller index and the value masked afterwards, so no
+    // load sits behind a branch.
     const int per = soff[N - 1];   // slice values per sample
-    const int tot = nb * per;
-    constexpr int LB = 16;
-    for (int e0 = 0; e0 < tot; e0 += 256 * LB) {
-        TC v[LB];
+    for (int w0 = 0; w0 < per; w0 += 256) {
+        const int w = w0 + tid, wc = w < per ? w : per - 1;
+        int q = 0;
+        while (q + 1 < N - 1 && wc >= soff[q + 1]) ++q;
+        const int k = (n + 1 + q) % N;
+        const int len = soff[q + 1] - soff[q], off = wc - soff[q];
+        const TC* src = static_cast<const TC*>(cores.p[k]);
+        constexpr int kSB = 16;   // samples per block at most
+        int row[kSB];
+        bool ok[kSB];
 #pragma unroll
-        for (int u = 0; u < LB; ++u) {
-            const int e = e0 + u * 256 + tid;
-            v[u] = TC(0);
-            if (e < tot) {
-                const int fl = e / per, w = e - fl * per;
-                int q = 0;
-                while (q + 1 < N - 1 && w >= soff[q + 1]) ++q;
-                const int k = (n + 1 + q) % N;
-                const int i = sidx[fl * kMaxOrder + k];
-                if (sok[fl])
-                    v[u] = static_cast<const TC*>(cores.p[k])[(int64_t)i * (soff[q + 1] - soff[q]) + (w - soff[q])];
-            }
+        for (int fl = 0; fl < kSB; ++fl) {   // sample indices clamped into the block's own
+            const int fc = fl < nb ? fl : nb - 1;
+            const int i = sidx[fc * kMaxOrder + k];
+            ok[fl] = sok[fc] != 0;
+            row[fl] = ok[fl] ? i : 0;
         }
+        TC v[kSB];
 #pragma unroll
-        for (int u = 0; u < LB; ++u) {
-            const int e = e0 + u * 256 + tid;
-            if (e < tot) sl[e] = v[u];
-        }
+        for (int fl = 0; fl < kSB; ++fl) v[fl] = src[(int64_t)row[fl] * len + off];
+#pragma unroll
+        for (int fl = 0; fl < kSB; ++fl)
+            if (fl < nb && w < per) sl[(size_t)fl * per + w] = ok[fl] ? v[fl] : TC(0);
     }
     __syncthreads();
 
@@ -178,6 +183,51 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
         // product tiles after the slices (and after the FP64 path's product
         // buffers, which exist for N > 3 only)
         float* Mw = reinterpret_cast<float*>(bufA + (N > 3 ? 2 * (size_t)SB * P2 : 0)) + wv * 256;
+        if (N == 3) {
+            // One product per sample, M = A_0 A_1; the wavefront's samples
+            // wv, wv + 4, wv + 8, wv + 12 (SB <= 16) side by side, operands
+            // read at clamped indices and masked.
+            const int k = (n + 2) % N, Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
+            const int lrA = lr < Rn1 ? lr : Rn1 - 1, lrB = lr < Rk1 ? lr : Rk1 - 1;
+            float a[4][4], b[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int fl = wv + 4 * u;
+                const float* base = reinterpret_cast<const float*>(sl) + (size_t)(fl < nb ? fl : 0) * per;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int kk = 4 * ks + lk, kc = kk < Rk ? kk : Rk - 1;
+                    // the masks multiply (a select would become a branch around
+                    // each LDS read); a clamped entry is one of the sample's own
+                    // and feeds the same outputs, so non-finite values propagate
+                    // exactly as with zero padding
+                    const float av = base[lrA + Rn1 * kc], bv = base[soff[1] + kc + Rk * lrB];
+                    a[u][ks] = av * ((lr < Rn1 && kk < Rk) ? 1.f : 0.f);
+                    b[u][ks] = bv * ((kk < Rk && lr < Rk1) ? 1.f : 0.f);
+                }
+            }
+            sf4 acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = sf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][ks], b[u][ks], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int fl = wv + 4 * u;
+                if (fl < nb) {   // uniform
+                    const bool ok = sok[fl] != 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {   // S(f, r + R_n s) = M_f(s, r), s = 4 lk + j, r = lr
+                        const int srow = 4 * lk + j;
+                        if (srow < Rn1 && lr < Rn)
+                            S[(int64_t)(f0 + fl) * RR + lr + Rn * srow] = ok ? (TC)acc[u][j] : TC(NAN);
+                    }
+                }
+            }
+            return;
+        }
         for (int fl = wv; fl < nb; fl += (int)(blockDim.x >> 6)) {
             const float* base = reinterpret_cast<const float*>(sl) + (size_t)fl * per;
             sf4 mv = {0.f, 0.f, 0.f, 0.f};
@@ -247,7 +297,7 @@ static int sample_block(const tr_desc& d, const Shape& sh, size_t es, size_t* ld
     const size_t prod = d.N > 3 ? 2 * (size_t)sh.maxR * sh.maxR : 0;   // product buffers
     const size_t need = (per + prod) * es + kMaxOrder * 12 + 4;
     int SB = (int)((48 * 1024) / need);
-    SB = SB < 1 ? 1 : (SB > 16 ? 16 : SB);
+    SB = SB < 1 ? 1 : (SB > 16 ? 16 : SB);   // the kernel's slice loads assume SB <= 16
     *lds = (size_t)SB * kMaxOrder * 12 + (size_t)((SB + 3) & ~3) * 4 + 16 +
            ((size_t)SB * per + (size_t)SB * prod) * es + (es == 4 ? 4 * 256 * 4 : 0);   // FP32: product tiles
     return SB;
