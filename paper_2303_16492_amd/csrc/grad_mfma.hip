@@ -30,11 +30,44 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
                                                        const int32_t* __restrict__ idx, const float* __restrict__ S,
                                                        const double* __restrict__ pF, int m, int groups,
                                                        int row_tiles_max, float* __restrict__ gpart,
-                                                       double* __restrict__ lpart, int maxIRR) {
+                                                       double* __restrict__ lpart, int maxIRR, int rr_fixed) {
+    const int N = d.N;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    constexpr int SB = (16 * CT + 63) / 64;   // 64-column strips of a staged row
+    const int nchunks = (m + kMfTF - 1) / kMfTF;
+    const int cpg = (nchunks + groups - 1) / groups;
+    const int cbeg = blockIdx.y * cpg, cend = min(nchunks, cbeg + cpg);
+    // The next chunk's operands are held in registers until its turn: S rows
+    // (16 per wavefront), the sample's indices and probability (every thread
+    // loads those of sample tid % 64; the first 64 use them).  Clamped
+    // indices, no load behind a branch.
+    float v[16][SB];
+    int ik[kMaxOrder];
+    double pf = 1.0;
+    auto load_chunk = [&](int ch, int RRl) {
+        const int f0 = ch * kMfTF;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            const int f = f0 + w + 4 * a;
+            const float* src = S + (int64_t)(f < m ? f : m - 1) * RRl;
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                const int c = l + 64 * b;
+                v[a][b] = src[c < RRl ? c : RRl - 1];
+            }
+        }
+        const int fi = f0 + l;
+        const int64_t fc = fi < m ? fi : m - 1;
+#pragma unroll
+        for (int k = 0; k < kMaxOrder; ++k) ik[k] = idx[fc * N + (k < N ? k : N - 1)];
+        pf = pF[fc];
+    };
+    // With one R_n R_{n+1} for every mode the first chunk's loads go out
+    // before the step's mode has arrived.
+    if (rr_fixed > 0 && cbeg < cend) load_chunk(cbeg, rr_fixed);
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
-    const int N = d.N;
     const int In = d.I[n];
     const int RR = d.R[n] * d.R[ring_next(n, N)];
     // Tiles are fixed at compile time (CT column tiles of 16, KQ = 4 CT steps
@@ -45,7 +78,6 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
     constexpr int RRs = mf_pitch(RRT);
     const int i0 = blockIdx.x * kMfTI;
     if (i0 >= In) return;
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float* sS = reinterpret_cast<float*>(smem_raw);             // [TF][RRs]
@@ -56,13 +88,16 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
 
     // A operand of GEMM1: this lane's G row, K in steps of 4.
     const float* Gn = static_cast<const float*>(cores.p[n]);
-    const int grow = i0 + 16 * w + lr;
+    // Loads at clamped indices, masked afterwards (no load behind a branch).
+    const int grow = i0 + 16 * w + lr, growc = grow < In ? grow : In - 1;
     float ag[KQ];
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
-        const int k = 4 * q + lk;
-        ag[q] = (grow < In && k < RR) ? Gn[(int64_t)grow * RR + k] : 0.f;
+        const int k = 4 * q + lk, kc = k < RR ? k : RR - 1;
+        ag[q] = Gn[(int64_t)growc * RR + kc];
     }
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) ag[q] *= (grow < In && 4 * q + lk < RR) ? 1.f : 0.f;
     const bool rep = xsrc.rep[n] != nullptr;
     const TX* X = static_cast<const TX*>(rep ? xsrc.rep[n] : xsrc.X);
     int64_t xs[kMaxOrder];
@@ -85,52 +120,37 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
     for (int c = 0; c < CT; ++c) acc2[c] = f32x4{0.f, 0.f, 0.f, 0.f};
     double lsum = 0.0;
     const double wbase = 1.0 / ((double)m * (double)J_of(d, n));
-    const int nchunks = (m + kMfTF - 1) / kMfTF;
-    const int cpg = (nchunks + groups - 1) / groups;
-    const int cbeg = blockIdx.y * cpg, cend = min(nchunks, cbeg + cpg);
     const int erow = 16 * w + 4 * lk;   // first of this lane's 4 D rows (block-local)
 
-    constexpr int SB = (16 * CT + 63) / 64;   // 64-column strips of a staged row
+    if (rr_fixed <= 0 && cbeg < cend) load_chunk(cbeg, RR);
     for (int ch = cbeg; ch < cend; ++ch) {
         const int f0 = ch * kMfTF;
         __syncthreads();
-        {   // stage the S chunk: every load issued before any LDS store
-            float v[16][SB];
+        // the staged chunk into LDS
 #pragma unroll
-            for (int a = 0; a < 16; ++a) {
-                const int f = w + 4 * a;
-                const bool okf = f0 + f < m;
-                const float* src = S + (int64_t)(f0 + f) * RR;
+        for (int a = 0; a < 16; ++a)
 #pragma unroll
-                for (int b = 0; b < SB; ++b) {
-                    const int c = l + 64 * b;
-                    v[a][b] = (okf && c < RR) ? src[c] : 0.f;
-                }
+            for (int b = 0; b < SB; ++b) {
+                const int c = l + 64 * b;
+                const bool ok = f0 + w + 4 * a < m && c < RR;
+                if (c < RRT) sS[(w + 4 * a) * RRs + c] = ok ? v[a][b] : 0.f;
             }
-#pragma unroll
-            for (int a = 0; a < 16; ++a)
-#pragma unroll
-                for (int b = 0; b < SB; ++b) {
-                    const int c = l + 64 * b;
-                    if (c < RRT) sS[(w + 4 * a) * RRs + c] = v[a][b];
-                }
-        }
         if (tid < kMfTF) {
             const int f = f0 + tid;
             bool ok = f < m;
             int64_t off = 0;
-            int ik[kMaxOrder];
+            int ikm[kMaxOrder];
 #pragma unroll
-            for (int k = 0; k < kMaxOrder; ++k) ik[k] = (ok && k < N) ? idx[(int64_t)f * N + k] : 0;
+            for (int k = 0; k < kMaxOrder; ++k) ikm[k] = (ok && k < N) ? ik[k] : 0;
 #pragma unroll
             for (int k = 0; k < kMaxOrder; ++k) {
                 if (k >= N || k == n) continue;
-                if (ik[k] < 0 || ik[k] >= d.I[k]) ok = false;
-                off += (int64_t)ik[k] * xs[k];
+                if (ikm[k] < 0 || ikm[k] >= d.I[k]) ok = false;
+                off += (int64_t)ikm[k] * xs[k];
             }
             sB[tid] = ok ? off : 0;
-            sW[tid] = ok ? (float)(wbase / pF[f]) : 0.f;
-            sL[tid] = ok ? 1.0 / (2.0 * (double)m * pF[f]) : 0.0;
+            sW[tid] = ok ? (float)(wbase / pf) : 0.f;
+            sL[tid] = ok ? 1.0 / (2.0 * (double)m * pf) : 0.0;
         }
         __syncthreads();
         // Fiber entries this lane needs, loaded before GEMM1 so that the HBM
@@ -148,6 +168,8 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
                 xv[u][j] = (float)to_f64(X[o]);
             }
         }
+        // the next chunk's operands, in flight during this chunk's products
+        if (ch + 1 < cend) load_chunk(ch + 1, RR);
 
         // GEMM1: P[16w + 4lk + j][16t + lr]
         f32x4 p[4];
@@ -214,8 +236,11 @@ static hipError_t launch_ct(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, c
                             int maxIRR, hipStream_t st) {
     constexpr size_t shm = grad_mfma_shm<CT>();
     if (!allow_lds(reinterpret_cast<const void*>(&k_grad_mfma_f32<TX, CT>), shm)) return hipErrorInvalidValue;
+    int rr_fixed = d.R[0] * d.R[1 % d.N];
+    for (int k = 1; k < d.N; ++k)
+        if (d.R[k] * d.R[(k + 1) % d.N] != rr_fixed) rr_fixed = 0;
     hipLaunchKernelGGL((k_grad_mfma_f32<TX, CT>), grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
-                       row_tiles, gp, lp, maxIRR);
+                       row_tiles, gp, lp, maxIRR, rr_fixed);
     return hipGetLastError();
 }
 
