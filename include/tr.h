@@ -139,11 +139,15 @@ int32_t tr_mode(uint64_t seed, uint64_t step, int32_t N);
  * "lev_est": p(i) = l_i(G_{k(2)}) / rank; Lemma "euc_est":
  * p(i) = ||G_k(:,i,:)||_F^2 / ||G_k||_F^2).  core_k: G_{k(2)} in the core
  * dtype.  cdf_k: uint64 [I_k], inclusive prefix sums of the weights.
- * Leverage scores come from an FP64 Cholesky of the FP64 Gram
- * G_{k(2)}^T G_{k(2)}; when I_k <= R_k R_{k+1} the rows are taken as
- * linearly independent and the law is uniform.  A zero core or a Gram that
- * is not positive definite sets TR_DEV_ZERO_DIST / TR_DEV_NOT_SPD and
- * writes the uniform CDF.  law must be TR_LAW_LEVERAGE or TR_LAW_EUCLID. */
+ * Leverage scores are l_i = g_i^T (G^T G)^{-1} g_i with the FP64 Gram
+ * G^T G of G = G_{k(2)}, inverted by the blocked FP64 sweep for
+ * R_k R_{k+1} <= 128 and through an FP64 Cholesky above; when
+ * I_k <= R_k R_{k+1} the rows are taken as linearly independent and the law
+ * is uniform.  A zero core or a Gram that is not positive definite sets
+ * TR_DEV_ZERO_DIST / TR_DEV_NOT_SPD and writes the uniform CDF.  law must be
+ * TR_LAW_LEVERAGE or TR_LAW_EUCLID.  ws: device workspace of at least
+ * tr_dist_workspace_size bytes (row norms, or the Gram, its inverse and the
+ * scores); the call fails with TR_E_WORKSPACE without it. */
 tr_status tr_dist(const tr_desc* d, int32_t k, int32_t law, const void* core_k,
                   uint64_t* cdf_k, int32_t* dev_status,
                   void* ws, size_t ws_bytes, tr_stream_t stream);

@@ -174,7 +174,7 @@ tr_status tr_dist(const tr_desc* d, int32_t k, int32_t law, const void* core_k, 
     if (s != TR_OK) return s;
     if (k < 0 || k >= d->N || !core_k || !cdf_k) return TR_E_ARG;
     if (law != TR_LAW_LEVERAGE && law != TR_LAW_EUCLID) return TR_E_ARG;
-    if (ws_bytes < dist_ws_bytes(*d, law) || (law == TR_LAW_LEVERAGE && !ws)) return TR_E_WORKSPACE;
+    if (ws_bytes < dist_ws_bytes(*d, law) || !ws) return TR_E_WORKSPACE;
     Ptrs cores{};
     cores.p[k] = core_k;
     uint64_t* outs[kMaxOrder] = {};
@@ -431,9 +431,8 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
     xs_paper.X = p->X;
     hipError_t e = hipSuccess;
     const bool refresh = c->law == TR_LAW_LEVERAGE || c->law == TR_LAW_EUCLID;
-    // The step counter advances in the last kernel of a step when that is
-    // the update; the law refresh of E/L reads the step's mode after it, so
-    // those laws keep a separate bump.
+    // The step counter advances in the last kernel of a step: the update,
+    // or for E/L the law refresh that reads the step's mode after it.
     unsigned* ctr = reinterpret_cast<unsigned*>(w + L.ctr);
     const StepBump fused = refresh ? StepBump{} : StepBump{t_dev, ctr};
     if (!refresh) e = launch_zero_u32(ctr, 1, st);
@@ -537,10 +536,8 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                                        dev_status, st, fused);
             }
         }
-        if (e == hipSuccess && refresh) {
-            e = launch_dist(d, ms, true, 0, c->law, cores, p->cdf, dev_status, w + L.dist, st);
-            if (e == hipSuccess) e = launch_bump(t_dev, st);
-        }
+        if (e == hipSuccess && refresh)   // the law's last kernel also advances the step counter
+            e = launch_dist(d, ms, true, 0, c->law, cores, p->cdf, dev_status, w + L.dist, st, t_dev);
     }
     return hip_status(e);
 }

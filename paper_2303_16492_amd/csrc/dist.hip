@@ -13,10 +13,15 @@ namespace trk {
 
 constexpr double kTwo40 = 1099511627776.0;
 
-// Inclusive scan of a[0..len) (uint64) by one block, in place.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Inclusive scan of a[0..len) (uint64) by one block, in place: each thread
+// scans a contiguous segment, the segment sums are scanned across lanes with
+// shuffles and across wavefronts through LDS, and each segment adds its
+// offset.  Integer sums: the result does not depend on the grouping.
 __device__ inline void block_scan_u64(uint64_t* a, int64_t len) {
-    __shared__ uint64_t part[1024];
-    const int T = blockDim.x;
+    __shared__ uint64_t wtot[16];
+    const int T = blockDim.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (T + 63) >> 6;
     const int64_t per = (len + T - 1) / T;
     const int64_t b = threadIdx.x * per, e = min(len, b + per);
     uint64_t s = 0;
@@ -24,18 +29,26 @@ __device__ inline void block_scan_u64(uint64_t* a, int64_t len) {
         s += a[i];
         a[i] = s;
     }
-    part[threadIdx.x] = s;
+    uint64_t incl = s;   // inclusive scan of the segment sums within the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(incl, (unsigned)o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wid] = incl;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t run = 0;
-        for (int i = 0; i < T; ++i) {
-            const uint64_t v = part[i];
-            part[i] = run;
-            run += v;
+    if (wid == 0) {   // exclusive scan of the wavefront totals
+        const uint64_t v = lane < nw ? wtot[lane] : 0ull;
+        uint64_t x = v;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const uint64_t y = __shfl_up(x, (unsigned)o, 64);
+            if (lane >= o) x += y;
         }
+        if (lane < nw) wtot[lane] = x - v;
     }
     __syncthreads();
-    const uint64_t off = part[threadIdx.x];
+    const uint64_t off = wtot[wid] + incl - s;
     for (int64_t i = b; i < e; ++i) a[i] += off;
     __syncthreads();
 }
@@ -48,28 +61,68 @@ __device__ inline void write_uniform_weights(uint64_t* w, int64_t len) {
     __syncthreads();
 }
 
-// Euclidean law of core k (one block).
+// Weights staged in LDS when every core has at most this many rows (the
+// launch then passes lds_rows = max I_k, else 0).
+constexpr int kLdsRows = 8192;
+
+// w (Ik weights, in LDS or global memory) -> inclusive CDF in cdf; the
+// step counter advances afterwards when ``bump`` is set (every thread of
+// the block read it before the block's first barrier).
+__device__ inline void finish_cdf(uint64_t* w, uint64_t* cdf, int Ik, uint64_t* bump) {
+    block_scan_u64(w, Ik);
+    if (w != cdf)
+        for (int i = threadIdx.x; i < Ik; i += blockDim.x) cdf[i] = w[i];
+    if (bump && threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long*>(bump), 1ull);
+}
+
+// Euclidean law of core k in two launches: the row norms ||g_i||^2 across
+// the GPU (a wavefront takes four rows, its lanes across the row, coalesced,
+// at most four passes of 64 since RR <= 256, then a shuffle sum), then the
+// total, weights, CDF and (inside a step) the counter advance in one block.
+constexpr int kEucRows = 16;
+
 template <typename TC>
-__global__ __launch_bounds__(1024) void k_dist_euclid(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
-                                                      Ptrs cores, MutPtrs cdf_out, int32_t* status) {
+__global__ __launch_bounds__(256) void k_euc_rows(tr_desc d, ModeSrc ms, int use_mode, int k_fixed, Ptrs cores,
+                                                  double* __restrict__ rn) {
     uint64_t t;
     int k = k_fixed;
     if (use_mode) resolve_mode(ms, d.N, &t, &k);
     const int Ik = d.I[k];
     const int RR = d.R[k] * d.R[ring_next(k, d.N)];
+    const int i0 = blockIdx.x * kEucRows + 4 * (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i0 >= Ik) return;
     const TC* G = static_cast<const TC*>(cores.p[k]);
-    uint64_t* w = static_cast<uint64_t*>(cdf_out.p[k]);
-    double* rn = reinterpret_cast<double*>(w);   // row norms staged in the output
-    double loc = 0.0;   // this thread's rows, then a fixed-order block sum
-    for (int i = threadIdx.x; i < Ik; i += blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < RR; ++c) {
-            const double v = (double)G[(int64_t)i * RR + c];
-            s += v * v;
+    double s[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r < Ik ? i0 + r : Ik - 1;
+        s[r] = 0.0;
+#pragma unroll
+        for (int pa = 0; pa < 4; ++pa) {
+            const int c = lane + 64 * pa;
+            const double v = (double)G[(int64_t)i * RR + (c < RR ? c : RR - 1)];
+            s[r] += c < RR ? v * v : 0.0;
         }
-        rn[i] = s;
-        loc += s;
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double tr = wave_sum(s[r]);
+        if (lane == 0 && i0 + r < Ik) rn[i0 + r] = tr;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_euc_cdf(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
+                                                  const double* __restrict__ rn, MutPtrs cdf_out, int32_t* status,
+                                                  uint64_t* bump, int lds_rows) {
+    uint64_t t;
+    int k = k_fixed;
+    if (use_mode) resolve_mode(ms, d.N, &t, &k);
+    const int Ik = d.I[k];
+    uint64_t* cdf = static_cast<uint64_t*>(cdf_out.p[k]);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint64_t* w = Ik <= lds_rows ? reinterpret_cast<uint64_t*>(smem_raw) : cdf;
+    double loc = 0.0;
+    for (int i = threadIdx.x; i < Ik; i += blockDim.x) loc += rn[i];
     __shared__ double red[16];
     const double tot = block_sum(loc, red);
     if (!(tot > 0.0) || !isfinite(tot)) {
@@ -79,14 +132,14 @@ __global__ __launch_bounds__(1024) void k_dist_euclid(tr_desc d, ModeSrc ms, int
         for (int i = threadIdx.x; i < Ik; i += blockDim.x) w[i] = quantize(rn[i] / tot);
         __syncthreads();
     }
-    block_scan_u64(w, Ik);
+    finish_cdf(w, cdf, Ik, bump);
 }
 
 // Leverage law of core k (one block): Gram, Cholesky, row solves.
 template <typename TC>
 __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
                                                         Ptrs cores, MutPtrs cdf_out, int32_t* status,
-                                                        double* __restrict__ A) {
+                                                        double* __restrict__ A, uint64_t* bump) {
     uint64_t t;
     int k = k_fixed;
     if (use_mode) resolve_mode(ms, d.N, &t, &k);
@@ -97,7 +150,7 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
     double* lev = reinterpret_cast<double*>(w);
     if (Ik <= RR) {   // full row rank taken: every leverage score is 1
         write_uniform_weights(w, Ik);
-        block_scan_u64(w, Ik);
+        finish_cdf(w, w, Ik, bump);
         return;
     }
     for (int e = threadIdx.x; e < RR * RR; e += blockDim.x) {
@@ -132,7 +185,7 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
     if (bad) {
         if (threadIdx.x == 0) set_status(status, TR_DEV_NOT_SPD);
         write_uniform_weights(w, Ik);
-        block_scan_u64(w, Ik);
+        finish_cdf(w, w, Ik, bump);
         return;
     }
     // l_i = ||L^{-1} g_i||^2 by forward substitution, one row per thread.
@@ -151,7 +204,7 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
     __syncthreads();
     for (int i = threadIdx.x; i < Ik; i += blockDim.x) w[i] = quantize(lev[i] / (double)RR);
     __syncthreads();
-    block_scan_u64(w, Ik);
+    finish_cdf(w, w, Ik, bump);
 }
 
 // The same law for R_k R_{k+1} <= 128 with the factor kept in LDS (one
@@ -162,203 +215,190 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
 // with L22^{-1} already formed); (4) l_i = ||L^{-1} g_i||^2, the rows of G
 // staged again, each row's RR entries of L^{-1} g_i split over a group of
 // threads and their squares summed by a shuffle reduction.
-constexpr int kLevThreads = 1024;
+// Leverage law for R_k R_{k+1} <= 128 in four launches across the GPU: the
+// FP64 Gram of G_{k(2)} (the sampled-Gram kernels on the core's own rows),
+// -(G^T G)^{-1} by the one-workgroup sweep, then
+//     l_i = g_i^T (G^T G)^{-1} g_i = -g_i . (g_i (-(G^T G)^{-1}))
+// for every row on the FP64 matrix cores, then the weights, CDF and
+// (inside a step) the counter advance in one block.
 
-static int lev_chunk_rows(int RR, int es) {
-    // the block scan's 8 KiB and a few words of static LDS come on top
-    const int budget = 160 * 1024 - 8192 - 1024 - RR * RR * 8 - RR * 8;
-    int cr = budget / (RR * es);
-    cr = cr > 64 ? 64 : cr;
-    return cr < 1 ? 1 : cr;
-}
+constexpr int kLevRows = 16;
 
+// l_i for 16 rows per block: wavefront w owns output columns 16 n.., n = w
+// and w + 4 (K = RR <= 128 in steps of 4), each lane's partial dot products
+// are added across its 16 lanes, then across the four wavefronts in a fixed
+// order.  Loads at clamped indices, masked afterwards.
 template <typename TC>
-__global__ __launch_bounds__(kLevThreads) void k_dist_leverage_lds(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
-                                                                  Ptrs cores, MutPtrs cdf_out, int32_t* status,
-                                                                  int CR) {
+__global__ __launch_bounds__(256) void k_lev_rows(tr_desc d, ModeSrc ms, int use_mode, int k_fixed, Ptrs cores,
+                                                  const double* __restrict__ hm, double* __restrict__ lev) {
     uint64_t t;
     int k = k_fixed;
     if (use_mode) resolve_mode(ms, d.N, &t, &k);
     const int Ik = d.I[k];
     const int RR = d.R[k] * d.R[ring_next(k, d.N)];
+    const int r0 = blockIdx.x * kLevRows;
+    if (r0 >= Ik) return;
     const TC* G = static_cast<const TC*>(cores.p[k]);
-    uint64_t* w = static_cast<uint64_t*>(cdf_out.p[k]);
-    double* lev = reinterpret_cast<double*>(w);
-    const int tid = threadIdx.x;
-    if (Ik <= RR) {   // full row rank taken: every leverage score is 1
-        write_uniform_weights(w, Ik);
-        block_scan_u64(w, Ik);
-        return;
+    const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4, w = tid >> 6;
+    constexpr int KS = 32;
+    const int row = r0 + lr, rowc = row < Ik ? row : Ik - 1;
+    TC ga[KS];
+    double hb[2][KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + lk, kc = kk < RR ? kk : RR - 1;
+        if (4 * ks < RR) {   // uniform
+            ga[ks] = G[(int64_t)rowc * RR + kc];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int c = 16 * (w + 4 * u) + lr, cc = c < RR ? c : RR - 1;
+                hb[u][ks] = hm[(int64_t)kc * RR + cc];
+            }
+        }
     }
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* sA = reinterpret_cast<double*>(smem_raw);   // RR x RR, column-major, lower triangle
-    double* scol = sA + RR * RR;                         // [RR]
-    TC* sG = reinterpret_cast<TC*>(scol + RR);          // [CR][RR], rows of G in the core dtype
-    __shared__ int bad;
+    TC gd[2][4];   // G[r0 + 4 j + lk][c], the entries this lane's outputs pair with
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + 4 * j + lk, rc = r < Ik ? r : Ik - 1;
+            const int c = 16 * (w + 4 * u) + lr, cc = c < RR ? c : RR - 1;
+            gd[u][j] = G[(int64_t)rc * RR + cc];
+        }
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = 16 * (w + 4 * u) + lr;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            if (4 * ks < RR) {
+                const int kk = 4 * ks + lk;
+                const double a = (row < Ik && kk < RR) ? (double)ga[ks] : 0.0;
+                const double b = (kk < RR && c < RR) ? hb[u][ks] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[j] += c < RR ? (double)gd[u][j] * acc[j] : 0.0;
+    }
+    __shared__ double sp[4][kLevRows];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double v = part[j];
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);   // the 16 lanes of one row
+        if (lr == 0) sp[w][4 * j + lk] = v;
+    }
+    __syncthreads();
+    if (tid < kLevRows && r0 + tid < Ik)
+        lev[r0 + tid] = -(((sp[0][tid] + sp[1][tid]) + sp[2][tid]) + sp[3][tid]);
+}
 
-    // (1) Gram, lower triangle; entry q of the column-major lower triangle is
-    // (a, b), a >= b, accumulated in place over the chunks of rows
-    const int ntri = RR * (RR + 1) / 2;
-    auto tri = [&](int q, int& ra, int& cb) {
-        // column: the largest c with c RR - c (c - 1) / 2 <= q
-        const double t2 = 2.0 * RR + 1.0;
-        int c = (int)((t2 - sqrt(t2 * t2 - 8.0 * q)) * 0.5);
-        c = c < 0 ? 0 : (c >= RR ? RR - 1 : c);
-        while (c > 0 && c * RR - c * (c - 1) / 2 > q) --c;
-        while (c + 1 < RR && (c + 1) * RR - (c + 1) * c / 2 <= q) ++c;
-        cb = c;
-        ra = c + (q - (c * RR - c * (c - 1) / 2));
-    };
-    for (int q = tid; q < ntri; q += kLevThreads) {
-        int ra, cb;
-        tri(q, ra, cb);
-        sA[ra + RR * cb] = 0.0;
-    }
-    for (int r0 = 0; r0 < Ik; r0 += CR) {
-        const int nr = min(CR, Ik - r0);
-        __syncthreads();
-        for (int e = tid; e < nr * RR; e += kLevThreads) sG[e] = G[(int64_t)r0 * RR + e];
-        __syncthreads();
-        for (int q = tid; q < ntri; q += kLevThreads) {
-            int ra, cb;
-            tri(q, ra, cb);
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four chains hide the LDS latency
-            int r = 0;
-            for (; r + 3 < nr; r += 4) {
-                s0 += (double)sG[r * RR + ra] * (double)sG[r * RR + cb];
-                s1 += (double)sG[(r + 1) * RR + ra] * (double)sG[(r + 1) * RR + cb];
-                s2 += (double)sG[(r + 2) * RR + ra] * (double)sG[(r + 2) * RR + cb];
-                s3 += (double)sG[(r + 3) * RR + ra] * (double)sG[(r + 3) * RR + cb];
-            }
-            for (; r < nr; ++r) s0 += (double)sG[r * RR + ra] * (double)sG[r * RR + cb];
-            sA[ra + RR * cb] += (s0 + s1) + (s2 + s3);
-        }
-    }
-    if (tid == 0) bad = 0;
-    // (2) Cholesky
-    for (int j = 0; j < RR; ++j) {
-        __syncthreads();
-        const double djj = sA[j + RR * j];
-        if (!(djj > 0.0) || !isfinite(djj)) {
-            if (tid == 0) bad = 1;
-            break;
-        }
-        const double ljj = sqrt(djj);
-        __syncthreads();
-        for (int i = j + tid; i < RR; i += kLevThreads) sA[i + RR * j] = i == j ? ljj : sA[i + RR * j] / ljj;
-        __syncthreads();
-        const int wd = RR - j - 1;
-        for (int e = tid; e < wd * wd; e += kLevThreads) {
-            const int i = j + 1 + e % wd, c = j + 1 + e / wd;
-            if (c <= i) sA[i + RR * c] -= sA[i + RR * j] * sA[c + RR * j];
-        }
-    }
-    __syncthreads();
-    if (bad) {
-        if (tid == 0) set_status(status, TR_DEV_NOT_SPD);
+// Weights floor(l_i / RR 2^40) + 1 and their CDF (one block); a factor that
+// is not positive definite (the sweep's verdict) gives the uniform law and
+// TR_DEV_NOT_SPD, I_k <= RR gives the uniform law (every score is 1).
+__global__ __launch_bounds__(1024) void k_lev_cdf(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
+                                                  const double* __restrict__ lev, const int* __restrict__ flag,
+                                                  MutPtrs cdf_out, int32_t* status, uint64_t* bump, int lds_rows) {
+    uint64_t t;
+    int k = k_fixed;
+    if (use_mode) resolve_mode(ms, d.N, &t, &k);
+    const int Ik = d.I[k];
+    const int RR = d.R[k] * d.R[ring_next(k, d.N)];
+    uint64_t* cdf = static_cast<uint64_t*>(cdf_out.p[k]);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint64_t* w = Ik <= lds_rows ? reinterpret_cast<uint64_t*>(smem_raw) : cdf;
+    if (Ik <= RR) {
         write_uniform_weights(w, Ik);
-        block_scan_u64(w, Ik);
-        return;
+    } else if (*flag != 0) {
+        if (threadIdx.x == 0) set_status(status, TR_DEV_NOT_SPD);
+        write_uniform_weights(w, Ik);
+    } else {
+        for (int i = threadIdx.x; i < Ik; i += blockDim.x) w[i] = quantize(lev[i] / (double)RR);
+        __syncthreads();
     }
-    // (3) L^{-1} in place
-    for (int j = RR - 1; j >= 0; --j) {
-        for (int i = j + 1 + tid; i < RR; i += kLevThreads) scol[i] = sA[i + RR * j];
-        __syncthreads();
-        const double dj = 1.0 / sA[j + RR * j];
-        double x = 0.0;
-        const int i = j + 1 + tid;
-        if (i < RR) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int c = j + 1;
-            for (; c + 3 <= i; c += 4) {
-                s0 += sA[i + RR * c] * scol[c];
-                s1 += sA[i + RR * (c + 1)] * scol[c + 1];
-                s2 += sA[i + RR * (c + 2)] * scol[c + 2];
-                s3 += sA[i + RR * (c + 3)] * scol[c + 3];
-            }
-            for (; c <= i; ++c) s0 += sA[i + RR * c] * scol[c];
-            x = -dj * ((s0 + s1) + (s2 + s3));
-        }
-        __syncthreads();
-        if (i < RR) sA[i + RR * j] = x;
-        if (tid == 0) sA[j + RR * j] = dj;
-    }
-    __syncthreads();
-    // (4) leverage scores, TPR threads per row
-    int TPR = 8;   // threads per row: rows per round = 1024 / TPR <= CR (CR >= 16 for RR <= 128)
-    while (TPR < 64 && TPR * CR < kLevThreads) TPR <<= 1;
-    const int RPB = kLevThreads / TPR;
-    for (int r0 = 0; r0 < Ik; r0 += RPB) {
-        const int nr = min(RPB, Ik - r0);
-        __syncthreads();
-        for (int e = tid; e < nr * RR; e += kLevThreads) sG[e] = G[(int64_t)r0 * RR + e];
-        __syncthreads();
-        const int rl = tid / TPR, sub = tid - rl * TPR;
-        double s2 = 0.0;
-        if (rl < nr) {
-            const TC* g = sG + rl * RR;
-            for (int j = sub; j < RR; j += TPR) {
-                double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-                int c = 0;
-                for (; c + 3 <= j; c += 4) {
-                    v0 += sA[j + RR * c] * (double)g[c];
-                    v1 += sA[j + RR * (c + 1)] * (double)g[c + 1];
-                    v2 += sA[j + RR * (c + 2)] * (double)g[c + 2];
-                    v3 += sA[j + RR * (c + 3)] * (double)g[c + 3];
-                }
-                for (; c <= j; ++c) v0 += sA[j + RR * c] * (double)g[c];
-                const double v = (v0 + v1) + (v2 + v3);
-                s2 += v * v;
-            }
-        }
-        for (int o = TPR >> 1; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
-        if (rl < nr && sub == 0) lev[r0 + rl] = s2;
-    }
-    __syncthreads();
-    for (int i = tid; i < Ik; i += kLevThreads) w[i] = quantize(lev[i] / (double)RR);
-    __syncthreads();
-    block_scan_u64(w, Ik);
+    finish_cdf(w, cdf, Ik, bump);
+}
+
+struct LevWs {
+    GramWs g;
+    size_t gram_off, upd_off, lev_off, total;
+    UpdWs u;
+};
+
+static LevWs lev_ws_layout(const tr_desc& d) {
+    const Shape sh = shape_of(d);
+    LevWs L{};
+    L.g = gram_ws_layout(d, sh.maxI);
+    L.gram_off = L.g.total;
+    L.upd_off = L.gram_off + align_up((size_t)sh.maxRR * sh.maxRR * 8);
+    L.u = UpdWs{};
+    L.u.L_off = 0;
+    L.u.flag_off = align_up((size_t)sh.maxRR * sh.maxRR * 8);
+    L.u.total = L.u.flag_off + 256;
+    L.lev_off = L.upd_off + L.u.total;
+    L.total = L.lev_off + align_up((size_t)sh.maxI * 8);
+    return L;
 }
 
 size_t dist_ws_bytes(const tr_desc& d, int law) {
     const Shape sh = shape_of(d);
-    return law == TR_LAW_LEVERAGE ? align_up((size_t)sh.maxRR * sh.maxRR * 8) : 256;
+    if (law == TR_LAW_EUCLID) return align_up((size_t)sh.maxI * 8);   // row norms
+    if (law != TR_LAW_LEVERAGE) return 256;
+    return sh.maxRR <= 128 ? lev_ws_layout(d).total : align_up((size_t)sh.maxRR * sh.maxRR * 8);
 }
 
 hipError_t launch_dist(const tr_desc& d, ModeSrc ms, bool use_mode, int k, int law, Ptrs cores,
-                       uint64_t* const* cdf_out, int32_t* status, void* ws, hipStream_t st) {
+                       uint64_t* const* cdf_out, int32_t* status, void* ws, hipStream_t st, uint64_t* bump) {
     MutPtrs out{};
     for (int q = 0; q < d.N; ++q) out.p[q] = cdf_out[q];
     const bool f64 = d.core_dtype == TR_F64;
+    const Shape sh = shape_of(d);
+    const int lds_rows = sh.maxI <= kLdsRows ? sh.maxI : 0;
+    const size_t lds = (size_t)lds_rows * 8;
     if (law == TR_LAW_EUCLID) {
+        double* rn = static_cast<double*>(ws);
+        const dim3 grid((sh.maxI + kEucRows - 1) / kEucRows);
         if (f64)
-            hipLaunchKernelGGL(k_dist_euclid<double>, dim3(1), dim3(1024), 0, st, d, ms, (int)use_mode, k, cores,
-                               out, status);
+            hipLaunchKernelGGL(k_euc_rows<double>, grid, dim3(256), 0, st, d, ms, (int)use_mode, k, cores, rn);
         else
-            hipLaunchKernelGGL(k_dist_euclid<float>, dim3(1), dim3(1024), 0, st, d, ms, (int)use_mode, k, cores,
-                               out, status);
-    } else if (law == TR_LAW_LEVERAGE && shape_of(d).maxRR <= 128) {
-        const int RR = use_mode ? shape_of(d).maxRR : d.R[k] * d.R[(k + 1) % d.N];
-        const int es = f64 ? 8 : 4;
-        const int CR = lev_chunk_rows(RR, es);
-        const size_t shm = (size_t)RR * RR * 8 + (size_t)RR * 8 + (size_t)CR * RR * es;
-#define TRK_LEV(TC)                                                                                         \
-    do {                                                                                                    \
-        if (!allow_lds(reinterpret_cast<const void*>(&k_dist_leverage_lds<TC>), shm)) return hipErrorInvalidValue; \
-        hipLaunchKernelGGL(k_dist_leverage_lds<TC>, dim3(1), dim3(kLevThreads), shm, st, d, ms, (int)use_mode, k,  \
-                           cores, out, status, CR);                                                         \
-    } while (0)
-        if (f64) TRK_LEV(double);
-        else TRK_LEV(float);
-#undef TRK_LEV
+            hipLaunchKernelGGL(k_euc_rows<float>, grid, dim3(256), 0, st, d, ms, (int)use_mode, k, cores, rn);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_euc_cdf, dim3(1), dim3(1024), lds, st, d, ms, (int)use_mode, k, rn, out, status, bump,
+                           lds_rows);
+    } else if (law == TR_LAW_LEVERAGE && sh.maxRR <= 128) {
+        // the mode source of the Gram, the inverse and the scores: the step's
+        // mode, or core k
+        const ModeSrc mk = use_mode ? ms : ModeSrc{nullptr, 0, k, 0};
+        const LevWs L = lev_ws_layout(d);
+        char* w = static_cast<char*>(ws);
+        double* gram = reinterpret_cast<double*>(w + L.gram_off);
+        hipError_t e = launch_gram(d, mk, nullptr, nullptr, sh.maxI, gram, w, L.g, st, nullptr, cores);
+        if (e != hipSuccess) return e;
+        // no status from the inverse: a factor that is not positive definite
+        // is reported by the CDF kernel as the law's own failure
+        e = launch_sweep_inverse(d, mk, gram, 0.0, L.u, w + L.upd_off, nullptr, st);
+        if (e != hipSuccess) return e;
+        const double* hm = reinterpret_cast<const double*>(w + L.upd_off + L.u.L_off);
+        const int* flag = reinterpret_cast<const int*>(w + L.upd_off + L.u.flag_off);
+        double* lev = reinterpret_cast<double*>(w + L.lev_off);
+        const dim3 grid((sh.maxI + kLevRows - 1) / kLevRows);
+        if (f64)
+            hipLaunchKernelGGL(k_lev_rows<double>, grid, dim3(256), 0, st, d, ms, (int)use_mode, k, cores, hm, lev);
+        else
+            hipLaunchKernelGGL(k_lev_rows<float>, grid, dim3(256), 0, st, d, ms, (int)use_mode, k, cores, hm, lev);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_lev_cdf, dim3(1), dim3(1024), lds, st, d, ms, (int)use_mode, k, lev, flag, out, status,
+                           bump, lds_rows);
     } else if (law == TR_LAW_LEVERAGE) {
         double* A = static_cast<double*>(ws);
         if (f64)
             hipLaunchKernelGGL(k_dist_leverage<double>, dim3(1), dim3(1024), 0, st, d, ms, (int)use_mode, k,
-                               cores, out, status, A);
+                               cores, out, status, A, bump);
         else
             hipLaunchKernelGGL(k_dist_leverage<float>, dim3(1), dim3(1024), 0, st, d, ms, (int)use_mode, k,
-                               cores, out, status, A);
+                               cores, out, status, A, bump);
     } else {
         return hipErrorInvalidValue;
     }

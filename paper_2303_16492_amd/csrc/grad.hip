@@ -301,11 +301,16 @@ template <typename TC>
 __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, const TC* __restrict__ S,
                                                       const double* __restrict__ pF, int m, int groups,
                                                       int tiles_max, double* __restrict__ part,
-                                                      int maxRR2) {
+                                                      int maxRR2, Ptrs rows) {
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
     const int RR = d.R[n] * d.R[ring_next(n, d.N)];
+    // S null: the rows are those of G_{n(2)} itself (I_n of them), unweighted
+    if (!S) {
+        S = static_cast<const TC*>(rows.p[n]);
+        m = d.I[n];
+    }
     const int tpd = (RR + kGramT - 1) / kGramT;
     const int tile = blockIdx.x;
     if (tile >= tpd * (tpd + 1) / 2) return;
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
     __shared__ TC sA[kGramF][kGramT + 1], sB[kGramF][kGramT + 1];
     __shared__ double sw[kGramF];
     const int tid = threadIdx.x;
-    const double wbase = 1.0 / ((double)m * (double)J_of(d, n));
+    const double wbase = pF ? 1.0 / ((double)m * (double)J_of(d, n)) : 1.0;
     const int per = (m + groups - 1) / groups;
     const int fb = blockIdx.y * per, fe = min(m, fb + per);
     // wavefront w computes the 16 x 16 quadrant (qr, qc) of the tile on the
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
             const int c = tid & (kGramT - 1), fo = tid >> 5;
             TC av[V], bv[V];
             double pv = 1.0;
-            if (tid < kGramF) pv = f0 + tid < fe ? pF[f0 + tid] : 1.0;
+            if (tid < kGramF && pF) pv = f0 + tid < fe ? pF[f0 + tid] : 1.0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int f = fo + 8 * v;
@@ -417,17 +422,17 @@ GramWs gram_ws_layout(const tr_desc& d, int m) {
 }
 
 hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double* pF, int m, double* gram,
-                       void* ws, const GramWs& L, hipStream_t st, hipEvent_t mid) {
+                       void* ws, const GramWs& L, hipStream_t st, hipEvent_t mid, Ptrs rows) {
     const Shape sh = shape_of(d);
     const int maxRR2 = sh.maxRR * sh.maxRR;
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + L.part_off);
     const dim3 grid(L.tiles, L.groups);
     if (d.core_dtype == TR_F64)
         hipLaunchKernelGGL(k_gram_partial<double>, grid, dim3(256), 0, st, d, ms,
-                           static_cast<const double*>(S), pF, m, L.groups, L.tiles, part, maxRR2);
+                           static_cast<const double*>(S), pF, m, L.groups, L.tiles, part, maxRR2, rows);
     else
         hipLaunchKernelGGL(k_gram_partial<float>, grid, dim3(256), 0, st, d, ms,
-                           static_cast<const float*>(S), pF, m, L.groups, L.tiles, part, maxRR2);
+                           static_cast<const float*>(S), pF, m, L.groups, L.tiles, part, maxRR2, rows);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (mid && (e = hipEventRecord(mid, st)) != hipSuccess) return e;

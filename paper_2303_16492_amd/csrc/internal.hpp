@@ -100,8 +100,11 @@ struct GramWs {
 GramWs gram_ws_layout(const tr_desc& d, int m);
 // ``mid`` (optional) is recorded between the per-group sums and their
 // reduction.
+// With S null and pF null: the unweighted Gram G_{n(2)}^T G_{n(2)} of the
+// step's core, rows taken from ``rows`` (m ignored; L laid out for maxI).
 hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double* pF, int m,
-                       double* gram, void* ws, const GramWs& L, hipStream_t st, hipEvent_t mid = nullptr);
+                       double* gram, void* ws, const GramWs& L, hipStream_t st, hipEvent_t mid = nullptr,
+                       Ptrs rows = Ptrs{});
 
 // a7/a8: Cholesky of gram + damping (with fallback) then solve and update.
 struct UpdWs {
@@ -128,8 +131,10 @@ hipError_t launch_plain_update(const tr_desc& d, ModeSrc ms, const void* g, MutP
 
 // a2: laws.
 size_t dist_ws_bytes(const tr_desc& d, int law);
+// bump (optional): the step counter the law's last kernel advances.
 hipError_t launch_dist(const tr_desc& d, ModeSrc ms, bool use_mode, int k, int law, Ptrs cores,
-                       uint64_t* const* cdf_out, int32_t* status, void* ws, hipStream_t st);
+                       uint64_t* const* cdf_out, int32_t* status, void* ws, hipStream_t st,
+                       uint64_t* bump = nullptr);
 size_t dist_opt_ws_bytes(const tr_desc& d);
 hipError_t launch_dist_optimal(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs,
                                uint64_t* cdf_J, int32_t* status, void* ws, hipStream_t st);
