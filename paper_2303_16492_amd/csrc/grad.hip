@@ -207,12 +207,15 @@ GradWs grad_ws_layout(const tr_desc& d, int m, int prec) {
     GradWs L{};
     const Shape sh = shape_of(d);
     const bool f64 = d.core_dtype == TR_F64;
-    L.ti = f64 ? GradCfg<double>::TI : 64;   // FP32 runs the matrix-core kernel (64 x 64 tiles)
+    L.ti = f64 ? GradCfg<double>::TI : 64;   // FP32 runs the matrix-core kernel (64-row tiles)
     L.tf = f64 ? GradCfg<double>::TF : 64;
     L.row_tiles = (sh.maxI + L.ti - 1) / L.ti;
-    const int nchunks = (m + L.tf - 1) / L.tf;
     // about one block per CU: fewer partial slices to add afterwards
     int groups = ((f64 ? 512 : 256) + L.row_tiles - 1) / L.row_tiles;
+    // FP32 with R_n R_{n+1} <= 128: chunks of 128 samples when that still
+    // gives at least half of those blocks
+    if (!f64 && sh.maxRR <= 128 && 2 * ((m + 127) / 128) >= groups) L.tf = 128;
+    const int nchunks = (m + L.tf - 1) / L.tf;
     groups = groups < 1 ? 1 : groups;
     groups = groups > nchunks ? nchunks : groups;
     const int cpg = (nchunks + groups - 1) / groups;
@@ -250,7 +253,7 @@ hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
     } else {
         return launch_grad_mfma_f32(d, ms, cores, xs, idx, static_cast<const float*>(S), pF, m, L.groups, L.row_tiles,
                                     reinterpret_cast<float*>(w + L.gpart_off), reinterpret_cast<double*>(w + L.lpart_off),
-                                    st);
+                                    L.tf, st);
     }
     return hipGetLastError();
 }

@@ -19,13 +19,30 @@ namespace trk {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMfTI = 64, kMfTF = 64, kMfEP = kMfTF + 4;
+constexpr int kMfTI = 64;
 
 // Row pitch of the staged S chunk: >= RRc and = 20 (mod 64) so that the
 // 16 x 4 lane patterns of both GEMMs fall in distinct LDS banks.
 __host__ __device__ constexpr int mf_pitch(int RRc) { return RRc + ((20 - RRc % 64) + 64) % 64; }
 
-template <typename TX, int CT>
+// Four consecutive tensor entries from a 4-element-aligned address.
+__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+}
+__device__ __forceinline__ void load4(const __half* p, float (&v)[4]) {
+    const uint2 q = *reinterpret_cast<const uint2*>(p);
+    const __half2 a = *reinterpret_cast<const __half2*>(&q.x), b = *reinterpret_cast<const __half2*>(&q.y);
+    v[0] = __low2float(a);
+    v[1] = __high2float(a);
+    v[2] = __low2float(b);
+    v[3] = __high2float(b);
+}
+
+template <typename TX, int CT, int TF>
 __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Ptrs cores, XSrc xsrc,
                                                        const int32_t* __restrict__ idx, const float* __restrict__ S,
                                                        const double* __restrict__ pF, int m, int groups,
@@ -34,20 +51,21 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
     const int N = d.N;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     constexpr int SB = (16 * CT + 63) / 64;   // 64-column strips of a staged row
-    const int nchunks = (m + kMfTF - 1) / kMfTF;
+    constexpr int EP = TF + 4;   // row pitch of the staged E tile
+    const int nchunks = (m + TF - 1) / TF;
     const int cpg = (nchunks + groups - 1) / groups;
     const int cbeg = blockIdx.y * cpg, cend = min(nchunks, cbeg + cpg);
     // The next chunk's operands are held in registers until its turn: S rows
-    // (16 per wavefront), the sample's indices and probability (every thread
-    // loads those of sample tid % 64; the first 64 use them).  Clamped
+    // (TF / 4 per wavefront), the sample's indices and probability (every
+    // thread loads those of sample tid % TF; the first TF use them).  Clamped
     // indices, no load behind a branch.
-    float v[16][SB];
+    float v[TF / 4][SB];
     int ik[kMaxOrder];
     double pf = 1.0;
     auto load_chunk = [&](int ch, int RRl) {
-        const int f0 = ch * kMfTF;
+        const int f0 = ch * TF;
 #pragma unroll
-        for (int a = 0; a < 16; ++a) {
+        for (int a = 0; a < TF / 4; ++a) {
             const int f = f0 + w + 4 * a;
             const float* src = S + (int64_t)(f < m ? f : m - 1) * RRl;
 #pragma unroll
@@ -56,7 +74,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
                 v[a][b] = src[c < RRl ? c : RRl - 1];
             }
         }
-        const int fi = f0 + l;
+        const int fi = f0 + (tid & (TF - 1));
         const int64_t fc = fi < m ? fi : m - 1;
 #pragma unroll
         for (int k = 0; k < kMaxOrder; ++k) ik[k] = idx[fc * N + (k < N ? k : N - 1)];
@@ -81,10 +99,10 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float* sS = reinterpret_cast<float*>(smem_raw);             // [TF][RRs]
-    float* sE = sS + kMfTF * RRs;                               // [TI][EP]
-    float* sW = sE + kMfTI * kMfEP;                             // [TF]
-    double* sL = reinterpret_cast<double*>(sW + kMfTF);         // [TF]
-    int64_t* sB = reinterpret_cast<int64_t*>(sL + kMfTF);       // [TF]
+    float* sE = sS + TF * RRs;                                  // [TI][EP]
+    float* sW = sE + kMfTI * EP;                                // [TF]
+    double* sL = reinterpret_cast<double*>(sW + TF);            // [TF]
+    int64_t* sB = reinterpret_cast<int64_t*>(sL + TF);          // [TF]
 
     // A operand of GEMM1: this lane's G row, K in steps of 4.
     const float* Gn = static_cast<const float*>(cores.p[n]);
@@ -124,18 +142,18 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
 
     if (rr_fixed <= 0 && cbeg < cend) load_chunk(cbeg, RR);
     for (int ch = cbeg; ch < cend; ++ch) {
-        const int f0 = ch * kMfTF;
+        const int f0 = ch * TF;
         __syncthreads();
         // the staged chunk into LDS
 #pragma unroll
-        for (int a = 0; a < 16; ++a)
+        for (int a = 0; a < TF / 4; ++a)
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
                 const int c = l + 64 * b;
                 const bool ok = f0 + w + 4 * a < m && c < RR;
                 if (c < RRT) sS[(w + 4 * a) * RRs + c] = ok ? v[a][b] : 0.f;
             }
-        if (tid < kMfTF) {
+        if (tid < TF) {
             const int f = f0 + tid;
             bool ok = f < m;
             int64_t off = 0;
@@ -155,38 +173,50 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
         __syncthreads();
         // Fiber entries this lane needs, loaded before GEMM1 so that the HBM
         // latency overlaps the matrix-core work (clamped, branch-free).
-        float xv[4][4];
+        constexpr int NU = TF / 16;   // 16-sample tiles of the chunk
+        float xv[NU][4];
+        if (xsn == 1 && (In & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & (4 * sizeof(TX) - 1)) == 0) {
+            // contiguous fibers and whole 4-row groups: one 4-wide load per
+            // sample (aligned: every fiber offset is a multiple of I_n)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int fl = 16 * u + lr;
-            const bool okf = sW[fl] != 0.f;
-            const int64_t base = sB[fl];
+            for (int u = 0; u < NU; ++u) {
+                const int fl = 16 * u + lr;
+                const bool ok4 = sW[fl] != 0.f && i0 + erow < In;
+                load4(X + (ok4 ? sB[fl] + i0 + erow : 0), xv[u]);
+            }
+        } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = i0 + erow + j;
-                const int64_t o = (okf && row < In) ? base + (int64_t)row * xsn : 0;
-                xv[u][j] = (float)to_f64(X[o]);
+            for (int u = 0; u < NU; ++u) {
+                const int fl = 16 * u + lr;
+                const bool okf = sW[fl] != 0.f;
+                const int64_t base = sB[fl];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = i0 + erow + j;
+                    const int64_t o = (okf && row < In) ? base + (int64_t)row * xsn : 0;
+                    xv[u][j] = (float)to_f64(X[o]);
+                }
             }
         }
         // the next chunk's operands, in flight during this chunk's products
         if (ch + 1 < cend) load_chunk(ch + 1, RR);
 
         // GEMM1: P[16w + 4lk + j][16t + lr]
-        f32x4 p[4];
+        f32x4 p[NU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int u = 0; u < NU; ++u) p[u] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
             const float a = ag[q];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < NU; ++u) {
                 const float b = sS[(16 * u + lr) * RRs + 4 * q + lk];
                 p[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, p[u], 0, 0, 0);
             }
         }
         // E = X_F - P, scaled; loss estimate
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < NU; ++u) {
             const int fl = 16 * u + lr;
             const float wf = sW[fl];
             const double lf = sL[fl];
@@ -195,14 +225,14 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
                 const bool ok = (i0 + erow + j < In) && wf != 0.f;
                 const float e = ok ? xv[u][j] - p[u][j] : 0.f;
                 lsum += (double)e * (double)e * lf;
-                sE[(erow + j) * kMfEP + fl] = -e * wf;
+                sE[(erow + j) * EP + fl] = -e * wf;
             }
         }
         __syncthreads();
         // GEMM2: g[16w + 4lk + j][16ct + lr] += sum_f E[.][f] S[f][.]
 #pragma unroll
-        for (int q = 0; q < kMfTF / 4; ++q) {
-            const float a = sE[(16 * w + lr) * kMfEP + 4 * q + lk];
+        for (int q = 0; q < TF / 4; ++q) {
+            const float a = sE[(16 * w + lr) * EP + 4 * q + lk];
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 const float b = sS[(4 * q + lk) * RRs + 16 * c + lr];
@@ -225,33 +255,48 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
     if (tid == 0) lpart[(int64_t)blockIdx.y * row_tiles_max + blockIdx.x] = tot;
 }
 
-template <int CT>
+template <int CT, int TF>
 static constexpr size_t grad_mfma_shm() {
-    return (size_t)(kMfTF * mf_pitch(16 * CT) + kMfTI * kMfEP + kMfTF) * 4 + (size_t)kMfTF * 16 + 64;
+    return (size_t)(TF * mf_pitch(16 * CT) + kMfTI * (TF + 4) + TF) * 4 + (size_t)TF * 16 + 64;
 }
 
-template <typename TX, int CT>
-static hipError_t launch_ct(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
-                            const double* pF, int m, dim3 grid, int groups, int row_tiles, float* gp, double* lp,
-                            int maxIRR, hipStream_t st) {
-    constexpr size_t shm = grad_mfma_shm<CT>();
-    if (!allow_lds(reinterpret_cast<const void*>(&k_grad_mfma_f32<TX, CT>), shm)) return hipErrorInvalidValue;
+template <typename TX, int CT, int TF>
+static hipError_t launch_ctf(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
+                             const double* pF, int m, dim3 grid, int groups, int row_tiles, float* gp, double* lp,
+                             int maxIRR, hipStream_t st) {
+    constexpr size_t shm = grad_mfma_shm<CT, TF>();
+    if (!allow_lds(reinterpret_cast<const void*>(&k_grad_mfma_f32<TX, CT, TF>), shm)) return hipErrorInvalidValue;
     int rr_fixed = d.R[0] * d.R[1 % d.N];
     for (int k = 1; k < d.N; ++k)
         if (d.R[k] * d.R[(k + 1) % d.N] != rr_fixed) rr_fixed = 0;
-    hipLaunchKernelGGL((k_grad_mfma_f32<TX, CT>), grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
-                       row_tiles, gp, lp, maxIRR, rr_fixed);
+    hipLaunchKernelGGL((k_grad_mfma_f32<TX, CT, TF>), grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m,
+                       groups, row_tiles, gp, lp, maxIRR, rr_fixed);
     return hipGetLastError();
+}
+
+// Chunks of 128 samples (one pass per block over twice the samples, half
+// the dependent staging rounds) for up to 8 column tiles; 64 otherwise.
+template <typename TX, int CT>
+static hipError_t launch_ct(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
+                            const double* pF, int m, dim3 grid, int groups, int row_tiles, float* gp, double* lp,
+                            int maxIRR, int tf, hipStream_t st) {
+    if constexpr (CT <= 8) {
+        if (tf == 128)
+            return launch_ctf<TX, CT, 128>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
+                                           st);
+    }
+    return launch_ctf<TX, CT, 64>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st);
 }
 
 // Smallest compiled tile count covering ceil(maxRR / 16) column tiles.
 template <typename TX>
 static hipError_t launch_tx(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
                             const double* pF, int m, dim3 grid, int groups, int row_tiles, float* gp, double* lp,
-                            int maxIRR, int maxRR, hipStream_t st) {
+                            int maxIRR, int maxRR, int tf, hipStream_t st) {
     const int nct = (maxRR + 15) / 16;
-#define TRK_CT(C) \
-    if (nct <= C) return launch_ct<TX, C>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st)
+#define TRK_CT(C)                                                                                              \
+    if (nct <= C)                                                                                              \
+    return launch_ct<TX, C>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, tf, st)
     TRK_CT(1);
     TRK_CT(2);
     TRK_CT(3);
@@ -269,17 +314,17 @@ static hipError_t launch_tx(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, c
 
 hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
                                 const float* S, const double* pF, int m, int groups, int row_tiles, float* gp,
-                                double* lp, hipStream_t st) {
+                                double* lp, int tf, hipStream_t st) {
     const Shape sh = shape_of(d);
     const dim3 grid(row_tiles, groups);
     const int maxIRR = sh.maxI * sh.maxRR;
     switch (d.x_dtype) {
         case TR_F32:
             return launch_tx<float>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
-                                    sh.maxRR, st);
+                                    sh.maxRR, tf, st);
         case TR_F16:
             return launch_tx<__half>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
-                                     sh.maxRR, st);
+                                     sh.maxRR, tf, st);
         default:
             return hipErrorInvalidValue;
     }

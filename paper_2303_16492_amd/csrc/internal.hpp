@@ -34,9 +34,10 @@ struct GradWs {
     int groups, row_tiles, ti, tf;
 };
 GradWs grad_ws_layout(const tr_desc& d, int m, int prec);
+// tf: samples per staged chunk (64, or 128 for at most 8 column tiles).
 hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
                                 const float* S, const double* pF, int m, int groups, int row_tiles, float* gp,
-                                double* lp, hipStream_t st);
+                                double* lp, int tf, hipStream_t st);
 hipError_t launch_grad_mixed(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
                              const double* pF, int m, int prec, int groups, int row_tiles, float* gp, double* lp,
                              hipStream_t st);
