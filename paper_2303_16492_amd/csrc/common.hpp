@@ -178,6 +178,23 @@ __device__ inline T block_sum(T v, T* scratch) {
     return s;
 }
 
+// Four consecutive tensor entries from a 4-element-aligned address.
+__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+}
+__device__ __forceinline__ void load4(const __half* p, float (&v)[4]) {
+    const uint2 q = *reinterpret_cast<const uint2*>(p);
+    const __half2 a = *reinterpret_cast<const __half2*>(&q.x), b = *reinterpret_cast<const __half2*>(&q.y);
+    v[0] = __low2float(a);
+    v[1] = __high2float(a);
+    v[2] = __low2float(b);
+    v[3] = __high2float(b);
+}
+
 __device__ inline void set_status(int32_t* st, int32_t bits) {
     if (st && bits) atomicOr(st, bits);
 }

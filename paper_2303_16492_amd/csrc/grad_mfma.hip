@@ -25,23 +25,6 @@ constexpr int kMfTI = 64;
 // 16 x 4 lane patterns of both GEMMs fall in distinct LDS banks.
 __host__ __device__ constexpr int mf_pitch(int RRc) { return RRc + ((20 - RRc % 64) + 64) % 64; }
 
-// Four consecutive tensor entries from a 4-element-aligned address.
-__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
-    const float4 q = *reinterpret_cast<const float4*>(p);
-    v[0] = q.x;
-    v[1] = q.y;
-    v[2] = q.z;
-    v[3] = q.w;
-}
-__device__ __forceinline__ void load4(const __half* p, float (&v)[4]) {
-    const uint2 q = *reinterpret_cast<const uint2*>(p);
-    const __half2 a = *reinterpret_cast<const __half2*>(&q.x), b = *reinterpret_cast<const __half2*>(&q.y);
-    v[0] = __low2float(a);
-    v[1] = __high2float(a);
-    v[2] = __low2float(b);
-    v[3] = __high2float(b);
-}
-
 template <typename TX, int CT, int TF>
 __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Ptrs cores, XSrc xsrc,
                                                        const int32_t* __restrict__ idx, const float* __restrict__ S,

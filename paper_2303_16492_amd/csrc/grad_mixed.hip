@@ -83,14 +83,23 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
 
     // A operand of GEMM1: this lane's G row split hi/lo, 8 values per K step.
     const float* Gn = static_cast<const float*>(cores.p[n]);
-    const int grow = i0 + 16 * w + lr;
+    // (loads at clamped indices, masked afterwards: none behind a branch)
+    const int grow = i0 + 16 * w + lr, growc = grow < In ? grow : In - 1;
+    float gv[KS][8];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 32 * s + 8 * lk + i;
+            gv[s][i] = Gn[(int64_t)growc * RR + (k < RR ? k : RR - 1)];
+        }
     v8 ah[KS], al[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int k = 32 * s + 8 * lk + i;
-            const float g = (grow < In && k < RR) ? Gn[(int64_t)grow * RR + k] : 0.f;
+            const float g = (grow < In && k < RR) ? gv[s][i] : 0.f;
             const T16 h = (T16)g;
             ah[s][i] = h;
             al[s][i] = (T16)(g - (float)h);
@@ -131,14 +140,18 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
 #pragma unroll
             for (int a = 0; a < 16; ++a) {
                 const int f = w + 4 * a;
-                const bool okf = f0 + f < m;
-                const float* src = S + (int64_t)(f0 + f) * RR;
+                const float* src = S + (int64_t)(f0 + f < m ? f0 + f : m - 1) * RR;
 #pragma unroll
                 for (int b = 0; b < SB; ++b) {
                     const int c = l + 64 * b;
-                    v[a][b] = (okf && c < RR) ? src[c] : 0.f;
+                    v[a][b] = src[c < RR ? c : RR - 1];
                 }
             }
+#pragma unroll
+            for (int a = 0; a < 16; ++a)
+#pragma unroll
+                for (int b = 0; b < SB; ++b)
+                    if (!(f0 + w + 4 * a < m && l + 64 * b < RR)) v[a][b] = 0.f;
 #pragma unroll
             for (int a = 0; a < 16; ++a) {
                 const int f = w + 4 * a;
@@ -163,8 +176,12 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
             bool ok = f < m;
             int64_t off = 0;
             int ik[kMaxOrder];
+            const int64_t fc = ok ? f : m - 1;
 #pragma unroll
-            for (int k = 0; k < kMaxOrder; ++k) ik[k] = (ok && k < N) ? idx[(int64_t)f * N + k] : 0;
+            for (int k = 0; k < kMaxOrder; ++k) ik[k] = idx[fc * N + (k < N ? k : N - 1)];
+            const double pf = pF[fc];
+#pragma unroll
+            for (int k = 0; k < kMaxOrder; ++k) ik[k] = (ok && k < N) ? ik[k] : 0;
 #pragma unroll
             for (int k = 0; k < kMaxOrder; ++k) {
                 if (k >= N || k == n) continue;
@@ -172,21 +189,32 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
                 off += (int64_t)ik[k] * xs[k];
             }
             sB[tid] = ok ? off : 0;
-            sW[tid] = ok ? (float)(wbase / pF[f]) : 0.f;
-            sL[tid] = ok ? 1.0 / (2.0 * (double)m * pF[f]) : 0.0;
+            sW[tid] = ok ? (float)(wbase / pf) : 0.f;
+            sL[tid] = ok ? 1.0 / (2.0 * (double)m * pf) : 0.0;
         }
         __syncthreads();
         float xv[4][4];
+        if (xsn == 1 && (In & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & (4 * sizeof(TX) - 1)) == 0) {
+            // contiguous fibers and whole 4-row groups: one 4-wide load per
+            // sample (aligned: every fiber offset is a multiple of I_n)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int fl = 16 * u + lr;
-            const bool okf = sW[fl] != 0.f;
-            const int64_t base = sB[fl];
+            for (int u = 0; u < 4; ++u) {
+                const int fl = 16 * u + lr;
+                const bool ok4 = sW[fl] != 0.f && i0 + erow < In;
+                load4(X + (ok4 ? sB[fl] + i0 + erow : 0), xv[u]);
+            }
+        } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = i0 + erow + j;
-                const int64_t o = (okf && row < In) ? base + (int64_t)row * xsn : 0;
-                xv[u][j] = (float)to_f64(X[o]);
+            for (int u = 0; u < 4; ++u) {
+                const int fl = 16 * u + lr;
+                const bool okf = sW[fl] != 0.f;
+                const int64_t base = sB[fl];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = i0 + erow + j;
+                    const int64_t o = (okf && row < In) ? base + (int64_t)row * xsn : 0;
+                    xv[u][j] = (float)to_f64(X[o]);
+                }
             }
         }
         // GEMM1 (three products)
