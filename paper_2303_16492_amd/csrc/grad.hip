@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_grad_reduce(tr_desc d, ModeSrc ms, cons
             apply_rule<TC>(G, A, e, -(double)acc, rule, t, status);
         }
     }
-    bump_if_last(step);
+    bump_if_last(step, rule.kind == 2);
 }
 
 GradWs grad_ws_layout(const tr_desc& d, int m, int prec) {

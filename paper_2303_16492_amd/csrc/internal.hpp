@@ -64,19 +64,28 @@ __device__ inline double loss_parts_sum(const LossParts& lp, int In, double* red
     return block_sum(s, red);
 }
 
-// Step-counter advance folded into the last kernel of a step: every block
-// counts itself in ``ctr`` once it is done; the last one resets ``ctr`` and
-// adds 1 to ``t``.  No fence is needed: a block's read of t has completed
-// before its count (its addresses depend on the mode drawn from t), the
-// counter and t change only through device-scope atomics, and the kernels
-// that read t next start after this kernel has ended.  (An agent-scope fence
-// here would write back the L2 once per block.)  Disabled when t is null.
+// Step-counter advance folded into the last kernel of a step.  When the
+// kernel's blocks use t (t_read: the Robbins-Monro rule), every block counts
+// itself in ``ctr`` once it is done and the last one resets ``ctr`` and adds
+// 1 to ``t``.  No fence is needed: a block's read of t has completed before
+// its count (its addresses depend on the mode drawn from t), the counter and
+// t change only through device-scope atomics, and the kernels that read t
+// next start after this kernel has ended.  (An agent-scope fence here would
+// write back the L2 once per block.)  Otherwise every other reader of t in
+// the step has finished before the kernel starts (its blocks take the mode
+// from the published slot and ignore t), and one block adds 1 at once.
+// Disabled when t is null.
 struct StepBump {
     uint64_t* t;
     unsigned* ctr;
 };
-__device__ inline void bump_if_last(const StepBump& b) {
+__device__ inline void bump_if_last(const StepBump& b, bool t_read) {
     if (!b.t) return;
+    if (!t_read) {   // no block uses t: one block advances it, nobody waits
+        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(b.t), 1ull);
+        return;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned nb = gridDim.x * gridDim.y * gridDim.z;

@@ -516,7 +516,7 @@ __global__ __launch_bounds__(64) void k_scaled_apply(tr_desc d, ModeSrc ms, cons
             }
         }
     }
-    bump_if_last(step);
+    bump_if_last(step, rule.kind == 2);
 }
 
 bool sweep_supported(const tr_desc& d) { return shape_of(d).maxRR <= 128; }
