@@ -117,10 +117,25 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
         }
         const float* Gn = static_cast<const float*>(it.cores[n]);
         const _Float16* X = static_cast<const _Float16*>(it.Xrep[n]);
-        // G_n as FP16 A operands for the whole step (K padded with zeros)
-        for (int e = tid; e < kBatchMaxI * kBatchMaxRR; e += NT) {
-            const int row = e / kBatchMaxRR, k = e - row * kBatchMaxRR;
-            sA[row * Lz::SP + k] = (_Float16)((row < In && k < RR) ? Gn[(int64_t)row * RR + k] : 0.f);
+        // G_n as FP16 A operands for the whole step (K padded with zeros);
+        // loads at clamped indices, eight per thread in flight, masked after
+        {
+            constexpr int TOT = kBatchMaxI * kBatchMaxRR, UB = 8;
+            for (int e0 = 0; e0 < TOT; e0 += NT * UB) {
+                float gv[UB];
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = e0 + u * NT + tid;
+                    const int row = e / kBatchMaxRR, k = e - row * kBatchMaxRR;
+                    gv[u] = Gn[(int64_t)(row < In ? row : In - 1) * RR + (k < RR ? k : RR - 1)];
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = e0 + u * NT + tid;
+                    const int row = e / kBatchMaxRR, k = e - row * kBatchMaxRR;
+                    if (e < TOT) sA[row * Lz::SP + k] = (_Float16)((row < In && k < RR) ? gv[u] : 0.f);
+                }
+            }
         }
         f32x4b gacc[GSL];
 #pragma unroll
@@ -183,7 +198,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
 #pragma unroll
                     for (int u = 0; u < 3; ++u) {
                         const int pidx = l + 64 * u, r = pidx % kBatchRank, c = pidx / kBatchRank;
-                        v[j][u] = (ok && pidx < PS && r < Rk && c < Rk1) ? src[r + Rk * c] : 0.f;
+                        v[j][u] = src[(r < Rk ? r : Rk - 1) + Rk * (c < Rk1 ? c : Rk1 - 1)];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const int pidx = l + 64 * u, r = pidx % kBatchRank, c = pidx / kBatchRank;
+                        if (!(ok && pidx < PS && r < Rk && c < Rk1)) v[j][u] = 0.f;
                     }
                 }
 #pragma unroll
@@ -255,7 +275,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
             }
             __syncthreads();
             // E = X_F - G_n S^T: wavefront wv takes row tiles wv (+ WAVES),
-            // all sample tiles; FP16 operands, FP32 accumulation.
+            // all sample tiles; FP16 operands, FP32 accumulation.  The fiber
+            // entries of the wavefront's outputs are loaded first (clamped
+            // rows, all in flight) so no load waits inside the products.
+            float xe[RTW][CH / 16][4];
+#pragma unroll
+            for (int u = 0; u < RTW; ++u)
+#pragma unroll
+                for (int st = 0; st < CH / 16; ++st) {
+                    const int64_t off = soff[16 * st + lr];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = 16 * (wv + WAVES * u) + 4 * lk + j;
+                        xe[u][st][j] = (float)X[off + (i < In ? i : In - 1)];
+                    }
+                }
 #pragma unroll
             for (int u = 0; u < RTW; ++u) {
                 const int rt = wv + WAVES * u;
@@ -271,13 +305,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
                     if (rt < MT) {
                         const int fl = 16 * st + lr;
                         const float ws = sw[fl];
-                        const int64_t off = soff[fl];
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const int i = 16 * rt + 4 * lk + j;
                             float e = 0.f;
                             if (i < In && fl < nb) {
-                                e = (float)X[off + i] - acc[j];
+                                e = xe[u][st][j] - acc[j];
                                 lsum += (double)ws * (double)e * (double)e;
                             }
                             sE[i * Lz::TP + fl] = (_Float16)(e * ws);
@@ -351,7 +384,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
 // The step of problem p after a split gradient: g = sum of the shares in
 // share order, p = g / m (the sign of the direction folded in, as in the
 // unsplit kernel), the rule on the core, the loss estimate, t + 1.
-__global__ __launch_bounds__(256) void k_batch_apply(const tr_batch_item* __restrict__ items, int splits,
+__global__ __launch_bounds__(1024) void k_batch_apply(const tr_batch_item* __restrict__ items, int splits,
                                                      const float* __restrict__ gpart,
                                                      const double* __restrict__ lpart, int64_t gstride) {
     const tr_batch_item& it = items[blockIdx.x];
@@ -365,10 +398,49 @@ __global__ __launch_bounds__(256) void k_batch_apply(const tr_batch_item* __rest
     float* G = static_cast<float*>(it.cores[n]);
     float* A = static_cast<float*>(it.accum[n]);
     const float* gp = gpart + (int64_t)blockIdx.x * splits * gstride;
-    for (int e = threadIdx.x; e < In * RR; e += blockDim.x) {
-        float g = 0.f;
-        for (int q = 0; q < splits; ++q) g += gp[(int64_t)q * gstride + e];
-        apply_rule<float>(G, A, e, (double)(g * invm), it.rule, t, it.dev_status);
+    // eight entries per thread per round, every load of the round in flight
+    // (clamped indices), the shares added in order as before
+    const int tot = In * RR;
+    constexpr int U = 8;
+    for (int e0 = 0; e0 < tot; e0 += (int)blockDim.x * U) {
+        float g[U], gv[U], av[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x, ec = e < tot ? e : tot - 1;
+            g[u] = 0.f;
+            gv[u] = G[ec];
+            av[u] = 0.f;
+        }
+        constexpr int QB = 4;   // shares fetched together
+        for (int q0 = 0; q0 < splits; q0 += QB) {
+            float pv[U][QB];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x, ec = e < tot ? e : tot - 1;
+#pragma unroll
+                for (int qq = 0; qq < QB; ++qq) {
+                    const int q = q0 + qq < splits ? q0 + qq : splits - 1;
+                    pv[u][qq] = gp[(int64_t)q * gstride + ec];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int qq = 0; qq < QB; ++qq)
+                    if (q0 + qq < splits) g[u] += pv[u][qq];
+        }
+        if (it.rule.kind == 1) {   // the accumulator exists only for AdaGrad
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x, ec = e < tot ? e : tot - 1;
+                av[u] = A[ec];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
+            if (e < tot) apply_rule_loaded<float>(G, A, e, gv[u], av[u], (double)(g[u] * invm), it.rule, t, it.dev_status);
+        }
     }
     if (threadIdx.x == 0) {
         double ls = 0.0;
@@ -407,7 +479,7 @@ hipError_t launch_batch_split(const tr_batch_item* items, int count, int steps, 
         else return hipErrorInvalidValue;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_batch_apply, dim3(count), dim3(256), 0, st, items, splits, gpart, lpart, gstride);
+        hipLaunchKernelGGL(k_batch_apply, dim3(count), dim3(1024), 0, st, items, splits, gpart, lpart, gstride);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
 #undef TRK_BSPLIT
