@@ -227,10 +227,30 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
         const int R2 = d.R[2];                       // slices of core 3: R_3 x R_1 (R_{N+1} = R_1)
         const int RR2 = R2 * R0;
         const float* G2 = static_cast<const float*>(cores.p[2]);
-        for (int e = tid; e < n_outer * RR2; e += blockDim.x) sP[e] = G2[(int64_t)o_lo * RR2 + e];
+        {   // the slices of core 3, all loads of a thread in flight (clamped, masked after)
+            constexpr int UB = (kRmMaxOuter * kMaxRR + 255) / 256;
+            const int tot = n_outer * RR2;
+            float pv[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int e = u * 256 + tid;
+                pv[u] = G2[(int64_t)o_lo * RR2 + (e < tot ? e : tot - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u)
+                if (u * 256 + tid < tot) sP[u * 256 + tid] = pv[u];
+        }
+        // column jj of the block: i_2 = (i2_0 + jj) mod I_2, i_3 = i3_0 + (i2_0 + jj) div I_2 (32-bit)
+        const int i2_0 = (int)(j0 % I1), i3_0 = (int)(j0 / I1);
+        int* sI2 = reinterpret_cast<int*>(sP + kRmMaxOuter * kMaxRR);   // [kRmCols]
+        int* sI3 = sI2 + kRmCols;                                         // [kRmCols], relative to o_lo
         for (int e = tid; e < kRmCols; e += blockDim.x) {
             const int64_t j = j0 + e;
-            sOff[e] = j < J ? (j % I1) * d.x_stride[1] + (j / I1) * d.x_stride[2] : -1;
+            const int q = (i2_0 + e) / I1;
+            const int i2 = i2_0 + e - q * I1, i3 = i3_0 + q;
+            sI2[e] = i2;
+            sI3[e] = i3 - o_lo;
+            sOff[e] = j < J ? (int64_t)i2 * d.x_stride[1] + (int64_t)i3 * d.x_stride[2] : -1;
         }
         __syncthreads();
         const float* G1 = static_cast<const float*>(cores.p[1]);
@@ -238,10 +258,11 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
         const int total = kRmCols * R1;
         auto load_row = [&](int e, float (&v)[kMaxRank]) {   // row s of G_2(i_2), clamped in bounds
             const int jj = e / R1, s = e - jj * R1;
-            const int64_t j = j0 + jj < J ? j0 + jj : J - 1;
-            const float* A = G1 + (j % I1) * RR1;
+            const float* A = G1 + (int64_t)sI2[jj] * RR1;
 #pragma unroll
             for (int c = 0; c < kMaxRank; ++c) v[c] = A[min(s + R1 * c, last)];
+#pragma unroll
+            for (int c = 0; c < kMaxRank; ++c) v[c] = c < R2 ? v[c] : 0.f;   // uniform mask
         };
         float v[kMaxRank];
         if (tid < total) load_row(tid, v);
@@ -254,12 +275,14 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
             if (j >= J) {
                 for (int r = 0; r < R0; ++r) out[r] = 0.f;
             } else {
-                const float* P = sP + ((int)(j / I1) - o_lo) * R2 * R0;
+                // every LDS read of a row issued together: no read behind a
+                // branch (entries past R_3 multiply the zeros of v)
+                const float* P = sP + sI3[jj] * R2 * R0;
                 for (int r = 0; r < R0; ++r) {
+                    const float* Pr = P + R2 * r;
                     float acc = 0.f;
 #pragma unroll
-                    for (int c = 0; c < kMaxRank; ++c)
-                        if (c < R2) acc += v[c] * P[c + R2 * r];
+                    for (int c = 0; c < kMaxRank; ++c) acc += v[c] * Pr[c < R2 ? c : R2 - 1];
                     out[r] = acc;
                 }
             }
@@ -402,7 +425,8 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
 }
 
 static size_t recon_mfma_shm(int KT) {
-    return (size_t)kRmCols * 8 + (size_t)kRmCols * (2 * KT + 1) * 4 + (size_t)kRmMaxOuter * kMaxRR * 4;
+    return (size_t)kRmCols * 8 + (size_t)kRmCols * (2 * KT + 1) * 4 + (size_t)kRmMaxOuter * kMaxRR * 4 +
+           (size_t)kRmCols * 8;   // per-column i_2 and i_3 (order 3)
 }
 
 static int64_t recon_mfma_blocks(const tr_desc& d) {
