@@ -303,7 +303,8 @@ def law_rate(args, law, init3, X, I, R, m, dev, K, G=50):
 
 def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, cap=None, scaled=True, alpha=None):
     """Wall time from the initial cores until an RSE check reaches
-    ``target`` (checks every ``every`` steps count toward the time), capped
+    ``target`` (checks every ``every`` steps count toward the time; the steps
+    between checks replay one captured graph), capped
     at ``cap`` (default args.ttt_steps) steps; the scaled method (default)
     or the plain one, fixed step ``alpha`` (default args.alpha)."""
     import torch
@@ -313,20 +314,33 @@ def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, c
     solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law="U", scaled=scaled,
                       prec=prec, rule=api.step_rule("fixed", alpha=args.alpha if alpha is None else alpha),
                       seed=args.seed, overlap=not args.no_overlap)
+    # The ``every`` steps between checks run as one captured HIP graph, as in
+    # the throughput measurement; the capture's warm-up step is undone (cores,
+    # accumulators, step counter restored) before the timer starts.
+    snap = [c.clone() for c in solver.cores]
+    acc_snap = [a.clone() if a is not None else None for a in solver.accum]
+    graph = solver.capture(every)
+    for c, s_ in zip(solver.cores, snap):
+        c.copy_(s_)
+    for a, s_ in zip(solver.accum, acc_snap):
+        if a is not None:
+            a.copy_(s_)
+    solver.t_dev.zero_()
+    solver.status.zero_()
     solver.rse()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cap = args.ttt_steps if cap is None else cap
     steps, rse, hist = 0, float("nan"), []
     while steps < cap:
-        solver.run(every)
+        graph.replay()
         steps += every
         rse = float(solver.rse())          # synchronises
         hist.append((steps, rse))
         if rse <= target:
             break
     wall = time.perf_counter() - t0
-    del solver
+    del graph, solver
     return {"prec": prec, "target": target, "reached": rse <= target,
             "seconds": round(wall, 4) if rse <= target else None, "steps": steps,
             "rse_at_stop": rse, "wall_s_at_stop": round(wall, 4), "rse_every": every,
