@@ -230,10 +230,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_steps(const tr_batch_item*
 #pragma unroll
                         for (int ks = 0; ks < 3; ++ks) {
                             const int kk = 4 * ks + lk;   // K index of this lane
+                            // operands read at clamped indices and masked by a factor
+                            // (a select would put each LDS read behind a branch)
+                            const int lrc = lr < kBatchRank ? lr : kBatchRank - 1;
+                            const float msk = lr < kBatchRank ? 1.f : 0.f;
                             float a;
-                            if (q == 1) a = lr < kBatchRank ? base[lr + kBatchRank * kk] : 0.f;   // slice 0 (row lr)
+                            if (q == 1) a = base[lrc + kBatchRank * kk] * msk;   // slice 0 (row lr)
                             else a = Mw[lr * 16 + kk];
-                            const float b = lr < kBatchRank ? Aq[kk + kBatchRank * lr] : 0.f;
+                            const float b = Aq[kk + kBatchRank * lrc] * msk;
                             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
                         }
                         m = acc;
