@@ -490,3 +490,36 @@ def test_full_size_mixed_gradient_at_bench_configuration():
                                       brsgd.gather_fibers(X, n, idx.cpu().numpy()), pF.cpu().numpy(), I * I)
         assert rel(g.cpu().numpy(), gref) < TOL[torch.bfloat16]
         assert abs(float(loss) - lref) <= TOL[torch.bfloat16] * lref
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_law_degenerate_cores(dtype):
+    """Failure paths of the mode-wise laws: a zero core gives the uniform
+    Euclidean CDF with TR_DEV_ZERO_DIST; a core whose unfolding has an
+    all-zero column (a Gram with a zero pivot) gives the uniform leverage
+    CDF with TR_DEV_NOT_SPD; a core with I_k <= R_k R_{k+1} gives the
+    uniform leverage CDF and no status."""
+    I, R = [60, 7, 30], [3, 4, 2]
+    _, _, cores, X, dcores, dX = problem(23, 3, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+
+    def uniform(n):
+        w = np.full(n, int(sampling.quantize(np.array([1.0 / n]))[0]), dtype=np.uint64)
+        return np.cumsum(w)
+
+    say("euclid zero core")
+    cdf, st = api.tr_dist(desc, 0, L.TR_LAW_EUCLID, torch.zeros_like(dcores[0]))
+    assert int(st) == L.TR_DEV_ZERO_DIST
+    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), uniform(I[0]))
+
+    say("leverage zero column")
+    G = unfold(cores[0]).copy()          # I_0 x R_0 R_1 = 60 x 12
+    G[:, 5] = 0.0
+    cdf, st = api.tr_dist(desc, 0, L.TR_LAW_LEVERAGE, to_dev(G, dtype))
+    assert int(st) == L.TR_DEV_NOT_SPD
+    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), uniform(I[0]))
+
+    say("leverage I_k <= RR")
+    cdf, st = api.tr_dist(desc, 1, L.TR_LAW_LEVERAGE, dcores[1])   # 7 x 8
+    assert int(st) == 0
+    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), uniform(I[1]))
