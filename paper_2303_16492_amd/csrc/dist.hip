@@ -1,8 +1,10 @@
 // a2: the sampling laws of Section 3.2 turned into integer-weight CDFs.
 //
 //   Euclidean (Lemma euc_est): p(i) = ||G_k(:,i,:)||_F^2 / ||G_k||_F^2.
-//   Leverage (Lemma lev_est):  p(i) = l_i(G_{k(2)}) / rank, l_i = ||L^{-1} g_i||^2
-//                              with L L^T the FP64 Gram G_{k(2)}^T G_{k(2)}.
+//   Leverage (Lemma lev_est):  p(i) = l_i(G_{k(2)}) / rank, l_i = g_i^T (G^T G)^{-1} g_i
+//                              with the FP64 Gram G^T G of G = G_{k(2)} (the sweep
+//                              inverse for R_k R_{k+1} <= 128, ||L^{-1} g_i||^2 with
+//                              its Cholesky factor L above).
 //   Optimal (eq:optimal_prob): q(j) ~ ||X_[n](:,j) - G_{n(2)} s_j|| * ||s_j||
 //                              over the J_n columns, FP64.
 // Weights w = floor(p 2^40) + 1 and their inclusive prefix sums are exact
