@@ -111,7 +111,9 @@ def test_each_problem_equals_itself_alone(splits):
 def test_tile_variants_agree():
     inst = small_instances(3, 4)
     outs = []
-    for (ch, wv), sp in [(v, 1) for v in TRBatch.VARIANTS] + [(v, 4) for v in TRBatch.VARIANTS]:
+    # every tile variant with one and four shares, plus six shares (the
+    # apply then fetches the shares in two rounds, the second partly clamped)
+    for (ch, wv), sp in [(v, 1) for v in TRBatch.VARIANTS] + [(v, 4) for v in TRBatch.VARIANTS] + [((64, 8), 6)]:
         probs, _ = build(inst, m=96)
         B = TRBatch(probs)
         B.run(3, ch, wv, sp)
