@@ -61,8 +61,8 @@ __host__ __device__ inline int pick_mode(uint64_t seed, uint64_t t, int N) {
 }
 
 // Integer-CDF pick: first i with cdf[i] > u, u = floor(r * W / 2^64).
-__device__ inline int cdf_pick(const uint64_t* __restrict__ cdf, int len, uint64_t r,
-                               double* p) {
+template <typename P>
+__device__ inline int cdf_pick(P cdf, int len, uint64_t r, double* p) {
     const uint64_t W = cdf[len - 1];
     const uint64_t u = mulhi64(r, W);
     int lo = 0, hi = len - 1;           // answer in [lo, hi]
@@ -107,6 +107,37 @@ struct CdfPtrs {
 };
 
 __host__ __device__ inline int ring_next(int k, int N) { return k + 1 == N ? 0 : k + 1; }
+
+// Entry k of a per-mode kernel-argument table where k differs between the
+// lanes of a wavefront.  Indexing the table directly would be a per-lane
+// vector load from the argument segment (a memory round trip, and its wait
+// also drains every store issued before it); the unrolled selects take all
+// entries from scalar registers.
+// (The empty asm makes each entry an opaque scalar value; without it the
+// compiler folds the selects back into one indexed load.)
+template <typename T>
+__device__ inline T lane_pick(const T (&tab)[kMaxOrder], int k) {
+    T r = tab[0];
+    asm("" : "+s"(r));
+#pragma unroll
+    for (int j = 1; j < kMaxOrder; ++j) {
+        T e = tab[j];
+        asm("" : "+s"(e));
+        r = k == j ? e : r;
+    }
+    return r;
+}
+
+// Pointer in global memory (an opaque pointer has lost the address space the
+// compiler infers for kernel arguments; a generic one would make every load
+// through it a flat load).
+template <typename T>
+using gptr = const T __attribute__((address_space(1)))*;
+
+template <typename T, typename P>
+__device__ inline gptr<T> lane_pick_global(const P (&tab)[kMaxOrder], int k) {
+    return (gptr<T>)(const T*)lane_pick(tab, k);
+}
 
 __host__ __device__ inline int64_t J_of(const tr_desc& d, int n) {
     int64_t J = 1;

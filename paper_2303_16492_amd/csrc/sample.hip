@@ -80,13 +80,15 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
                 const int fl = w / (N - 1), q = w - fl * (N - 1);
                 const int k = (n + 1 + q) % N;
                 const uint64_t r = draw_word(ms.seed, t, (uint64_t)(f0 + fl), (uint64_t)k, (uint64_t)stream_tag);
+                const gptr<uint64_t> ck = lane_pick_global<uint64_t>(cdf.p, k);   // k differs across lanes
+                const int Ik = lane_pick(d.I, k);
                 double pk;
                 int i;
-                if (cdf.p[k]) {
-                    i = cdf_pick(cdf.p[k], d.I[k], r, &pk);
+                if (ck) {
+                    i = cdf_pick(ck, Ik, r, &pk);
                 } else {
-                    i = (int)mulhi64(r, (uint64_t)d.I[k]);
-                    pk = 1.0 / (double)d.I[k];
+                    i = (int)mulhi64(r, (uint64_t)Ik);
+                    pk = 1.0 / (double)Ik;
                 }
                 sidx[fl * kMaxOrder + k] = i;
                 sp[fl * kMaxOrder + q] = pk;
@@ -97,18 +99,6 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
             }
         }
         __syncthreads();
-        for (int fl = tid; fl < nb; fl += blockDim.x) {
-            const int64_t f = f0 + fl;
-            double p;
-            if (cdf_J) {
-                p = sp[fl * kMaxOrder];
-            } else {
-                p = 1.0;
-                for (int q = 0; q < N - 1; ++q) p = p * sp[fl * kMaxOrder + q];
-            }
-            pF[f] = p;
-            for (int k = 0; k < N; ++k) idx[f * N + k] = sidx[fl * kMaxOrder + k];
-        }
     } else {
         for (int fl = tid; fl < nb; fl += blockDim.x) {
             const int64_t f = f0 + fl;
@@ -122,7 +112,26 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
         }
         __syncthreads();
     }
-    if (!do_subchain) return;
+    // The draws and their probabilities go out after the slice loads are in
+    // flight: a store issued before them would hold up their first wait.
+    auto write_draws = [&]() {
+        for (int fl = tid; fl < nb; fl += blockDim.x) {
+            const int64_t f = f0 + fl;
+            double p;
+            if (cdf_J) {
+                p = sp[fl * kMaxOrder];
+            } else {
+                p = 1.0;
+                for (int q = 0; q < N - 1; ++q) p = p * sp[fl * kMaxOrder + q];
+            }
+            pF[f] = p;
+            for (int k = 0; k < N; ++k) idx[f * N + k] = sidx[fl * kMaxOrder + k];
+        }
+    };
+    if (!do_subchain) {
+        if (do_sample) write_draws();
+        return;
+    }
 
     // Phase 2: slices of every sample, all loads in flight together.  Thread
     // w of a pass owns value w of every sample's slices (its slice q, mode k
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
         while (q + 1 < N - 1 && wc >= soff[q + 1]) ++q;
         const int k = (n + 1 + q) % N;
         const int len = soff[q + 1] - soff[q], off = wc - soff[q];
-        const TC* src = static_cast<const TC*>(cores.p[k]);
+        const gptr<TC> src = lane_pick_global<TC>(cores.p, k);   // k differs across lanes
         constexpr int kSB = 16;   // samples per block at most
         int row[kSB];
         bool ok[kSB];
@@ -151,6 +160,7 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
         TC v[kSB];
 #pragma unroll
         for (int fl = 0; fl < kSB; ++fl) v[fl] = src[(int64_t)row[fl] * len + off];
+        if (w0 == 0 && do_sample) write_draws();   // while the loads above are in flight
 #pragma unroll
         for (int fl = 0; fl < kSB; ++fl)
             if (fl < nb && w < per) sl[(size_t)fl * per + w] = ok[fl] ? v[fl] : TC(0);
