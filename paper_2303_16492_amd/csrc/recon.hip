@@ -185,6 +185,57 @@ __global__ __launch_bounds__(256) void k_recon_pack(tr_desc d, const float* __re
     Gpk[e] = (i < I0 && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
 }
 
+// Error sums on FP16 matrix cores with a hi/lo split (three products per K
+// step: lo*hi, hi*lo, hi*hi, FP32 accumulation).  Each operand tile is
+// scaled by a power of two that puts its largest magnitude in [2^13, 2^14),
+// so hi + lo carries 22 significant bits of every entry that is not far
+// below the tile's largest; the result is scaled back exactly.
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline int h3_exponent(float mx) {   // mx * 2^e in [2^13, 2^14); 0 if none
+    if (!(mx > 0.f) || !(mx <= 3.4e38f)) return 0;
+    int x;
+    frexpf(mx, &x);
+    return 14 - x;
+}
+
+// G_{1(2)} split for the B operand of v_mfma_f32_32x32x16_f16, one block per
+// row tile it of 32 rows: lane l of K step q holds G(32 it + l % 32,
+// 16 q + 8 (l / 32) + i), i < 8, at Bh/Bl[((it K16 + q) 64 + l) 8 + i] (hi and
+// lo halves of the scaled value, zero outside); escale[it] is the tile's
+// scale exponent.
+__global__ __launch_bounds__(256) void k_recon_pack_h3(tr_desc d, const float* __restrict__ G0, int K16,
+                                                       _Float16* __restrict__ Bh, _Float16* __restrict__ Bl,
+                                                       int* __restrict__ escale) {
+    const int I0 = d.I[0], RR = d.R[0] * d.R[1 % d.N];
+    const int it = blockIdx.x, tid = threadIdx.x;
+    const int per = K16 * 512;   // packed values of the tile
+    auto value = [&](int p) {
+        const int q = p >> 9, l = (p >> 3) & 63, i = p & 7;
+        const int row = 32 * it + (l & 31), k = 16 * q + 8 * (l >> 5) + i;
+        const int rc = row < I0 ? row : I0 - 1, kc = k < RR ? k : RR - 1;
+        const float v = G0[(int64_t)rc * RR + kc];
+        return (row < I0 && k < RR) ? v : 0.f;
+    };
+    float mx = 0.f;
+    for (int p = tid; p < per; p += blockDim.x) mx = fmaxf(mx, fabsf(value(p)));
+    __shared__ float red[256];
+    red[tid] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] = fmaxf(red[tid], red[tid + o]);
+        __syncthreads();
+    }
+    const int e = h3_exponent(red[0]);
+    for (int p = tid; p < per; p += blockDim.x) {
+        const float v = ldexpf(value(p), e);
+        const _Float16 h = (_Float16)v;
+        Bh[(int64_t)it * per + p] = h;
+        Bl[(int64_t)it * per + p] = (_Float16)(v - (float)h);
+    }
+    if (tid == 0) escale[it] = e;
+}
+
 // Order 3 builds a block's rows from LDS when its columns touch at most this
 // many slices of the last core (true whenever I_2 >= 32).
 constexpr int kRmMaxOuter = 8;
@@ -197,10 +248,16 @@ constexpr int kRmMaxOuter = 8;
 // (row tile, column tile) pairs are taken in row-tile-major order, and each
 // wavefront takes a contiguous quarter of them (exactly ceil(I_1/32) pairs
 // each), so it loads a B fragment only when its row tile changes.
-template <typename TX, int KT, int MODE>
+// H3 (error sums only): the split FP16 products above, with KT = 8 K16, the
+// B operand from k_recon_pack_h3 (Bh, Bl, escale) and the block's subchain
+// rows split into hi/lo halves in LDS once they are built.
+template <typename TX, int KT, int MODE, bool H3 = false>
 __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const float* __restrict__ Gpk,
                                                     const TX* __restrict__ Xt, TX* __restrict__ Xo,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, const _Float16* __restrict__ Bh = nullptr,
+                                                    const _Float16* __restrict__ Bl = nullptr,
+                                                    const int* __restrict__ escale = nullptr) {
+    static_assert(!H3 || (MODE == 0 && KT % 8 == 0), "split products: error sums, K in steps of 16");
     constexpr int SP = 2 * KT + 1;          // LDS row pitch of the subchain rows
     const int N = d.N;
     const int I0 = d.I[0];
@@ -359,6 +416,93 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
     const int64_t xs0 = d.x_stride[0];
     const int nti = (I0 + 31) / 32;
     double err = 0.0, xx = 0.0;
+    if constexpr (H3) {
+        // Split the block's rows: every thread reads its share of sS into
+        // registers (and its largest magnitude), then, after the block's
+        // largest is known and every read is done, writes the hi/lo halves
+        // over the same LDS (row pitch HP halves; the FP32 rows, the staged
+        // slices and column indices behind them are no longer needed).
+        constexpr int K16 = KT / 8, KW = 16 * K16, HP = KW + 8;
+        constexpr int PT = kRmCols * KW / 256;   // values per thread
+        float v[PT];
+        float mx = 0.f;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int e = u * 256 + tid, row = e / KW, k = e - row * KW;
+            v[u] = sS[row * SP + k];
+            mx = fmaxf(mx, fabsf(v[u]));
+        }
+        __shared__ float redm[4];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (l == 0) redm[w] = mx;
+        __syncthreads();
+        const int eA = h3_exponent(fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3])));
+        _Float16* Ah = reinterpret_cast<_Float16*>(sS);
+        _Float16* Al = Ah + kRmCols * HP;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int e = u * 256 + tid, row = e / KW, k = e - row * KW;
+            const float sv = ldexpf(v[u], eA);
+            const _Float16 h = (_Float16)sv;
+            Ah[row * HP + k] = h;
+            Al[row * HP + k] = (_Float16)(sv - (float)h);
+        }
+        __syncthreads();
+        h16x8 bh[K16], bl[K16];
+        int it_loaded = -1;
+        float bscale = 0.f;
+        for (int pr = w * nti; pr < (w + 1) * nti; ++pr) {
+            const int it = pr >> 2, ct = pr & 3;
+            const int i = 32 * it + lc;
+            const bool iok = i < I0;
+            if (it != it_loaded) {   // B fragment of row tile it, kept across its column tiles
+                it_loaded = it;
+                const h16x8* sh = reinterpret_cast<const h16x8*>(Bh) + (int64_t)it * K16 * 64 + l;
+                const h16x8* sl = reinterpret_cast<const h16x8*>(Bl) + (int64_t)it * K16 * 64 + l;
+#pragma unroll
+                for (int q = 0; q < K16; ++q) {
+                    bh[q] = sh[q * 64];
+                    bl[q] = sl[q * 64];
+                }
+                bscale = ldexpf(1.f, -(eA + escale[it]));
+            }
+            const int64_t* offw = sOff + 32 * ct + 4 * lh;
+            float x[16];
+            {   // issued before the matrix work, consumed after it (clamped, masked after)
+                const int64_t ic = iok ? i : I0 - 1;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t o = offw[8 * (r >> 2) + (r & 3)];
+                    const float xv = Cvt<TX>::to_f32(Xt[(o >= 0 ? o : 0) + ic * xs0]);
+                    x[r] = (iok && o >= 0) ? xv : 0.f;
+                }
+            }
+            const h16x8* ah = reinterpret_cast<const h16x8*>(Ah + (32 * ct + lc) * HP + 8 * lh);
+            const h16x8* al = reinterpret_cast<const h16x8*>(Al + (32 * ct + lc) * HP + 8 * lh);
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+            for (int q = 0; q < K16; ++q) {
+                const h16x8 a_h = ah[2 * q], a_l = al[2 * q];
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_l, bh[q], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, bl[q], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, bh[q], acc, 0, 0, 0);
+            }
+            if (iok) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t o = offw[8 * (r >> 2) + (r & 3)];
+                    if (o < 0) continue;
+                    const double xd = (double)x[r];
+                    const double df = (double)(acc[r] * bscale) - xd;
+                    err += df * df;
+                    xx += xd * xd;
+                }
+            }
+        }
+    } else {
     float b[KT];
     int it_loaded = -1;
     for (int pr = w * nti; pr < (w + 1) * nti; ++pr) {
@@ -413,6 +557,7 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
             }
         }
     }
+    }
     if (MODE == 0) {
         __shared__ double red[4];
         const double e = block_sum(err, red);
@@ -435,9 +580,12 @@ static int64_t recon_mfma_blocks(const tr_desc& d) {
     return (J + kRmCols - 1) / kRmCols;
 }
 
-static size_t recon_pack_bytes(const tr_desc& d) {
-    const int KT = recon_kt(d.R[0] * d.R[1 % d.N]);
-    return (size_t)((d.I[0] + 31) / 32) * KT * 64 * 4;
+static int recon_k16(const tr_desc& d) { return (d.R[0] * d.R[1 % d.N] + 15) / 16; }
+
+// split B operand: hi and lo halves, then the per-tile scale exponents
+static size_t recon_pack_h3_bytes(const tr_desc& d) {
+    const size_t nti = (size_t)(d.I[0] + 31) / 32;
+    return 2 * align_up(nti * recon_k16(d) * 512 * 2) + align_up(nti * 4);
 }
 
 template <int MODE, typename TX>
@@ -465,6 +613,35 @@ static hipError_t launch_recon_mfma_t(const tr_desc& d, Ptrs cores, const float*
     return hipGetLastError();
 }
 
+template <typename TX>
+static hipError_t launch_recon_h3(const tr_desc& d, Ptrs cores, const _Float16* Bh, const _Float16* Bl,
+                                  const int* escale, const TX* Xt, double* part, hipStream_t st) {
+    const int K16 = recon_k16(d);
+    const dim3 grid((unsigned)recon_mfma_blocks(d)), block(256);
+    const size_t shm = recon_mfma_shm(8 * K16);
+#define TRK_RH(K)                                                                                         \
+    case K:                                                                                               \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_recon_mfma<TX, 8 * K, 0, true>), shm))           \
+            return hipErrorInvalidConfiguration;                                                          \
+        hipLaunchKernelGGL((k_recon_mfma<TX, 8 * K, 0, true>), grid, block, shm, st, d, cores, nullptr, Xt,  \
+                           (TX*)nullptr, part, Bh, Bl, escale);                                           \
+        break;
+    switch (K16) {
+        TRK_RH(1)
+        TRK_RH(2)
+        TRK_RH(3)
+        TRK_RH(4)
+        TRK_RH(5)
+        TRK_RH(6)
+        TRK_RH(7)
+        TRK_RH(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef TRK_RH
+    return hipGetLastError();
+}
+
 static size_t recon_shm(const tr_desc& d, size_t es) {
     const int RR = d.R[0] * d.R[1 % d.N];
     const int RRp = RR + ((RR & 1) ? 0 : 1);
@@ -479,7 +656,7 @@ static int64_t recon_blocks(const tr_desc& d) {
 
 size_t relerr_ws_bytes(const tr_desc& d) {
     size_t b = align_up(16) + align_up((size_t)recon_blocks(d) * 16);
-    if (recon_mfma_ok(d)) b += align_up(recon_pack_bytes(d));
+    if (recon_mfma_ok(d)) b += align_up(recon_pack_h3_bytes(d));
     return b;
 }
 
@@ -489,16 +666,19 @@ hipError_t launch_relerr(const tr_desc& d, Ptrs cores, const void* Xt, double xn
     double* sums = reinterpret_cast<double*>(w);
     double* part = reinterpret_cast<double*>(w + align_up(16));
     if (recon_mfma_ok(d)) {
-        float* Gpk = reinterpret_cast<float*>(w + align_up(16) + align_up((size_t)recon_blocks(d) * 16));
-        const int KT = recon_kt(d.R[0] * d.R[1 % d.N]);
-        const int64_t np = (int64_t)((d.I[0] + 31) / 32) * KT * 64;
-        hipLaunchKernelGGL(k_recon_pack, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d,
-                           static_cast<const float*>(cores.p[0]), KT, Gpk);
+        char* pk = w + align_up(16) + align_up((size_t)recon_blocks(d) * 16);
+        const int nti = (d.I[0] + 31) / 32, K16 = recon_k16(d);
+        const size_t half_bytes = align_up((size_t)nti * K16 * 512 * 2);
+        _Float16* Bh = reinterpret_cast<_Float16*>(pk);
+        _Float16* Bl = reinterpret_cast<_Float16*>(pk + half_bytes);
+        int* escale = reinterpret_cast<int*>(pk + 2 * half_bytes);
+        hipLaunchKernelGGL(k_recon_pack_h3, dim3((unsigned)nti), dim3(256), 0, st, d,
+                           static_cast<const float*>(cores.p[0]), K16, Bh, Bl, escale);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = d.x_dtype == TR_F32
-                ? launch_recon_mfma_t<0>(d, cores, Gpk, static_cast<const float*>(Xt), (float*)nullptr, part, st)
-                : launch_recon_mfma_t<0>(d, cores, Gpk, static_cast<const __half*>(Xt), (__half*)nullptr, part, st);
+                ? launch_recon_h3(d, cores, Bh, Bl, escale, static_cast<const float*>(Xt), part, st)
+                : launch_recon_h3(d, cores, Bh, Bl, escale, static_cast<const __half*>(Xt), part, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_recon_finish, dim3(1), dim3(256), 0, st, part, recon_mfma_blocks(d), xnorm2, rse,
                            sums);

@@ -359,6 +359,29 @@ def test_relerr_matrix_core_shapes(N, I, R, xdt):
     assert rel(Xh.double().cpu().numpy(), flat_paper(ref)) < (TOL[dtype] if xdt == torch.float32 else 1e-3)
 
 
+def test_relerr_small_residual_matrix_cores():
+    """The error sums on the matrix cores (FP16 hi/lo products scaled per
+    tile) stay accurate when the residual is small next to the tensor:
+    X = TR(G) plus noise of relative size 1e-5 (about where a planted run
+    stops), with the rows of G_1 scaled by 1e2, 1 and 1e-2 in its three row
+    tiles; the RSE agrees with the FP64 oracle to 1%."""
+    I, R = [96, 40, 33], [10, 10, 10]
+    cores = ti.gaussian_cores(21, 3, I, R)
+    rows = np.repeat([1e2, 1.0, 1e-2], 32)
+    cores[0] = cores[0] * rows[None, :, None]
+    cores = [rounded(c, torch.float32) for c in cores]
+    Xt = tr.full_tensor(cores)
+    noise = ti.standard_normal(22, Xt.shape)
+    X = rounded(Xt + noise * (1e-5 * np.linalg.norm(Xt) / np.linalg.norm(noise)), torch.float32)
+    desc = api.make_desc(I, R, torch.float32)
+    say("relerr small residual")
+    rse = float(api.tr_relerr(desc, [to_dev(unfold(c), torch.float32) for c in cores],
+                              to_dev(flat_paper(X), torch.float32)))
+    want = tr.rse(cores, X)
+    assert 5e-6 < want < 2e-5
+    assert abs(rse - want) <= 1e-2 * want, (rse, want)
+
+
 def test_relerr_zero_at_truth_fp64():
     cores = [rounded(c, torch.float64) for c in ti.gaussian_cores(3, 3, [12, 10, 11], [3, 2, 4])]
     X = tr.full_tensor(cores)
