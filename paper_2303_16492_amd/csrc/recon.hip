@@ -4,14 +4,15 @@
 // FP32 cores with R_1 R_2 <= 128 take the matrix-core kernel k_recon_mfma:
 // a block owns 128 columns j of X_[1] (paper order: column j is the
 // multi-index of (i_2..i_N), first fastest), 32 per wavefront.  The block
-// builds their subchain rows s_j in LDS (chain products of lateral slices),
-// each wavefront keeps its 32 rows as the A operand of
-// v_mfma_f32_32x32x2_f32 in registers for the whole kernel, and sweeps the
-// rows i_1 of G_{1(2)} in tiles of 32: the B operand comes pre-packed in
-// lane order (one coalesced 256-byte load per instruction), the 32 x 32
-// result tile is compared with X_true as it leaves the accumulators (each
-// half-wavefront reads 32 consecutive i_1 of one column, 128 bytes), and
-// X_hat is never stored.  X_true is read exactly once.
+// builds their subchain rows s_j in LDS (chain products of lateral slices)
+// and each wavefront sweeps the rows i_1 of G_{1(2)} in tiles of 32 against
+// its 32 rows on the matrix cores.  For the RSE the products are FP16 with a
+// hi/lo split (below), the B operand comes pre-packed in lane order (one
+// coalesced load per instruction), the 32 x 32 result tile is compared with
+// X_true as it leaves the accumulators (each half-wavefront reads 32
+// consecutive i_1 of one column, 128 bytes), and X_hat is never stored:
+// X_true is read exactly once.  The written reconstruction uses FP32
+// products (v_mfma_f32_32x32x2_f32) with B read from G_{1(2)} directly.
 //
 // Other cases (FP64, larger ranks) take k_recon: every thread takes rows
 // i_1 = tid, tid + 256, ... and forms TJ dot products with s_j broadcast
@@ -170,21 +171,6 @@ static bool recon_mfma_ok(const tr_desc& d) {
            recon_kt(d.R[0] * d.R[1 % d.N]) > 0;
 }
 
-// G_{1(2)} in the lane order of the B operand of v_mfma_f32_32x32x2_f32:
-// Gpk[(it KT + q) 64 + l] = G(32 it + l % 32, 2 q + l / 32), zero outside.
-__global__ __launch_bounds__(256) void k_recon_pack(tr_desc d, const float* __restrict__ G0, int KT,
-                                                    float* __restrict__ Gpk) {
-    const int I0 = d.I[0], RR = d.R[0] * d.R[1 % d.N];
-    const int nti = (I0 + 31) / 32;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)nti * KT * 64) return;
-    const int l = (int)(e & 63);
-    const int64_t u = e >> 6;
-    const int q = (int)(u % KT), it = (int)(u / KT);
-    const int i = 32 * it + (l & 31), k = 2 * q + (l >> 5);
-    Gpk[e] = (i < I0 && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
-}
-
 // Error sums on FP16 matrix cores with a hi/lo split (three products per K
 // step: lo*hi, hi*lo, hi*hi, FP32 accumulation).  Each operand tile is
 // scaled by a power of two that puts its largest magnitude in [2^13, 2^14),
@@ -209,29 +195,36 @@ __global__ __launch_bounds__(256) void k_recon_pack_h3(tr_desc d, const float* _
                                                        int* __restrict__ escale) {
     const int I0 = d.I[0], RR = d.R[0] * d.R[1 % d.N];
     const int it = blockIdx.x, tid = threadIdx.x;
-    const int per = K16 * 512;   // packed values of the tile
-    auto value = [&](int p) {
+    const int per = K16 * 512;          // packed values of the tile
+    constexpr int PV = 8 * 512 / 256;   // per thread at K16 = 8
+    // every load of the thread in flight together (indices clamped, masked after)
+    float v[PV];
+    float mx = 0.f;
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+        const int p = u * 256 + tid;
         const int q = p >> 9, l = (p >> 3) & 63, i = p & 7;
         const int row = 32 * it + (l & 31), k = 16 * q + 8 * (l >> 5) + i;
         const int rc = row < I0 ? row : I0 - 1, kc = k < RR ? k : RR - 1;
-        const float v = G0[(int64_t)rc * RR + kc];
-        return (row < I0 && k < RR) ? v : 0.f;
-    };
-    float mx = 0.f;
-    for (int p = tid; p < per; p += blockDim.x) mx = fmaxf(mx, fabsf(value(p)));
-    __shared__ float red[256];
-    red[tid] = mx;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) red[tid] = fmaxf(red[tid], red[tid + o]);
-        __syncthreads();
+        const float g = G0[(int64_t)rc * RR + kc];
+        v[u] = (p < per && row < I0 && k < RR) ? g : 0.f;
+        mx = fmaxf(mx, fabsf(v[u]));
     }
-    const int e = h3_exponent(red[0]);
-    for (int p = tid; p < per; p += blockDim.x) {
-        const float v = ldexpf(value(p), e);
-        const _Float16 h = (_Float16)v;
-        Bh[(int64_t)it * per + p] = h;
-        Bl[(int64_t)it * per + p] = (_Float16)(v - (float)h);
+    __shared__ float red[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    const int e = h3_exponent(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+        const int p = u * 256 + tid;
+        const float sv = ldexpf(v[u], e);
+        const _Float16 h = (_Float16)sv;
+        if (p < per) {
+            Bh[(int64_t)it * per + p] = h;
+            Bl[(int64_t)it * per + p] = (_Float16)(sv - (float)h);
+        }
     }
     if (tid == 0) escale[it] = e;
 }
@@ -240,24 +233,22 @@ __global__ __launch_bounds__(256) void k_recon_pack_h3(tr_desc d, const float* _
 // many slices of the last core (true whenever I_2 >= 32).
 constexpr int kRmMaxOuter = 8;
 
-// MODE 0: per-block sums of (X_hat - X_true)^2 and X_true^2 into part;
-// MODE 1: X_hat written to Xo.  Gpk null: B operand read from G_{1(2)}
-// directly (uncoalesced; used by the one-off reconstruction).
+// MODE 0: per-block sums of (X_hat - X_true)^2 and X_true^2 into part, on
+// the split FP16 products with KT = 8 K16, the B operand from
+// k_recon_pack_h3 (Bh, Bl, escale) and the block's subchain rows split into
+// hi/lo halves in LDS once they are built.  MODE 1: X_hat written to Xo
+// (FP32 products, B operand read from G_{1(2)} directly).
 //
 // Work split: the block's 128 columns are four column tiles of 32; the
 // (row tile, column tile) pairs are taken in row-tile-major order, and each
 // wavefront takes a contiguous quarter of them (exactly ceil(I_1/32) pairs
 // each), so it loads a B fragment only when its row tile changes.
-// H3 (error sums only): the split FP16 products above, with KT = 8 K16, the
-// B operand from k_recon_pack_h3 (Bh, Bl, escale) and the block's subchain
-// rows split into hi/lo halves in LDS once they are built.
-template <typename TX, int KT, int MODE, bool H3 = false>
-__global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const float* __restrict__ Gpk,
-                                                    const TX* __restrict__ Xt, TX* __restrict__ Xo,
-                                                    double* __restrict__ part, const _Float16* __restrict__ Bh = nullptr,
-                                                    const _Float16* __restrict__ Bl = nullptr,
-                                                    const int* __restrict__ escale = nullptr) {
-    static_assert(!H3 || (MODE == 0 && KT % 8 == 0), "split products: error sums, K in steps of 16");
+template <typename TX, int KT, int MODE>
+__global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const TX* __restrict__ Xt,
+                                                    TX* __restrict__ Xo, double* __restrict__ part,
+                                                    const _Float16* __restrict__ Bh, const _Float16* __restrict__ Bl,
+                                                    const int* __restrict__ escale) {
+    static_assert(MODE == 1 || KT % 8 == 0, "split products: K in steps of 16");
     constexpr int SP = 2 * KT + 1;          // LDS row pitch of the subchain rows
     const int N = d.N;
     const int I0 = d.I[0];
@@ -416,7 +407,7 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
     const int64_t xs0 = d.x_stride[0];
     const int nti = (I0 + 31) / 32;
     double err = 0.0, xx = 0.0;
-    if constexpr (H3) {
+    if constexpr (MODE == 0) {
         // Split the block's rows: every thread reads its share of sS into
         // registers (and its largest magnitude), then, after the block's
         // largest is known and every read is done, writes the hi/lo halves
@@ -452,7 +443,21 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
         h16x8 bh[K16], bl[K16];
         int it_loaded = -1;
         float bscale = 0.f;
-        for (int pr = w * nti; pr < (w + 1) * nti; ++pr) {
+        // X_true entries of pair pr, read at clamped indices and kept as
+        // loaded (no select on them, which would wait for the load at
+        // once); entries outside the tensor are skipped where they are used
+        auto load_x = [&](int pr, TX (&x)[16]) {
+            const int it = pr >> 2, ct = pr & 3;
+            const int i = 32 * it + lc;
+            const int64_t ic = i < I0 ? i : I0 - 1;
+            const int64_t* offw = sOff + 32 * ct + 4 * lh;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t o = offw[8 * (r >> 2) + (r & 3)];
+                x[r] = Xt[(o >= 0 ? o : 0) + ic * xs0];
+            }
+        };
+        auto pair = [&](int pr, const TX (&x)[16]) {
             const int it = pr >> 2, ct = pr & 3;
             const int i = 32 * it + lc;
             const bool iok = i < I0;
@@ -468,16 +473,6 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
                 bscale = ldexpf(1.f, -(eA + escale[it]));
             }
             const int64_t* offw = sOff + 32 * ct + 4 * lh;
-            float x[16];
-            {   // issued before the matrix work, consumed after it (clamped, masked after)
-                const int64_t ic = iok ? i : I0 - 1;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t o = offw[8 * (r >> 2) + (r & 3)];
-                    const float xv = Cvt<TX>::to_f32(Xt[(o >= 0 ? o : 0) + ic * xs0]);
-                    x[r] = (iok && o >= 0) ? xv : 0.f;
-                }
-            }
             const h16x8* ah = reinterpret_cast<const h16x8*>(Ah + (32 * ct + lc) * HP + 8 * lh);
             const h16x8* al = reinterpret_cast<const h16x8*>(Al + (32 * ct + lc) * HP + 8 * lh);
             f32x16 acc;
@@ -495,68 +490,57 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
                 for (int r = 0; r < 16; ++r) {
                     const int64_t o = offw[8 * (r >> 2) + (r & 3)];
                     if (o < 0) continue;
-                    const double xd = (double)x[r];
+                    const double xd = (double)Cvt<TX>::to_f32(x[r]);
                     const double df = (double)(acc[r] * bscale) - xd;
                     err += df * df;
                     xx += xd * xd;
                 }
             }
+        };
+        // Two register buffers in turn: the entries of the next pair are
+        // requested before this pair's products, so a pair's X_true reads
+        // have a whole pair of matrix work to arrive in.
+        TX xa[16], xb[16];
+        const int pb = w * nti, pe = (w + 1) * nti;
+        load_x(pb, xa);
+        for (int pr = pb; pr < pe; pr += 2) {
+            if (pr + 1 < pe) load_x(pr + 1, xb);
+            pair(pr, xa);
+            if (pr + 1 < pe) {
+                if (pr + 2 < pe) load_x(pr + 2, xa);
+                pair(pr + 1, xb);
+            }
         }
     } else {
-    float b[KT];
-    int it_loaded = -1;
-    for (int pr = w * nti; pr < (w + 1) * nti; ++pr) {
-        const int it = pr >> 2, ct = pr & 3;
-        const int i = 32 * it + lc;
-        const bool iok = i < I0;
-        if (it != it_loaded) {   // B fragment of row tile it, kept across its column tiles
-            it_loaded = it;
-            if (Gpk) {
-                const float* src = Gpk + (int64_t)it * KT * 64 + l;
-#pragma unroll
-                for (int q = 0; q < KT; ++q) b[q] = src[q * 64];
-            } else {
+        float b[KT];
+        int it_loaded = -1;
+        for (int pr = w * nti; pr < (w + 1) * nti; ++pr) {
+            const int it = pr >> 2, ct = pr & 3;
+            const int i = 32 * it + lc;
+            const bool iok = i < I0;
+            if (it != it_loaded) {   // B fragment of row tile it, kept across its column tiles
+                it_loaded = it;
 #pragma unroll
                 for (int q = 0; q < KT; ++q) {
                     const int k = 2 * q + lh;
                     b[q] = (iok && k < RR) ? G0[(int64_t)i * RR + k] : 0.f;
                 }
             }
-        }
-        const int64_t* offw = sOff + 32 * ct + 4 * lh;
-        float x[16];
-        if (MODE == 0) {   // issued before the matrix work, consumed after it;
-                           // unconditional (clamped in bounds), masked after
-            const int64_t ic = iok ? i : I0 - 1;
+            const int64_t* offw = sOff + 32 * ct + 4 * lh;
+            const float* arow = sS + (32 * ct + lc) * SP + lh;
+            f32x16 acc;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t o = offw[8 * (r >> 2) + (r & 3)];
-                const float xv = Cvt<TX>::to_f32(Xt[(o >= 0 ? o : 0) + ic * xs0]);
-                x[r] = (iok && o >= 0) ? xv : 0.f;
-            }
-        }
-        const float* arow = sS + (32 * ct + lc) * SP + lh;
-        f32x16 acc;
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+            for (int q = 0; q < KT; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[2 * q], b[q], acc, 0, 0, 0);
+            if (iok) {
 #pragma unroll
-        for (int q = 0; q < KT; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[2 * q], b[q], acc, 0, 0, 0);
-        if (iok) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t o = offw[8 * (r >> 2) + (r & 3)];
-                if (o < 0) continue;
-                if (MODE == 0) {
-                    const double xd = (double)x[r];
-                    const double df = (double)acc[r] - xd;
-                    err += df * df;
-                    xx += xd * xd;
-                } else {
-                    Xo[o + (int64_t)i * xs0] = from_f64<TX>((double)acc[r]);
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t o = offw[8 * (r >> 2) + (r & 3)];
+                    if (o >= 0) Xo[o + (int64_t)i * xs0] = from_f64<TX>((double)acc[r]);
                 }
             }
         }
-    }
     }
     if (MODE == 0) {
         __shared__ double red[4];
@@ -588,17 +572,17 @@ static size_t recon_pack_h3_bytes(const tr_desc& d) {
     return 2 * align_up(nti * recon_k16(d) * 512 * 2) + align_up(nti * 4);
 }
 
-template <int MODE, typename TX>
-static hipError_t launch_recon_mfma_t(const tr_desc& d, Ptrs cores, const float* Gpk, const TX* Xt, TX* Xo,
-                                      double* part, hipStream_t st) {
+template <typename TX>
+static hipError_t launch_recon_write(const tr_desc& d, Ptrs cores, TX* Xo, hipStream_t st) {
     const int KT = recon_kt(d.R[0] * d.R[1 % d.N]);
     const dim3 grid((unsigned)recon_mfma_blocks(d)), block(256);
     const size_t shm = recon_mfma_shm(KT);
 #define TRK_RM(KTV)                                                                                      \
     case KTV:                                                                                            \
-        if (!allow_lds(reinterpret_cast<const void*>(&k_recon_mfma<TX, KTV, MODE>), shm))               \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_recon_mfma<TX, KTV, 1>), shm))                  \
             return hipErrorInvalidConfiguration;                                                         \
-        hipLaunchKernelGGL((k_recon_mfma<TX, KTV, MODE>), grid, block, shm, st, d, cores, Gpk, Xt, Xo, part); \
+        hipLaunchKernelGGL((k_recon_mfma<TX, KTV, 1>), grid, block, shm, st, d, cores, (const TX*)nullptr, Xo, \
+                           nullptr, nullptr, nullptr, nullptr);                                          \
         break;
     switch (KT) {
         TRK_RM(8)
@@ -621,10 +605,10 @@ static hipError_t launch_recon_h3(const tr_desc& d, Ptrs cores, const _Float16* 
     const size_t shm = recon_mfma_shm(8 * K16);
 #define TRK_RH(K)                                                                                         \
     case K:                                                                                               \
-        if (!allow_lds(reinterpret_cast<const void*>(&k_recon_mfma<TX, 8 * K, 0, true>), shm))           \
+        if (!allow_lds(reinterpret_cast<const void*>(&k_recon_mfma<TX, 8 * K, 0>), shm))                 \
             return hipErrorInvalidConfiguration;                                                          \
-        hipLaunchKernelGGL((k_recon_mfma<TX, 8 * K, 0, true>), grid, block, shm, st, d, cores, nullptr, Xt,  \
-                           (TX*)nullptr, part, Bh, Bl, escale);                                           \
+        hipLaunchKernelGGL((k_recon_mfma<TX, 8 * K, 0>), grid, block, shm, st, d, cores, Xt, (TX*)nullptr, \
+                           part, Bh, Bl, escale);                                                         \
         break;
     switch (K16) {
         TRK_RH(1)
@@ -707,10 +691,8 @@ hipError_t launch_relerr(const tr_desc& d, Ptrs cores, const void* Xt, double xn
 
 hipError_t launch_reconstruct(const tr_desc& d, Ptrs cores, void* Xo, hipStream_t st) {
     if (recon_mfma_ok(d)) {
-        return d.x_dtype == TR_F32
-                   ? launch_recon_mfma_t<1>(d, cores, nullptr, (const float*)nullptr, static_cast<float*>(Xo), nullptr, st)
-                   : launch_recon_mfma_t<1>(d, cores, nullptr, (const __half*)nullptr, static_cast<__half*>(Xo), nullptr,
-                                            st);
+        return d.x_dtype == TR_F32 ? launch_recon_write(d, cores, static_cast<float*>(Xo), st)
+                                   : launch_recon_write(d, cores, static_cast<__half*>(Xo), st);
     }
     const int64_t nb = recon_blocks(d);
     const dim3 grid((unsigned)nb);
