@@ -232,6 +232,11 @@ size_t tr_update_workspace_size(const tr_desc* d, int32_t n, int32_t scaled);
 /* ------------------------------------------------------------------ */
 
 /* rse = ||TR(cores) - X_true||_F / ||X_true||_F, FP64 reduction.
+ * FP32 cores with R_1 R_2 <= 128 form TR(cores) on FP16 matrix cores from
+ * a hi/lo split of both operands (three products per K step, FP32
+ * accumulation, each operand tile scaled by a power of two), about 22
+ * significant bits per operand; FP64 cores and larger ranks take FP64 or
+ * FP32 dot products.
  * x_true_norm2 = ||X_true||_F^2 if known, else a negative value (then it
  * is computed in the same pass).  rse: device float64 scalar.  Also
  * writes ||TR(cores) - X_true||^2 and ||X_true||^2 into ws[0..1] (float64). */
