@@ -382,6 +382,19 @@ def test_relerr_small_residual_matrix_cores():
     assert abs(rse - want) <= 1e-2 * want, (rse, want)
 
 
+@pytest.mark.parametrize("N,I,R", [(3, [40, 30, 21], [6, 7, 5]), (3, [70, 9, 10], [8, 16, 8])])
+def test_relerr_zero_cores_matrix_cores(N, I, R):
+    """All-zero FP32 cores on the matrix-core path (tiles whose largest
+    magnitude is zero take scale 2^0): X_hat = 0, so the RSE is exactly 1."""
+    rng = np.random.default_rng(5)
+    X = rounded(rng.standard_normal(I), torch.float32)
+    desc = api.make_desc(I, R, torch.float32)
+    zero = [torch.zeros(I[k] * R[k] * R[(k + 1) % N], dtype=torch.float32, device=DEV) for k in range(N)]
+    say("relerr zero cores", I, R)
+    rse = float(api.tr_relerr(desc, zero, to_dev(flat_paper(X), torch.float32)))
+    assert rse == 1.0, rse
+
+
 def test_relerr_zero_at_truth_fp64():
     cores = [rounded(c, torch.float64) for c in ti.gaussian_cores(3, 3, [12, 10, 11], [3, 2, 4])]
     X = tr.full_tensor(cores)
