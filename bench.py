@@ -301,12 +301,19 @@ def law_rate(args, law, init3, X, I, R, m, dev, K, G=50):
     return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "dev_status": status}
 
 
+# An RSE check runs after a replay only when the step's own loss estimate,
+# as a relative error sqrt(2 loss / ||X||^2) (unbiased for the pre-update
+# cores' squared error), is within this factor of the target.
+RSE_TRIGGER = 30.0
+
+
 def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, cap=None, scaled=True, alpha=None):
     """Wall time from the initial cores until an RSE check reaches
-    ``target`` (checks every ``every`` steps count toward the time; the steps
-    between checks replay one captured graph), capped
-    at ``cap`` (default args.ttt_steps) steps; the scaled method (default)
-    or the plain one, fixed step ``alpha`` (default args.alpha)."""
+    ``target`` (checks after every ``every`` steps count toward the time
+    when the last step's loss estimate triggers them; the steps between
+    checks replay one captured graph), capped at ``cap`` (default
+    args.ttt_steps) steps; the scaled method (default) or the plain one,
+    fixed step ``alpha`` (default args.alpha)."""
     import torch
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
@@ -319,7 +326,9 @@ def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, c
     # accumulators, step counter restored) before the timer starts.
     snap = [c.clone() for c in solver.cores]
     acc_snap = [a.clone() if a is not None else None for a in solver.accum]
-    graph = solver.capture(every)
+    losses = torch.zeros(every, dtype=torch.float64, device=dev)
+    graph = solver.capture(every, losses)
+    xnorm2 = float(X.double().pow(2).sum())
     for c, s_ in zip(solver.cores, snap):
         c.copy_(s_)
     for a, s_ in zip(solver.accum, acc_snap):
@@ -331,10 +340,14 @@ def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, c
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cap = args.ttt_steps if cap is None else cap
-    steps, rse, hist = 0, float("nan"), []
+    steps, rse, hist, skipped = 0, float("nan"), [], 0
     while steps < cap:
         graph.replay()
         steps += every
+        est = (2.0 * max(float(losses[-1]), 0.0) / xnorm2) ** 0.5   # synchronises
+        if est > RSE_TRIGGER * target and steps < cap:
+            skipped += 1
+            continue
         rse = float(solver.rse())          # synchronises
         hist.append((steps, rse))
         if rse <= target:
@@ -344,6 +357,8 @@ def time_to_target(args, prec, init3, X, I, R, m, dev, target=1e-4, every=100, c
     return {"prec": prec, "target": target, "reached": rse <= target,
             "seconds": round(wall, 4) if rse <= target else None, "steps": steps,
             "rse_at_stop": rse, "wall_s_at_stop": round(wall, 4), "rse_every": every,
+            "rse_trigger": f"loss estimate within {RSE_TRIGGER:g}x of the target", "rse_checks": len(hist),
+            "rse_checks_skipped": skipped,
             "rse_trace": [[s_, float(f"{r_:.4e}")] for s_, r_ in hist[:: max(1, len(hist) // 10)]]}
 
 

@@ -92,8 +92,10 @@ class TRSolver:
     def run(self, steps: int, loss_out=None):
         api.tr_run_ex(self.problem, self.config, self.t_dev, steps, loss_out, self.status, self.ws, self.opts)
 
-    def capture(self, steps: int):
-        """HIP graph of ``steps`` iterations (replay with graph.replay())."""
+    def capture(self, steps: int, loss_out=None):
+        """HIP graph of ``steps`` iterations (replay with graph.replay());
+        with ``loss_out`` (``steps`` float64 on the device) every replay
+        writes each step's loss estimate there."""
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -102,7 +104,7 @@ class TRSolver:
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         with torch.cuda.graph(g):
-            self.run(steps)
+            self.run(steps, loss_out)
         return g
 
     def rse(self, X_true=None, x_norm2=-1.0):
