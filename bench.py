@@ -33,7 +33,7 @@ PEAK = {"f32": (157.3, "TFLOP/s"), "bf16": (2516.6, "TFLOP/s"), "f16": (2516.6, 
 HBM_PEAK_GBS = 8000.0
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--prec", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
+                    help="CPU work of the oracle baseline, split between 1 thread and all threads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the Gram/inverse branch on the main stream too")
@@ -51,7 +52,7 @@ def parse():
                     help="only run 20 plain device copies of MIB MiB (counter calibration) and exit")
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="timed steps of the 64-problem batched workload (0: skip it)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def hip_events(n):
@@ -73,6 +74,44 @@ def elapsed_ms(hip, a, b):
     out = C.c_float()
     assert hip.hipEventElapsedTime(C.byref(out), a, b) == 0
     return float(out.value)
+
+
+def graph_schedule(K: int, G: int = 50):
+    """Graph lengths and replay counts that time exactly K steps: full
+    graphs of min(G, K) steps, then one graph of the remainder."""
+    if K < 1:
+        raise ValueError("--steps must be at least 1")
+    g = min(G, K)
+    plan = [(g, K // g)]
+    if K % g:
+        plan.append((K % g, 1))
+    assert sum(n * r for n, r in plan) == K
+    return plan
+
+
+def replay_timed(solver, K: int, G: int = 50, hip=None, evs=None):
+    """Capture the graphs of ``graph_schedule(K, G)`` (each capture runs
+    one eager warm-up step first), replay each once untimed, then time
+    exactly K steps of replays between two events on the current stream.
+    Returns ms per step."""
+    import torch
+    plan = graph_schedule(K, G)
+    graphs = [(solver.capture(n), r) for n, r in plan]
+    for gr, _ in graphs:
+        gr.replay()
+    torch.cuda.synchronize()
+    t_before = solver.t
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for gr, r in graphs:
+        for _ in range(r):
+            gr.replay()
+    b.record()
+    torch.cuda.synchronize()
+    assert solver.t - t_before == K, (solver.t, t_before, K)
+    ms = a.elapsed_time(b) / K
+    del graphs
+    return ms
 
 
 def build_problem(seed, I, R, kappa, dev, kind="illcond"):
@@ -136,16 +175,40 @@ def build_batch(seed, dev):
     return TRBatch(probs, dev), insts
 
 
-def cpu_baseline(seconds, seed, I, R, kappa, m, alpha):
+def host_info():
+    """CPU model, logical CPUs usable by this process, and memory of the
+    host, read from the kernel's own files."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    mem_gb = None
+    try:
+        for ln in open("/proc/meminfo"):
+            if ln.startswith("MemTotal"):
+                mem_gb = round(int(ln.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": usable, "logical_cpus": os.cpu_count(), "mem_gb": mem_gb}
+
+
+def cpu_baseline(seconds, seed, I, R, kappa, m, alpha, threads=None):
     """The oracle as it stands, on the same workload, for a bounded number
-    of steps; returns (steps/s, steps, threads)."""
+    of steps (about ``seconds`` of CPU work after one warm-up step), with
+    the BLAS thread pools limited to ``threads`` (None: as configured);
+    returns (steps/s, steps, threads actually used)."""
     import tr_inputs as ti
     from oracle import brsgd, tr
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
     N = 3
     true3 = ti.illcond_cores(seed, N, I, R, kappa)
     X = tr.full_tensor(true3)
@@ -154,14 +217,16 @@ def cpu_baseline(seconds, seed, I, R, kappa, m, alpha):
     sig = (1.0 / R ** N) ** (1.0 / (2 * N))
     st = brsgd.State(ti.gaussian_cores(seed + 1, N, I, R, scale=sig))
     cfg = brsgd.Config(m=m, variant="scaled", alpha=alpha, seed=seed)
-    brsgd.step(st, X, cfg)               # warm-up
-    t0 = time.perf_counter()
-    k = 0
-    while time.perf_counter() - t0 < seconds:
-        brsgd.step(st, X, cfg)
-        k += 1
-    dt = time.perf_counter() - t0
-    return k / dt, k, threads
+    with threadpool_limits(limits=threads):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        brsgd.step(st, X, cfg)               # warm-up
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < seconds:
+            brsgd.step(st, X, cfg)
+            k += 1
+        dt = time.perf_counter() - t0
+    return k / dt, k, used
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scaled-illcond-n3-i400-r10.txt")
@@ -191,19 +256,20 @@ def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup, G=50, E=200):
     """The scaled method in precision ``prec`` from the initial cores:
     (1) E eager steps with HIP events recorded around the gradient and the
     inverse kernel of every step, on the streams they run on (per-launch
-    kernel durations); (2) K timed steps replayed from a HIP graph of G
-    steps (K / G replays), whose rate is the result."""
+    kernel durations); (2) exactly K timed steps replayed from HIP graphs
+    (``graph_schedule``: graphs of min(G, K) steps plus a remainder graph),
+    whose rate is the result."""
     import torch
     from paper_2303_16492_amd import _lib as L
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
     N = 3
-    assert K % G == 0, "--steps must be a multiple of the graph length (50)"
     cores = cores_to_device(init3, torch.float32, dev)
     solver = TRSolver(cores, X, [I] * N, [R] * N, m, law="U", scaled=True, prec=prec,
                       rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
                       overlap=not args.no_overlap)
-    solver.run(warmup)
+    if warmup > 0:
+        solver.run(warmup)
     torch.cuda.synchronize()
     hip, evs = hip_events(4 * E + 2)
     arr = lambda j: (C.c_void_p * E)(*[e.value for e in evs[2 + j * E:2 + (j + 1) * E]])
@@ -226,58 +292,39 @@ def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup, G=50, E=200):
     grad_us = 1e3 * float(np.mean([elapsed_ms(hip, gb[i], ge[i]) for i in range(E)]))
     inv_us = (1e3 * float(np.mean([elapsed_ms(hip, ib[i], ie[i]) for i in range(E)]))
               if solver.opts is not None else None)
-    graph = solver.capture(G)               # one eager warm-up step, then the capture
-    graph.replay()                          # warm-up replay
-    torch.cuda.synchronize()
-    t_before = solver.t
-    assert hip.hipEventRecord(evs[0], C.c_void_p(stream.cuda_stream)) == 0
-    for _ in range(K // G):
-        graph.replay()
-    assert hip.hipEventRecord(evs[1], C.c_void_p(stream.cuda_stream)) == 0
-    torch.cuda.synchronize()
-    total_ms = elapsed_ms(hip, evs[0], evs[1])
-    assert solver.t - t_before == K
-    rse = float(solver.rse())
-    status = int(solver.status.item())
-    del graph
     for e in evs:
         hip.hipEventDestroy(e)
+    ms = replay_timed(solver, K, G)
+    rse = float(solver.rse())
+    status = int(solver.status.item())
     del solver
-    return dict(ms_per_step=total_ms / K, eager_ms_per_step=eager_ms, grad_us=grad_us, inv_us=inv_us, rse_after=rse,
-                dev_status=status)
+    return dict(ms_per_step=ms, eager_ms_per_step=eager_ms, grad_us=grad_us, inv_us=inv_us, rse_after=rse,
+                dev_status=status, graphs=graph_schedule(K, G))
 
 
 def plain_rate(args, prec, init3, X, I, R, m, dev, K, G=50):
     """Steps/s of the plain method (TR-BRSGD, AdaGrad step) in precision
     ``prec`` on the same workload: draws, subchain, gradient, update; here
-    the gradient kernel is on the critical path of every step.  K steps
-    replayed from a HIP graph of G steps."""
+    the gradient kernel is on the critical path of every step.  Exactly K
+    steps replayed from HIP graphs (``graph_schedule``)."""
     import torch
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
     N = 3
     solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law="U", scaled=False,
                       prec=prec, rule=api.step_rule("adagrad", eta=1e-3), seed=args.seed)
-    solver.run(args.warmup)
-    graph = solver.capture(G)
-    graph.replay()
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(K // G):
-        graph.replay()
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / K
+    if args.warmup > 0:
+        solver.run(args.warmup)
+    ms = replay_timed(solver, K, G)
     status = int(solver.status.item())
-    del graph, solver
-    return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "dev_status": status}
+    del solver
+    return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "steps": K, "dev_status": status}
 
 
 def law_rate(args, law, init3, X, I, R, m, dev, K, G=50):
     """Steps/s of the scaled FP32 step with fibers drawn under ``law`` (E or
     L), including the refresh of the updated core's law after every step;
-    K steps replayed from a HIP graph of G steps."""
+    exactly K steps replayed from HIP graphs (``graph_schedule``)."""
     import torch
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRSolver, cores_to_device
@@ -285,20 +332,12 @@ def law_rate(args, law, init3, X, I, R, m, dev, K, G=50):
     solver = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law=law, scaled=True,
                       prec="f32", rule=api.step_rule("fixed", alpha=args.alpha), seed=args.seed,
                       overlap=not args.no_overlap)
-    solver.run(10)
-    graph = solver.capture(G)
-    graph.replay()
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(K // G):
-        graph.replay()
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / K
+    if args.warmup > 0:
+        solver.run(args.warmup)
+    ms = replay_timed(solver, K, G)
     status = int(solver.status.item())
-    del graph, solver
-    return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "dev_status": status}
+    del solver
+    return {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "steps": K, "dev_status": status}
 
 
 # An RSE check runs after a replay only when the step's own loss estimate,
@@ -385,8 +424,8 @@ def relerr_timing(desc, cores, X, reps=20):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is a design note, not implemented)"}))
+        print(json.dumps({"error": "--gpus must be 1: the path runs on one GPU "
+                          "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
 
@@ -413,7 +452,7 @@ def main():
     alt = timed_run(args, other, init3, X, I, R, m, dev, K, args.warmup)
     print(f"[bench] {other}: {alt['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
     plain = {pr: plain_rate(args, pr, init3, X, I, R, m, dev, K) for pr in ("f32", "bf16")}
-    laws = {lw: law_rate(args, lw, init3, X, I, R, m, dev, 500) for lw in ("E", "L")}
+    laws = {lw: law_rate(args, lw, init3, X, I, R, m, dev, K) for lw in ("E", "L")}
     print(f"[bench] scaled step under the Euclidean and leverage laws: {laws}", file=sys.stderr, flush=True)
     print(f"[bench] plain method: {plain}", file=sys.stderr, flush=True)
     ttt = []
@@ -481,10 +520,8 @@ def main():
         roof = {"bound": "mfma", "achieved": round(i_ach, 6), "peak": PEAK["f64"][0], "unit": "TFLOP/s",
                 "frac": round(i_ach / PEAK["f64"][0], 7), "traffic": measured_traffic("k_sweep"), "kernel": "k_sweep",
                 "kernel_avg_us": round(main["inv_us"], 3), "flops_per_launch": inv_flops,
-                "one_cu_peak": round(PEAK["f64"][0] / 256, 4),
-                "one_cu_frac": round(i_ach / (PEAK["f64"][0] / 256), 4),
-                "note": "one workgroup on one CU (by design: the inverse is a chain of 13 dependent 8-pivot "
-                        "steps); one_cu_frac is against that CU's share of the FP64 peak"}
+                "note": "one workgroup (the inverse is a chain of dependent pivot steps); frac is against the "
+                        "whole chip's FP64 peak"}
 
     batched = None
     if args.batch_steps > 0:
@@ -516,9 +553,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu oracle baseline ...", file=sys.stderr, flush=True)
-        v, k, th = cpu_baseline(args.cpu_seconds, args.seed, I, R, kappa, m, args.alpha)
-        cpu = {"value": round(v, 4), "unit": "steps/s", "cores": th, "kind": "oracle",
-               "sample": f"{k} oracle steps (FP64 numpy/scipy) of the same 400^3 workload after 1 warm-up step"}
+        host = host_info()
+        half = args.cpu_seconds / 2.0
+        v_all, k_all, th_all = cpu_baseline(half, args.seed, I, R, kappa, m, args.alpha, threads=host["nproc"])
+        v_one, k_one, th_one = cpu_baseline(half, args.seed, I, R, kappa, m, args.alpha, threads=1)
+        legs = {"threads_all": {"value": round(v_all, 4), "unit": "steps/s", "cores": th_all,
+                                "sample": f"{k_all} oracle steps, {th_all} BLAS threads, about {half:g} s"},
+                "threads_1": {"value": round(v_one, 4), "unit": "steps/s", "cores": th_one,
+                              "sample": f"{k_one} oracle steps, 1 BLAS thread, about {half:g} s"}}
+        best = max(legs.values(), key=lambda x: x["value"])
+        cpu = {"value": best["value"], "unit": "steps/s", "cores": best["cores"], "kind": "oracle",
+               "sample": f"oracle steps (FP64 numpy/scipy) of the same 400^3 scaled workload after 1 warm-up step; "
+                         f"value is the faster of the two thread settings ({best['sample']})",
+               **legs, "host": host}
 
     out = {
         "metric": "sampled-gradient steps/s + time to rel.err 1e-4: mixed vs plain FP32, 1 GPU",
