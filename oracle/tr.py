@@ -85,11 +85,10 @@ def subchain_product(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     I1, J1, K = A.shape
     K2, J2, I2 = B.shape
     assert K == K2
-    out = np.empty((I1, J1 * J2, I2))
-    for j2 in range(J2):
-        for j1 in range(J1):
-            out[:, j1 + J1 * j2, :] = A[:, j1, :] @ B[:, j2, :]
-    return out
+    # every pair (j1, j2) at once: T[a, j2, j1, b] = sum_k A[a, j1, k] B[k, j2, b],
+    # and the (j2, j1) axes flattened with j1 fastest give the multi-index
+    T = np.einsum("ajk,kcb->acjb", A, B)
+    return T.reshape(I1, J2 * J1, I2)
 
 
 def slices_hadamard(A: np.ndarray, B: np.ndarray) -> np.ndarray:
