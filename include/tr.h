@@ -141,10 +141,17 @@ int32_t tr_mode(uint64_t seed, uint64_t step, int32_t N);
  * dtype.  cdf_k: uint64 [I_k], inclusive prefix sums of the weights.
  * Leverage scores are l_i = g_i^T (G^T G)^{-1} g_i with the FP64 Gram
  * G^T G of G = G_{k(2)}, inverted by the blocked FP64 sweep for
- * R_k R_{k+1} <= 128 and through an FP64 Cholesky above; when
- * I_k <= R_k R_{k+1} the rows are taken as linearly independent and the law
- * is uniform.  A zero core or a Gram that is not positive definite sets
- * TR_DEV_ZERO_DIST / TR_DEV_NOT_SPD and writes the uniform CDF.  law must be
+ * R_k R_{k+1} <= 128 and through an FP64 Cholesky above.  The rank is
+ * found on the Gram: when a pivot of that factorisation is at or below
+ * 2^-40 of the largest diagonal entry, or when I_k <= R_k R_{k+1}, the
+ * scores come from a Cholesky with diagonal pivoting of G^T G stopped at
+ * pivots <= R_k R_{k+1} 2^-52 max diag: the rank r is the number of pivots
+ * taken, l_i = g_i[P]^T (G_P^T G_P)^{-1} g_i[P] over the chosen columns P
+ * (the diagonal of the projector onto the column space of G), and
+ * p(i) = l_i / r (r = I_k, full row rank: the uniform law).  This agrees with an SVD rank at the usual tolerance unless a
+ * singular value of G_{k(2)} lies between about 1e-13 and 1e-7 of the
+ * largest.  A zero core (Euclidean total 0, or leverage rank 0) sets
+ * TR_DEV_ZERO_DIST and writes the uniform CDF.  law must be
  * TR_LAW_LEVERAGE or TR_LAW_EUCLID.  ws: device workspace of at least
  * tr_dist_workspace_size bytes (row norms, or the Gram, its inverse and the
  * scores); the call fails with TR_E_WORKSPACE without it. */

@@ -4,7 +4,10 @@
 //   Leverage (Lemma lev_est):  p(i) = l_i(G_{k(2)}) / rank, l_i = g_i^T (G^T G)^{-1} g_i
 //                              with the FP64 Gram G^T G of G = G_{k(2)} (the sweep
 //                              inverse for R_k R_{k+1} <= 128, ||L^{-1} g_i||^2 with
-//                              its Cholesky factor L above).
+//                              its Cholesky factor L above); a Gram that is singular
+//                              or close to it, and I_k <= R_k R_{k+1}, take the
+//                              rank-revealing route (pivoted Cholesky, scores on the
+//                              chosen columns, divided by the rank found).
 //   Optimal (eq:optimal_prob): q(j) ~ ||X_[n](:,j) - G_{n(2)} s_j|| * ||s_j||
 //                              over the J_n columns, FP64.
 // Weights w = floor(p 2^40) + 1 and their inclusive prefix sums are exact
@@ -66,6 +69,7 @@ __device__ inline void write_uniform_weights(uint64_t* w, int64_t len) {
 // Weights staged in LDS when every core has at most this many rows (the
 // launch then passes lds_rows = max I_k, else 0).
 constexpr int kLdsRows = 8192;
+constexpr int kLevLdsRows = 4096;
 
 // w (Ik weights, in LDS or global memory) -> inclusive CDF in cdf; the
 // step counter advances afterwards when ``bump`` is set (every thread of
@@ -137,6 +141,137 @@ __global__ __launch_bounds__(1024) void k_euc_cdf(tr_desc d, ModeSrc ms, int use
     finish_cdf(w, cdf, Ik, bump);
 }
 
+// ----------------------------------------------------- rank-revealing law --
+//
+// Leverage law of a core whose unfolding may be rank deficient (Lemma
+// lev_est divides the scores of Definition "Leverage Scores" by the rank):
+// Cholesky with diagonal pivoting on the Gram B = G^T G of G = G_{k(2)}
+// (the largest remaining pivot first), stopped once no remaining pivot
+// exceeds RR 2^-52 max_i B_ii; r = the steps taken is the rank.  The chosen
+// columns P of G span its column space, so with L the r x r factor of B_PP
+//     l_i = g_i[P]^T (G_P^T G_P)^{-1} g_i[P] = ||L^{-1} g_i[P]||^2,
+// and r = I_k (full row rank, possible only when I_k <= RR) gives l_i = 1.
+// One block of 1024 threads.  Bm: RR x RR doubles of device scratch
+// (row-major) holding G^T G on entry, overwritten.  Writes the weights
+// floor(l_i / r 2^40) + 1 into w (r = 0, a zero core: the uniform law and
+// TR_DEV_ZERO_DIST).
+constexpr double kLevTrigger = 1.0 / 1099511627776.0;   // 2^-40: pivot test that sends the fast path here
+
+template <typename TC>
+__device__ void leverage_pivoted(const TC* __restrict__ G, int Ik, int RR, double* __restrict__ Bm,
+                                 uint64_t* __restrict__ w, int32_t* status) {
+    __shared__ int perm[kMaxRR];
+    __shared__ double dinv[kMaxRR];
+    __shared__ double xw[8][kMaxRR];   // rows are scored by the first eight wavefronts
+    __shared__ double rv[16];
+    __shared__ int ri[16];
+    __shared__ double red[16];
+    const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = T >> 6;
+    const int nB = RR;
+    for (int i = tid; i < nB; i += T) perm[i] = i;
+    __syncthreads();
+    double mx = 0.0;
+    for (int i = tid; i < nB; i += T) mx = fmax(mx, Bm[(int64_t)i * nB + i]);
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) red[wid] = mx;
+    __syncthreads();
+    mx = 0.0;
+    for (int q = 0; q < nw; ++q) mx = fmax(mx, red[q]);
+    const double tol = (double)nB * 2.220446049250313e-16 * mx;
+    int r = 0;
+    for (int j = 0; j < nB; ++j) {
+        // largest remaining pivot (ties: the smallest index)
+        double bv = -1.0;
+        int bi = nB;
+        for (int i = j + tid; i < nB; i += T) {
+            const double v = Bm[(int64_t)i * nB + i];
+            if (v > bv) { bv = v; bi = i; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) { rv[wid] = bv; ri[wid] = bi; }
+        __syncthreads();
+        bv = rv[0];
+        bi = ri[0];
+        for (int q = 1; q < nw; ++q)
+            if (rv[q] > bv || (rv[q] == bv && ri[q] < bi)) { bv = rv[q]; bi = ri[q]; }
+        __syncthreads();
+        if (!(bv > tol) || !isfinite(bv)) break;   // the same verdict in every thread
+        r = j + 1;
+        if (bi != j) {   // symmetric exchange of j and bi: rows (all columns), then columns of the trailing rows
+            for (int c = tid; c < nB; c += T) {
+                const double a = Bm[(int64_t)j * nB + c];
+                Bm[(int64_t)j * nB + c] = Bm[(int64_t)bi * nB + c];
+                Bm[(int64_t)bi * nB + c] = a;
+            }
+            __syncthreads();
+            for (int i = j + tid; i < nB; i += T) {
+                const double a = Bm[(int64_t)i * nB + j];
+                Bm[(int64_t)i * nB + j] = Bm[(int64_t)i * nB + bi];
+                Bm[(int64_t)i * nB + bi] = a;
+            }
+            if (tid == 0) {
+                const int a = perm[j];
+                perm[j] = perm[bi];
+                perm[bi] = a;
+            }
+            __syncthreads();
+        }
+        const double ljj = sqrt(Bm[(int64_t)j * nB + j]);
+        __syncthreads();
+        for (int i = j + 1 + tid; i < nB; i += T) Bm[(int64_t)i * nB + j] /= ljj;
+        if (tid == 0) Bm[(int64_t)j * nB + j] = ljj;
+        __syncthreads();
+        const int wd = nB - j - 1;
+        for (int e = tid; e < wd * wd; e += T) {
+            const int i = j + 1 + e / wd, c = j + 1 + e % wd;
+            Bm[(int64_t)i * nB + c] -= Bm[(int64_t)i * nB + j] * Bm[(int64_t)c * nB + j];
+        }
+        __syncthreads();
+    }
+    if (r == 0 || r == Ik) {   // zero core, or full row rank: every score 0 or 1
+        if (r == 0 && tid == 0) set_status(status, TR_DEV_ZERO_DIST);
+        write_uniform_weights(w, Ik);
+        return;
+    }
+    // L^{-1}: column c by thread c; its diagonal in dinv, the rest in the
+    // free upper triangle (entry (jj, c) of L^{-1} at Bm[c][jj]).
+    for (int c = tid; c < r; c += T) {
+        const double yc = 1.0 / Bm[(int64_t)c * nB + c];
+        dinv[c] = yc;
+        for (int jj = c + 1; jj < r; ++jj) {
+            double acc = Bm[(int64_t)jj * nB + c] * yc;
+            for (int k = c + 1; k < jj; ++k) acc += Bm[(int64_t)jj * nB + k] * Bm[(int64_t)c * nB + k];
+            Bm[(int64_t)c * nB + jj] = -acc / Bm[(int64_t)jj * nB + jj];
+        }
+    }
+    __syncthreads();
+    // l_i, one row per wavefront: x = g_i[P] staged in LDS, then z = L^{-1} x
+    // with the lanes over the entries of z.
+    double* x = xw[wid & 7];
+    for (int i = wid; i < Ik && wid < 8; i += 8) {
+        for (int c = lane; c < r; c += 64) x[c] = (double)G[(int64_t)i * RR + perm[c]];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double acc = 0.0;
+        for (int jj = lane; jj < r; jj += 64) {
+            double z = dinv[jj] * x[jj];
+            for (int c = 0; c < jj; ++c) z += Bm[(int64_t)c * nB + jj] * x[c];
+            acc += z * z;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) w[i] = quantize(acc / (double)r);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+}
+
 // Leverage law of core k (one block): Gram, Cholesky, row solves.
 template <typename TC>
 __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
@@ -150,11 +285,6 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
     const TC* G = static_cast<const TC*>(cores.p[k]);
     uint64_t* w = static_cast<uint64_t*>(cdf_out.p[k]);
     double* lev = reinterpret_cast<double*>(w);
-    if (Ik <= RR) {   // full row rank taken: every leverage score is 1
-        write_uniform_weights(w, Ik);
-        finish_cdf(w, w, Ik, bump);
-        return;
-    }
     for (int e = threadIdx.x; e < RR * RR; e += blockDim.x) {
         const int a = e % RR, b = e / RR;
         double s = 0.0;
@@ -162,13 +292,28 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
         A[e] = s;
     }
     __syncthreads();
-    // Right-looking Cholesky in A (column-major).
+    if (Ik <= RR) {   // the Gram is singular: pivoted; full row rank gives the uniform law
+        leverage_pivoted(G, Ik, RR, A, w, status);
+        finish_cdf(w, w, Ik, bump);
+        return;
+    }
+    __shared__ double dmax[16];
+    double mx = 0.0;
+    for (int c = threadIdx.x; c < RR; c += blockDim.x) mx = fmax(mx, A[c + (int64_t)RR * c]);
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) dmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) mx = fmax(mx, dmax[q]);
+    const double ptol = kLevTrigger * mx;
+    // Right-looking Cholesky in A (column-major); a pivot at or below ptol
+    // sends the law to the rank-revealing route.
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
     for (int j = 0; j < RR; ++j) {
         __syncthreads();
         const double djj = A[j + (int64_t)RR * j];
-        if (!(djj > 0.0) || !isfinite(djj)) {
+        if (!(djj > ptol) || !isfinite(djj)) {
             if (threadIdx.x == 0) bad = 1;
             break;
         }
@@ -184,9 +329,15 @@ __global__ __launch_bounds__(1024) void k_dist_leverage(tr_desc d, ModeSrc ms, i
         }
     }
     __syncthreads();
-    if (bad) {
-        if (threadIdx.x == 0) set_status(status, TR_DEV_NOT_SPD);
-        write_uniform_weights(w, Ik);
+    if (bad) {   // rank deficient (or close to it): the Gram again, then pivoted
+        for (int e = threadIdx.x; e < RR * RR; e += blockDim.x) {
+            const int a = e % RR, b = e / RR;
+            double s = 0.0;
+            for (int i = 0; i < Ik; ++i) s += (double)G[(int64_t)i * RR + a] * (double)G[(int64_t)i * RR + b];
+            A[e] = s;
+        }
+        __syncthreads();
+        leverage_pivoted(G, Ik, RR, A, w, status);
         finish_cdf(w, w, Ik, bump);
         return;
     }
@@ -296,12 +447,15 @@ __global__ __launch_bounds__(256) void k_lev_rows(tr_desc d, ModeSrc ms, int use
         lev[r0 + tid] = -(((sp[0][tid] + sp[1][tid]) + sp[2][tid]) + sp[3][tid]);
 }
 
-// Weights floor(l_i / RR 2^40) + 1 and their CDF (one block); a factor that
-// is not positive definite (the sweep's verdict) gives the uniform law and
-// TR_DEV_NOT_SPD, I_k <= RR gives the uniform law (every score is 1).
-__global__ __launch_bounds__(1024) void k_lev_cdf(tr_desc d, ModeSrc ms, int use_mode, int k_fixed,
-                                                  const double* __restrict__ lev, const int* __restrict__ flag,
-                                                  MutPtrs cdf_out, int32_t* status, uint64_t* bump, int lds_rows) {
+// Weights floor(l_i / RR 2^40) + 1 and their CDF (one block).  When the
+// sweep found a pivot at or below 2^-40 max_i h_ii (the Gram is singular or
+// close to it), or when I_k <= RR, the scores come from the rank-revealing
+// route instead (it overwrites the Gram ``gram``).
+template <typename TC>
+__global__ __launch_bounds__(1024) void k_lev_cdf(tr_desc d, ModeSrc ms, int use_mode, int k_fixed, Ptrs cores,
+                                                  double* __restrict__ gram, const double* __restrict__ lev,
+                                                  const int* __restrict__ flag, MutPtrs cdf_out, int32_t* status,
+                                                  uint64_t* bump, int lds_rows) {
     uint64_t t;
     int k = k_fixed;
     if (use_mode) resolve_mode(ms, d.N, &t, &k);
@@ -310,11 +464,8 @@ __global__ __launch_bounds__(1024) void k_lev_cdf(tr_desc d, ModeSrc ms, int use
     uint64_t* cdf = static_cast<uint64_t*>(cdf_out.p[k]);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint64_t* w = Ik <= lds_rows ? reinterpret_cast<uint64_t*>(smem_raw) : cdf;
-    if (Ik <= RR) {
-        write_uniform_weights(w, Ik);
-    } else if (*flag != 0) {
-        if (threadIdx.x == 0) set_status(status, TR_DEV_NOT_SPD);
-        write_uniform_weights(w, Ik);
+    if (Ik <= RR || *flag != 0) {
+        leverage_pivoted(static_cast<const TC*>(cores.p[k]), Ik, RR, gram, w, status);
     } else {
         for (int i = threadIdx.x; i < Ik; i += blockDim.x) w[i] = quantize(lev[i] / (double)RR);
         __syncthreads();
@@ -378,21 +529,30 @@ hipError_t launch_dist(const tr_desc& d, ModeSrc ms, bool use_mode, int k, int l
         double* gram = reinterpret_cast<double*>(w + L.gram_off);
         hipError_t e = launch_gram(d, mk, nullptr, nullptr, sh.maxI, gram, w, L.g, st, nullptr, cores);
         if (e != hipSuccess) return e;
-        // no status from the inverse: a factor that is not positive definite
-        // is reported by the CDF kernel as the law's own failure
-        e = launch_sweep_inverse(d, mk, gram, 0.0, L.u, w + L.upd_off, nullptr, st);
+        // no status from the inverse and no damping ladder: a pivot at or
+        // below 2^-40 of the largest diagonal entry sends the CDF kernel to
+        // the rank-revealing route
+        e = launch_sweep_inverse(d, mk, gram, 0.0, L.u, w + L.upd_off, nullptr, st, kLevTrigger);
         if (e != hipSuccess) return e;
         const double* hm = reinterpret_cast<const double*>(w + L.upd_off + L.u.L_off);
         const int* flag = reinterpret_cast<const int*>(w + L.upd_off + L.u.flag_off);
         double* lev = reinterpret_cast<double*>(w + L.lev_off);
         const dim3 grid((sh.maxI + kLevRows - 1) / kLevRows);
+        // the CDF kernel's static LDS (rank-revealing route, about 20 KB)
+        // plus the staged weights stay within 64 KB
+        const int lev_lds_rows = sh.maxI <= kLevLdsRows ? sh.maxI : 0;
+        const size_t lev_lds = (size_t)lev_lds_rows * 8;
         if (f64)
             hipLaunchKernelGGL(k_lev_rows<double>, grid, dim3(256), 0, st, d, ms, (int)use_mode, k, cores, hm, lev);
         else
             hipLaunchKernelGGL(k_lev_rows<float>, grid, dim3(256), 0, st, d, ms, (int)use_mode, k, cores, hm, lev);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_lev_cdf, dim3(1), dim3(1024), lds, st, d, ms, (int)use_mode, k, lev, flag, out, status,
-                           bump, lds_rows);
+        if (f64)
+            hipLaunchKernelGGL(k_lev_cdf<double>, dim3(1), dim3(1024), lev_lds, st, d, ms, (int)use_mode, k, cores,
+                               gram, lev, flag, out, status, bump, lev_lds_rows);
+        else
+            hipLaunchKernelGGL(k_lev_cdf<float>, dim3(1), dim3(1024), lev_lds, st, d, ms, (int)use_mode, k, cores,
+                               gram, lev, flag, out, status, bump, lev_lds_rows);
     } else if (law == TR_LAW_LEVERAGE) {
         double* A = static_cast<double*>(ws);
         if (f64)

@@ -132,7 +132,7 @@ hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram,
 // The two halves: -(gram + damping I)^{-1} (one workgroup) and the
 // row-parallel p = g (-M^{-1}) with the rule.
 hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const UpdWs& L,
-                                void* ws, int32_t* status, hipStream_t st);
+                                void* ws, int32_t* status, hipStream_t st, double rank_tol = 0.0);
 hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossParts lp, double* loss, MutPtrs cores,
                               MutPtrs accum, tr_step rule, int32_t* status, void* ws, const UpdWs& L, StepBump step,
                               hipStream_t st);

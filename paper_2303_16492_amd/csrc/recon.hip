@@ -442,7 +442,7 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
         __syncthreads();
         h16x8 bh[K16], bl[K16];
         int it_loaded = -1;
-        float bscale = 0.f;
+        double bscale = 0.0;   // 2^-(eA + escale): applied in FP64, exact at any tensor scale
         // X_true entries of pair pr, read at clamped indices and kept as
         // loaded (no select on them, which would wait for the load at
         // once); entries outside the tensor are skipped where they are used
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
                     bh[q] = sh[q * 64];
                     bl[q] = sl[q * 64];
                 }
-                bscale = ldexpf(1.f, -(eA + escale[it]));
+                bscale = ldexp(1.0, -(eA + escale[it]));
             }
             const int64_t* offw = sOff + 32 * ct + 4 * lh;
             const h16x8* ah = reinterpret_cast<const h16x8*>(Ah + (32 * ct + lc) * HP + 8 * lh);
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256) void k_recon_mfma(tr_desc d, Ptrs cores, const
                     const int64_t o = offw[8 * (r >> 2) + (r & 3)];
                     if (o < 0) continue;
                     const double xd = (double)Cvt<TX>::to_f32(x[r]);
-                    const double df = (double)(acc[r] * bscale) - xd;
+                    const double df = (double)acc[r] * bscale - xd;
                     err += df * df;
                     xx += xd * xd;
                 }

@@ -94,8 +94,8 @@ __device__ __forceinline__ double rcp_nr(double p) {
 //     a_kk <- -1 / a_kk,
 // the classical symmetric sweep.  Only lower-triangle entries are read, so
 // the lanes of the lower triangle compute exactly the operations of the
-// sequential algorithm on that triangle.  False on a pivot that is not
-// positive (or not finite); every lane reaches the same verdict.
+// sequential algorithm on that triangle.  False on a pivot not above ``tol``
+// (0: not positive) or not finite; every lane reaches the same verdict.
 __device__ __forceinline__ double permute_lane(double v, int src) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
@@ -104,29 +104,29 @@ __device__ __forceinline__ double permute_lane(double v, int src) {
 }
 
 template <int K>
-__device__ __forceinline__ void sweep8_pivot(double& a, bool& good, int i, int j) {
+__device__ __forceinline__ void sweep8_pivot(double& a, bool& good, int i, int j, double tol) {
     const double p = readlane_f64(a, 9 * K);
     const double ci = permute_lane(a, i > K ? 8 * i + K : 8 * K + i);
     const double cj = permute_lane(a, j > K ? 8 * j + K : 8 * K + j);
-    good = good && (p > 0.0) && isfinite(p);
+    good = good && (p > tol) && isfinite(p);
     const double dk = rcp_nr(p);
     const double ti = ci * dk, tj = cj * dk;
     const double up = __builtin_fma(-ti, cj, a);
     a = (i != K) ? ((j != K) ? up : ti) : ((j != K) ? tj : -dk);   // selects, no branches
 }
 
-__device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw) {
+__device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw, double tol) {
     const int l = threadIdx.x & 63, i = l >> 3, j = l & 7;
     double a = D8[i * 8 + j];
     bool good = true;
-    sweep8_pivot<0>(a, good, i, j);
-    sweep8_pivot<1>(a, good, i, j);
-    sweep8_pivot<2>(a, good, i, j);
-    sweep8_pivot<3>(a, good, i, j);
-    sweep8_pivot<4>(a, good, i, j);
-    sweep8_pivot<5>(a, good, i, j);
-    sweep8_pivot<6>(a, good, i, j);
-    sweep8_pivot<7>(a, good, i, j);
+    sweep8_pivot<0>(a, good, i, j, tol);
+    sweep8_pivot<1>(a, good, i, j, tol);
+    sweep8_pivot<2>(a, good, i, j, tol);
+    sweep8_pivot<3>(a, good, i, j, tol);
+    sweep8_pivot<4>(a, good, i, j, tol);
+    sweep8_pivot<5>(a, good, i, j, tol);
+    sweep8_pivot<6>(a, good, i, j, tol);
+    sweep8_pivot<7>(a, good, i, j, tol);
     if (j <= i) Bw[tri8(i) + j] = a;
     return good;
 }
@@ -309,7 +309,7 @@ struct SweepShared {
 // wavefront forms pivot block q+1 as it will be after step q and sweeps it.
 // Returns the verdict on pivot block q + 1 (true after the last step).
 template <int NT, int WV, int HQ>
-__device__ __forceinline__ bool sweep_step(dbl4 (&acc)[tpw<NT>()], SweepShared& sh, int q, int npiv) {
+__device__ __forceinline__ bool sweep_step(dbl4 (&acc)[tpw<NT>()], SweepShared& sh, int q, int npiv, double tol) {
     const double* Vt = sh.Vt[HQ];
     const bool more = q + 1 < npiv;
     if (WV == kFactorWave) {
@@ -319,7 +319,7 @@ __device__ __forceinline__ bool sweep_step(dbl4 (&acc)[tpw<NT>()], SweepShared& 
             __builtin_amdgcn_s_waitcnt(0xc07f);
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const bool g = sweep8(sh.Dn, sh.Bw[HQ ^ 1]);
+            const bool g = sweep8(sh.Dn, sh.Bw[HQ ^ 1], tol);
             if ((threadIdx.x & 63) == 0) sh.good[HQ ^ 1] = g ? 1 : 0;
         }
     } else {
@@ -343,13 +343,25 @@ __device__ __forceinline__ bool sweep_step(dbl4 (&acc)[tpw<NT>()], SweepShared& 
 // One wavefront's part of the sweep with the fallback ladder.  Returns the
 // attempt that succeeded, or -1.  Every wavefront passes the same barriers
 // and reads the same verdicts, so every wavefront returns the same value.
+// rank_tol > 0: a rank test instead of the ladder; one attempt, and a pivot
+// not above rank_tol * max_i h_ii fails it.
 template <int NT, int WV>
-__device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int RR, double damping,
+__device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int RR, double damping, double rank_tol,
                                           double* __restrict__ hm, SweepShared& sh) {
     const int npiv = (RR + 7) >> 3;
     dbl4 acc[tpw<NT>()];
     double base = 0.0;   // tr(h + damping I) / RR, needed only once a factorisation has failed
-    for (int attempt = 0; attempt < 8; ++attempt) {
+    double tol = 0.0;
+    if (rank_tol > 0.0) {
+        double mx = 0.0;
+        for (int c = threadIdx.x; c < RR; c += blockDim.x) mx = fmax(mx, gram[(int64_t)c * RR + c]);
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        tol = rank_tol * fmax(fmax(sh.red[0], sh.red[1]), fmax(sh.red[2], sh.red[3]));
+    }
+    const int attempts = rank_tol > 0.0 ? 1 : 8;
+    for (int attempt = 0; attempt < attempts; ++attempt) {
         if (attempt == 1) {
             double tr = 0.0;
             for (int c = threadIdx.x; c < RR; c += blockDim.x) tr += gram[(int64_t)c * RR + c];
@@ -375,7 +387,7 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
             __builtin_amdgcn_s_waitcnt(0xc07f);
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const bool g = sweep8(sh.Dn, sh.Bw[0]);
+            const bool g = sweep8(sh.Dn, sh.Bw[0], tol);
             if ((threadIdx.x & 63) == 0) sh.good[0] = g ? 1 : 0;
         } else {
             fill_tiles<NT, WV>(acc, gram, RR, eta);
@@ -385,8 +397,8 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
         // block steps in pairs (even q, then odd q)
         bool good = sh.good[0] != 0;
         for (int q = 0; q < npiv && good; q += 2) {
-            good = sweep_step<NT, WV, 0>(acc, sh, q, npiv);
-            if (good && q + 1 < npiv) good = sweep_step<NT, WV, 1>(acc, sh, q + 1, npiv);
+            good = sweep_step<NT, WV, 0>(acc, sh, q, npiv, tol);
+            if (good && q + 1 < npiv) good = sweep_step<NT, WV, 1>(acc, sh, q + 1, npiv, tol);
         }
         if (good) {
             if (WV != kFactorWave) store_tiles<NT, WV>(acc, hm, RR);
@@ -397,11 +409,13 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
 }
 
 // -(gram + eta I)^{-1} into hm (RR x RR, row-major, both triangles), with
-// the fallback ladder; flag: 0 ok, 1 damped, 2 failed.  256 threads.
+// the fallback ladder; flag: 0 ok, 1 damped, 2 failed.  With rank_tol > 0
+// (the leverage law) there is no ladder: flag 2 means a pivot at or below
+// rank_tol * max_i gram_ii, i.e. the Gram is taken as singular.  256 threads.
 template <int NT>
 __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const double* __restrict__ gram,
-                                               double damping, double* __restrict__ hm, int* __restrict__ flag,
-                                               int32_t* status) {
+                                               double damping, double rank_tol, double* __restrict__ hm,
+                                               int* __restrict__ flag, int32_t* status) {
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
@@ -410,10 +424,10 @@ __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const doub
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int ok_at;
     switch (w) {
-        case 0: ok_at = sweep_wave<NT, 0>(gram, RR, damping, hm, sh); break;
-        case 1: ok_at = sweep_wave<NT, 1>(gram, RR, damping, hm, sh); break;
-        case 2: ok_at = sweep_wave<NT, 2>(gram, RR, damping, hm, sh); break;
-        default: ok_at = sweep_wave<NT, 3>(gram, RR, damping, hm, sh); break;
+        case 0: ok_at = sweep_wave<NT, 0>(gram, RR, damping, rank_tol, hm, sh); break;
+        case 1: ok_at = sweep_wave<NT, 1>(gram, RR, damping, rank_tol, hm, sh); break;
+        case 2: ok_at = sweep_wave<NT, 2>(gram, RR, damping, rank_tol, hm, sh); break;
+        default: ok_at = sweep_wave<NT, 3>(gram, RR, damping, rank_tol, hm, sh); break;
     }
     if (threadIdx.x == 0) {
         const int fl = ok_at < 0 ? 2 : (ok_at > 0 ? 1 : 0);
@@ -522,7 +536,7 @@ __global__ __launch_bounds__(64) void k_scaled_apply(tr_desc d, ModeSrc ms, cons
 bool sweep_supported(const tr_desc& d) { return shape_of(d).maxRR <= 128; }
 
 hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const UpdWs& L,
-                                void* ws, int32_t* status, hipStream_t st) {
+                                void* ws, int32_t* status, hipStream_t st, double rank_tol) {
     const Shape sh = shape_of(d);
     if (sh.maxRR > 128) return hipErrorInvalidValue;
     char* w = static_cast<char*>(ws);
@@ -538,7 +552,8 @@ hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram
 #define TRK_SWEEP(NTV)                                                                                          \
     do {                                                                                                        \
         const size_t dyn = allow_lds(reinterpret_cast<const void*>(&k_sweep<NTV>), reserve) ? reserve : 0;     \
-        hipLaunchKernelGGL(k_sweep<NTV>, dim3(1), dim3(256), dyn, st, d, ms, gram, damping, hm, flag, status); \
+        hipLaunchKernelGGL(k_sweep<NTV>, dim3(1), dim3(256), dyn, st, d, ms, gram, damping, rank_tol, hm, \
+                           flag, status);                                                               \
     } while (0)
     switch (nt) {
         case 1: TRK_SWEEP(1); break;

@@ -185,14 +185,19 @@ def test_full_batch_step_at_bench_configuration(splits):
     """The 64-problem workload the benchmark times (orders 3-5, sizes 16-128,
     ranks 3-12, FP16 tensors, m = 1024, AdaGrad) in its launch configuration
     (chunks of 64 samples, eight wavefronts, each problem's samples on one or
-    four workgroups): one step of all problems; the
-    smallest problem of each order is checked against the oracle, every
-    problem advances its counter with no device flag raised."""
+    four workgroups): one step of all problems; the smallest problem of each
+    order, the problem with the largest R_n R_{n+1} and the one with the most
+    entries are checked against the oracle, every problem advances its
+    counter with no device flag raised."""
     inst = ti.batched_instances(0)
     sampled = {}
     for N in (3, 4, 5):
         p = min((q for q, b in enumerate(inst) if b.N == N), key=lambda q: int(np.prod(inst[q].I)))
         sampled[p] = None
+    rr = [max(b.R[k] * b.R[(k + 1) % b.N] for k in range(b.N)) for b in inst]
+    sampled[int(np.argmax(rr))] = None
+    sampled[int(np.argmax([int(np.prod(b.I)) for b in inst]))] = None
+    assert len(sampled) == 5
     m, eta = 1024, 0.05
     probs, host = [], {}
     for p, b in enumerate(inst):
@@ -222,21 +227,26 @@ def test_full_batch_step_at_bench_configuration(splits):
     assert int(B.status.max()) == 0
     for p in sorted(sampled):
         X, init, b = host[p]
-        (st, losses), = oracle_steps([host[p]], m, 1, "adagrad", eta=eta)
+        say("oracle step of problem", p, b.N, b.I, b.R)
+        st = brsgd.State([c.copy() for c in init])
+        trace = {}
+        n = brsgd.step(st, X, brsgd.Config(m=m, eta=eta, rule="adagrad", seed=b.seed), trace=trace)
         for k in range(b.N):
             got = probs[p]["cores"][k].cpu().numpy().astype(np.float64)
             want, base = unfold(st.cores[k]), unfold(init[k])
-            if np.linalg.norm(want - base) == 0:
+            if k != n:
                 assert np.array_equal(got, base), (p, k)
                 continue
             # AdaGrad's first step is eta * sign(p) entrywise: an entry whose
-            # direction is below the 16-bit products' rounding may take the
-            # other sign; the rest must agree to the FP32 rounding of the sum.
+            # direction is below the rounding of the 16-bit products (relative
+            # 5e-3 of the largest) may take the other sign; every other entry
+            # must agree to the FP32 rounding of the sum.
             dg, dw = got - base, want - base
+            pdir = np.abs(trace["p"])
             flip = np.sign(dg) != np.sign(dw)
-            assert flip.mean() < 2e-3, (p, k, flip.mean())
+            assert np.all(pdir[flip] <= TOL16 * pdir.max()), (p, k, int(flip.sum()))
             assert rel(np.where(flip, 0.0, dg), np.where(flip, 0.0, dw)) < TOL16, (p, k)
-        assert abs(float(B.loss[p]) - losses[-1]) <= TOL16 * abs(losses[-1]), p
+        assert abs(float(B.loss[p]) - trace["loss"]) <= TOL16 * abs(trace["loss"]), p
     for pr in probs:
         for c in pr["cores"]:
             assert bool(torch.isfinite(c).all())

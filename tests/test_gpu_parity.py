@@ -180,6 +180,33 @@ def test_plain_update_parity(dtype, kind):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("b,eps", [(0.5, 0.0), (0.0, 0.2), (2.0, 0.25)])
+def test_adagrad_update_with_b_and_eps(dtype, b, eps):
+    """The AdaGrad rule with b > 0 and/or eps > 0 (the remark after
+    Algorithm TR-BRSGD): G += eta p / (b + A)^(1/2 + eps), A += p*p, with
+    some accumulator entries zero and some directions zero (b = 0 leaves
+    those entries unchanged)."""
+    I, R, cores, X, dcores, dX = problem(4, 3, [17, 9, 12], [3, 2, 4], dtype)
+    desc = api.make_desc(I, R, dtype)
+    n = 1
+    rule = api.step_rule("adagrad", eta=0.03, b=b, eps=eps)
+    cfg = brsgd.Config(m=1, rule="adagrad", eta=0.03, b=b, eps=eps)
+    rng = np.random.default_rng(1)
+    g = rounded(rng.standard_normal((I[n], R[n] * R[2])), dtype)
+    g[0, :3] = 0.0
+    acc0 = rounded(np.abs(rng.standard_normal(g.shape)), dtype)
+    acc0[0, :2] = 0.0
+    acc = to_dev(acc0, dtype)
+    core = dcores[n].clone()
+    say("adagrad b eps", dtype, b, eps)
+    st = api.tr_update(desc, n, core, to_dev(g, dtype), rule=rule, t=3, accum=acc)
+    new, A = brsgd.update(unfold(cores[n]), -g, cfg, 3, acc0)
+    assert rel(core.cpu().numpy(), new) < TOL[dtype]
+    assert rel(acc.cpu().numpy(), A) < TOL[dtype]
+    assert int(st) == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("damping", [0.0, 0.3])
 def test_scaled_update_parity(dtype, damping):
     I, R, cores, X, dcores, dX = problem(5, 3, [40, 30, 35], [3, 4, 3], dtype)
@@ -332,9 +359,9 @@ def test_relerr_and_reconstruct_parity(N, I, R, dtype):
     assert rel(Xh.cpu().numpy(), flat_paper(ref)) < TOL[dtype]
     rse = float(api.tr_relerr(desc, dcores, dX))
     want = tr.rse(cores, X)
-    assert abs(rse - want) <= 10 * TOL[dtype] * want
+    assert abs(rse - want) <= TOL[dtype] * want, (rse, want)
     rse2 = float(api.tr_relerr(desc, dcores, dX, x_true_norm2=float(np.sum(X * X))))
-    assert abs(rse2 - want) <= 10 * TOL[dtype] * want
+    assert abs(rse2 - want) <= TOL[dtype] * want, (rse2, want)
 
 
 @pytest.mark.parametrize("xdt", [torch.float32, torch.float16])
@@ -353,7 +380,7 @@ def test_relerr_matrix_core_shapes(N, I, R, xdt):
     say("relerr mfma", N, I, R, xdt)
     rse = float(api.tr_relerr(desc, dcores, dX))
     want = tr.rse(cores, X)
-    assert abs(rse - want) <= 10 * TOL[dtype] * want, (rse, want)
+    assert abs(rse - want) <= TOL[dtype] * want, (rse, want)
     Xh = api.tr_reconstruct(desc, dcores)
     ref = rounded(tr.full_tensor(cores), xdt)
     assert rel(Xh.double().cpu().numpy(), flat_paper(ref)) < (TOL[dtype] if xdt == torch.float32 else 1e-3)
@@ -380,6 +407,28 @@ def test_relerr_small_residual_matrix_cores():
     want = tr.rse(cores, X)
     assert 5e-6 < want < 2e-5
     assert abs(rse - want) <= 1e-2 * want, (rse, want)
+
+
+@pytest.mark.parametrize("scales", [(1e-20, 1e-5, 1e-5), (1e-11, 1e-11, 1e-11), (1e15, 1e5, 1e5),
+                                    (1e-25, 1e12, 1e12)])
+def test_relerr_matrix_cores_at_extreme_scales(scales):
+    """The RSE is scale-invariant: cores scaled so that X sits near the
+    bottom (about 1e-30, 1e-33) or well above (1e25) the usual range, or
+    with operand tiles of opposite extremes, give the oracle's RSE on the
+    same rounded values at the FP32 bar (the per-tile power-of-two scales
+    are undone in FP64)."""
+    I, R = [40, 30, 21], [6, 7, 5]
+    base = ti.gaussian_cores(41, 3, I, R, scale=0.7)
+    cores = [rounded(c * s_, torch.float32) for c, s_ in zip(base, scales)]
+    Xt = tr.full_tensor([c * s_ for c, s_ in zip(base, scales)])
+    X = rounded(Xt + 0.1 * np.sqrt(np.mean(Xt * Xt)) * ti.standard_normal(42, Xt.shape), torch.float32)
+    assert np.all(np.isfinite(X)) and np.min(np.abs(X[X != 0])) > 1.2e-38
+    desc = api.make_desc(I, R, torch.float32)
+    say("relerr scales", scales)
+    rse = float(api.tr_relerr(desc, [to_dev(unfold(c), torch.float32) for c in cores],
+                              to_dev(flat_paper(X), torch.float32)))
+    want = tr.rse(cores, X)
+    assert abs(rse - want) <= TOL[torch.float32] * want, (rse, want)
 
 
 @pytest.mark.parametrize("N,I,R", [(3, [40, 30, 21], [6, 7, 5]), (3, [70, 9, 10], [8, 16, 8])])
@@ -528,34 +577,91 @@ def test_full_size_mixed_gradient_at_bench_configuration():
         assert abs(float(loss) - lref) <= TOL[torch.bfloat16] * lref
 
 
+def _lev_weights(cdf):
+    return np.diff(np.concatenate([[0], cdf.cpu().numpy().astype(np.uint64)])).astype(np.int64)
+
+
+def _uniform_cdf(n):
+    w = np.full(n, int(sampling.quantize(np.array([1.0 / n]))[0]), dtype=np.uint64)
+    return np.cumsum(w)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_law_degenerate_cores(dtype):
-    """Failure paths of the mode-wise laws: a zero core gives the uniform
-    Euclidean CDF with TR_DEV_ZERO_DIST; a core whose unfolding has an
-    all-zero column (a Gram with a zero pivot) gives the uniform leverage
-    CDF with TR_DEV_NOT_SPD; a core with I_k <= R_k R_{k+1} gives the
-    uniform leverage CDF and no status."""
+    """Zero cores: the uniform Euclidean CDF with TR_DEV_ZERO_DIST, and the
+    uniform leverage CDF (rank 0) with TR_DEV_ZERO_DIST, as the oracle's
+    law returns for rank 0.  A core with I_k <= R_k R_{k+1} and full row
+    rank: the uniform leverage CDF and no status (every score is 1)."""
     I, R = [60, 7, 30], [3, 4, 2]
     _, _, cores, X, dcores, dX = problem(23, 3, I, R, dtype)
     desc = api.make_desc(I, R, dtype)
 
-    def uniform(n):
-        w = np.full(n, int(sampling.quantize(np.array([1.0 / n]))[0]), dtype=np.uint64)
-        return np.cumsum(w)
-
     say("euclid zero core")
     cdf, st = api.tr_dist(desc, 0, L.TR_LAW_EUCLID, torch.zeros_like(dcores[0]))
     assert int(st) == L.TR_DEV_ZERO_DIST
-    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), uniform(I[0]))
+    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), _uniform_cdf(I[0]))
 
-    say("leverage zero column")
-    G = unfold(cores[0]).copy()          # I_0 x R_0 R_1 = 60 x 12
-    G[:, 5] = 0.0
-    cdf, st = api.tr_dist(desc, 0, L.TR_LAW_LEVERAGE, to_dev(G, dtype))
-    assert int(st) == L.TR_DEV_NOT_SPD
-    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), uniform(I[0]))
+    say("leverage zero core")
+    for k in (0, 1):
+        cdf, st = api.tr_dist(desc, k, L.TR_LAW_LEVERAGE, torch.zeros_like(dcores[k]))
+        assert int(st) == L.TR_DEV_ZERO_DIST
+        assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), _uniform_cdf(I[k]))
+        assert np.allclose(sampling.dist_leverage(np.zeros_like(cores[k])), 1.0 / I[k])
 
     say("leverage I_k <= RR")
     cdf, st = api.tr_dist(desc, 1, L.TR_LAW_LEVERAGE, dcores[1])   # 7 x 8
     assert int(st) == 0
-    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), uniform(I[1]))
+    assert np.array_equal(cdf.cpu().numpy().astype(np.uint64), _uniform_cdf(I[1]))
+
+
+def _rank_deficient_unfoldings(seed, G):
+    """Unfoldings of the same shape as G whose rank is below min(shape), with
+    the deficiency exact in binary floating point (so an SVD at the usual
+    tolerance and the Gram's pivots agree on the rank): a zero column, a
+    duplicated column (or row, when rows are fewer than columns), and an
+    exact integer product of rank r."""
+    Ik, RR = G.shape
+    rng = np.random.default_rng(seed)
+    out = []
+    a = G.copy()
+    b = G.copy()
+    if Ik > RR:
+        a[:, RR // 2] = 0.0
+        b[:, RR - 1] = b[:, 1]
+        out += [("zero column", a), ("duplicated column", b)]
+    else:
+        a[Ik // 2, :] = 0.0
+        b[Ik - 1, :] = b[0, :]
+        out += [("zero row", a), ("duplicated row", b)]
+    r = max(1, min(Ik, RR) // 3)
+    A = rng.integers(-3, 4, size=(Ik, r)).astype(np.float64)
+    B = rng.integers(-3, 4, size=(r, RR)).astype(np.float64)
+    out.append((f"integer rank {r}", A @ B))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("I,R,k", [([60, 7, 30], [3, 4, 2], 0),      # sweep route, I_k > RR
+                                   ([60, 7, 30], [3, 4, 2], 1),      # I_k <= RR: G G^T
+                                   ([400, 30, 20], [10, 10, 10], 0),  # the benchmark's core shape
+                                   ([300, 20, 30], [12, 12, 4], 0)])  # RR = 144: one-block Cholesky route
+def test_leverage_law_rank_deficient_cores(dtype, I, R, k):
+    """The leverage law p(i) = l_i / rank (Lemma lev_est, Definition
+    "Leverage Scores") on unfoldings of lower rank, against the oracle's
+    SVD law: same integer weights up to 64 units of the 2^40 scale, no
+    status bit (a rank-deficient core has a valid law)."""
+    I, R, cores, X, dcores, dX = problem(29, 3, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+    Rk, Rk1 = R[k], R[(k + 1) % 3]
+    for name, G in _rank_deficient_unfoldings(31 + k, unfold(cores[k])):
+        G = rounded(G, dtype)
+        rank = int(np.linalg.matrix_rank(G))
+        assert rank < min(G.shape), name
+        say("leverage", name, I, R, k, dtype, "rank", rank)
+        cdf, st = api.tr_dist(desc, k, L.TR_LAW_LEVERAGE, to_dev(G, dtype))
+        wref = sampling.quantize(sampling.dist_leverage(fold(G, Rk, Rk1))).astype(np.int64)
+        w = _lev_weights(cdf)
+        assert int(st) == 0, name
+        assert np.max(np.abs(w - wref)) <= 64, (name, np.max(np.abs(w - wref)))
+
+

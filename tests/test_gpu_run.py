@@ -27,7 +27,9 @@ def planted(N, I, R, dtype, seed=0, noise_db=None):
 
 def test_fp64_trajectory_indices_bit_exact_every_step():
     """20^3, ranks 3, uniform fibers, m = 100, alpha = 0.2, 500 steps, seed 0:
-    the per-call path draws the oracle's index sets at every step."""
+    the per-call path draws the oracle's index sets and p_F at each of the
+    500 steps; final cores within 1e-10 and the final RSE within 1e-12 (RSE
+    units) of the oracle's."""
     N, I, R, m, steps = 3, 20, 3, 100, 500
     X, _, init = planted(N, I, R, torch.float64)
     desc = api.make_desc([I] * N, [R] * N, torch.float64)
@@ -46,16 +48,19 @@ def test_fp64_trajectory_indices_bit_exact_every_step():
         S = api.tr_subchain(desc, n, dcores, idx, m)
         g, _, _ = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, L.TR_PREC_F64)
         api.tr_update(desc, n, dcores[n], g, rule=rule, t=t)
-        if t % 25 == 0 or t == steps - 1:
+        if t % 100 == 0:
             say("trajectory step", t)
-            assert np.array_equal(idx.cpu().numpy(), trace["idx"])
-            assert np.array_equal(pF.cpu().numpy(), trace["pF"])
+        assert np.array_equal(idx.cpu().numpy(), trace["idx"]), t
+        assert np.array_equal(pF.cpu().numpy(), trace["pF"]), t
     for k in range(N):
         assert rel(dcores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-10
     want = tr.rse(st.cores, X)
     assert want < 1e-8
     got = float(api.tr_relerr(desc, dcores, dX))
-    assert abs(got - want) < 1e-10
+    # RSE units (relative to ||X||): the subtraction X_hat - X alone leaves
+    # about u ||X|| of error in a residual of size RSE ||X||
+    assert abs(got - want) < 1e-12, (got, want)
+    assert abs(got - want) < 1e-3 * want, (got, want)
 
 
 def _run_both(N, I, R, dtype, m, law, scaled, rule_kind, steps, seed=0, m_H=0, noise_db=40.0,
@@ -231,3 +236,82 @@ def test_adagrad_run_each_law_at_full_size(law):
     assert sol.t == 6 and int(sol.status.item()) == st.status
     for k in range(4):
         assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-4, (law, k)
+
+
+def _graph_steps(sol, steps):
+    """``steps`` steps from one captured graph of that length, replayed once
+    (the capture itself runs one eager step first)."""
+    g = sol.capture(steps)
+    g.replay()
+    torch.cuda.synchronize()
+    return g
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_benchmarked_configuration_equal_shapes(prec):
+    """The launch configuration the benchmark times, on a small problem:
+    every mode with the same I_n and R_n R_{n+1} (the Gram, its reduction
+    and the inverse then take mode 0's shape and never read the step
+    counter), the Gram/inverse branch on a second stream, the mode slot
+    published by the first kernel, graph capture and replay.  11 steps
+    against the FP64 oracle's trajectory."""
+    dtype = torch.float32
+    N, I, R, m = 3, 28, 3, 300
+    X, _, init = planted(N, I, R, dtype, seed=3, noise_db=None)
+    dX = to_dev(flat_paper(X), dtype)
+    sol = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [I] * N, [R] * N, m, scaled=True, prec=prec,
+                   rule=api.step_rule("fixed", alpha=0.5), seed=3, overlap=True)
+    assert sol.opts is not None
+    _graph_steps(sol, 10)
+    assert sol.t == 11
+    st = brsgd.State(init)
+    cfg = brsgd.Config(m=m, variant="scaled", alpha=0.5, seed=3)
+    for _ in range(11):
+        brsgd.step(st, X, cfg)
+    tol = 2e-4 if prec == "f32" else 5e-3
+    for k in range(N):
+        e = rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k]))
+        say("equal shapes", prec, k, e)
+        assert e < tol, (k, e)
+    assert int(sol.status.item()) == st.status
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_benchmarked_configuration_full_size(prec):
+    """The benchmark's workload and launch configuration: 400^3, ranks 10,
+    each unfolding with singular values from 1 to 1e-4, |F_n| = 4096,
+    alpha = 1, TRSolver with the second stream, captured one-step graphs
+    replayed.  Each of 4 steps is checked against the oracle's step from the
+    same (device) cores: the updated core within max(bar, 2^-22 cond(h)) of
+    the oracle's (its Hessian's condition number amplifies the rounding of
+    S), the other cores untouched, the step counter advanced."""
+    dtype = torch.float32
+    N, I, R, m = 3, 400, 10, 4096
+    true3 = ti.illcond_cores(0, N, I, R, 1e4)
+    X = tr.full_tensor(true3)
+    X = rounded(X / np.sqrt(np.mean(X * X)), dtype)
+    init = [rounded(c, dtype) for c in ti.gaussian_cores(1, N, I, R, scale=(1.0 / R ** N) ** (1 / (2 * N)))]
+    dX = to_dev(flat_paper(X), dtype)
+    sol = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [I] * N, [R] * N, m, scaled=True, prec=prec,
+                   rule=api.step_rule("fixed", alpha=1.0), seed=0, overlap=True)
+    g = sol.capture(1)               # t: 0 -> 1 (eager warm-up step)
+    torch.cuda.synchronize()
+    cfg = brsgd.Config(m=m, variant="scaled", alpha=1.0, seed=0)
+    bar = 1e-5 if prec == "f32" else 5e-3
+    for it in range(4):
+        before = [fold(c.double().cpu().numpy(), R, R) for c in sol.cores]
+        t = sol.t
+        st = brsgd.State([c.copy() for c in before], t=t)
+        trace = {}
+        n = brsgd.step(st, X, cfg, trace=trace)
+        g.replay()
+        torch.cuda.synchronize()
+        assert sol.t == t + 1
+        cond = float(np.linalg.cond(trace["h"]))
+        e = rel(sol.cores[n].double().cpu().numpy() - unfold(before[n]), trace["p"])
+        say("full-size run", prec, "step", t, "mode", n, "rel", e, "cond(h)", f"{cond:.3e}")
+        assert e < max(bar, 2.0 ** -22 * cond), (t, n, e, cond)
+        for k in range(N):
+            if k != n:
+                assert np.array_equal(sol.cores[k].double().cpu().numpy(), unfold(before[k]))
+    assert int(sol.status.item()) == 0
