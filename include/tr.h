@@ -47,7 +47,8 @@
  * bits (TR_DEV_*) in the caller's device word ``dev_status`` (OR-ed in,
  * never cleared by the library).  Calls are asynchronous on ``stream``;
  * results written to device scalars (loss, rse) are valid once the
- * stream reaches them.  The library keeps no mutable global state.
+ * stream reaches them.  The library keeps no mutable global state apart
+ * from the per-GPU address of tr_run_noalloc's scratch, set once.
  */
 #ifndef TR_H_
 #define TR_H_
@@ -337,6 +338,26 @@ typedef struct {
 tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps,
                     double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
                     tr_stream_t stream, const tr_run_opts* opts);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tr_run_ex
+ * with the library's own device scratch instead of a caller workspace.  The
+ * scratch is a static device array of TR_NOALLOC_SCRATCH_BYTES on every GPU
+ * the library runs on (kept until the process ends); its address on the
+ * current GPU is looked up on the first call there.  The call allocates
+ * nothing and computes exactly what tr_run_ex computes with a workspace.
+ * A problem/config whose tr_run_workspace_size exceeds
+ * TR_NOALLOC_SCRATCH_BYTES is rejected with TR_E_WORKSPACE (nothing
+ * enqueued).  Every call on one GPU shares that GPU's scratch and the
+ * scratch keeps the last call's contents (each step rewrites what it reads;
+ * the step counter scratch is cleared by a kernel at the start of every
+ * call): calls that overlap on one GPU (other streams, other host threads)
+ * race and must be serialised by the caller.  The current device must be
+ * the device of ``stream``. */
+#define TR_NOALLOC_SCRATCH_BYTES (16u << 20)
+tr_status tr_run_noalloc(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps,
+                         double* loss_out, int32_t* dev_status, tr_stream_t stream,
+                         const tr_run_opts* opts);
 
 /* ------------------------------------------------------------------ */
 /* a10: sampled-entry loss, forward and backward for every core        */

@@ -18,6 +18,8 @@ TR_MAX_ORDER = 8
 TR_MAX_RANK = 16
 
 TR_OK = 0
+TR_E_ARG, TR_E_SHAPE, TR_E_DTYPE, TR_E_ALIGN, TR_E_WORKSPACE, TR_E_HIP, TR_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+TR_NOALLOC_SCRATCH_BYTES = 16 << 20
 TR_F64, TR_F32, TR_F16, TR_BF16 = 0, 1, 2, 3
 TR_PREC_F64, TR_PREC_F32, TR_PREC_BF16, TR_PREC_F16 = 0, 1, 2, 3
 TR_LAW_UNIFORM, TR_LAW_LEVERAGE, TR_LAW_EUCLID, TR_LAW_OPTIMAL = 0, 1, 2, 3
@@ -132,6 +134,8 @@ _SIGS = {
                             VP]),
     "tr_run_ex": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP, SZ, VP,
                         C.POINTER(tr_run_opts)]),
+    "tr_run_noalloc": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP,
+                             C.POINTER(tr_run_opts)]),
     "tr_run_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_config)]),
     "tr_batch_table_size": (SZ, [I32]),
     "tr_batch_upload": (I32, [C.POINTER(tr_batch_item), I32, VP, SZ, VP]),

@@ -211,6 +211,13 @@ def tr_run_ex(problem: L.tr_problem, config: L.tr_config, t_dev, steps, loss_out
                                        C.byref(opts) if opts is not None else None))
 
 
+def tr_run_noalloc(problem: L.tr_problem, config: L.tr_config, t_dev, steps, loss_out, status, opts=None):
+    """tr_run_ex on the library's own device scratch (no workspace)."""
+    check("tr_run_noalloc", lib().tr_run_noalloc(C.byref(problem), C.byref(config), _p(t_dev), steps,
+                                                 _p(loss_out), _p(status), _stream(),
+                                                 C.byref(opts) if opts is not None else None))
+
+
 def tr_run_workspace_size(problem, config) -> int:
     return lib().tr_run_workspace_size(C.byref(problem), C.byref(config))
 

@@ -1,8 +1,15 @@
 // C ABI of include/tr.h: host validation, workspace sizing, dispatch, and
 // the multi-step driver (Algorithm TR-BRSGD / TR-ScaledBRSGD).
 #include <cstring>
+#include <mutex>
 
 #include "internal.hpp"
+
+// Device scratch of tr_run_noalloc, for callers that cannot allocate: one
+// copy per GPU the library runs on, held until the process ends.  In host
+// code ``scratch`` is only a stand-in for the symbol; its device address on
+// the current GPU comes from hipGetSymbolAddress (see noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[TR_NOALLOC_SCRATCH_BYTES];
 
 namespace trk {
 
@@ -540,6 +547,51 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
             e = launch_dist(d, ms, true, 0, c->law, cores, p->cdf, dev_status, w + L.dist, st, t_dev);
     }
     return hip_status(e);
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_addr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+std::once_flag g_scratch_once[kMaxDevices];
+
+// Device address of ``scratch`` on the current GPU, looked up once per GPU
+// (with that GPU current) and kept.
+hipError_t noalloc_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::call_once(g_scratch_once[dev], [dev]() {
+        void* ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_addr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    });
+    if (g_scratch_err[dev] != hipSuccess) return g_scratch_err[dev];
+    *out = g_scratch_addr[dev];
+    return *out ? hipSuccess : hipErrorInvalidSymbol;
+}
+
+}  // namespace
+
+extern "C" {
+
+tr_status tr_run_noalloc(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps, double* loss_out,
+                         int32_t* dev_status, tr_stream_t stream, const tr_run_opts* opts) {
+    if (!p || !c || !t_dev) return TR_E_ARG;
+    tr_status s = validate_desc(&p->desc);
+    if (s != TR_OK) return s;
+    if (c->m < 1 || c->m > kMaxM || c->m_H < 0 || c->m_H > kMaxM) return TR_E_SHAPE;
+    if (run_layout(p, c).total > (size_t)TR_NOALLOC_SCRATCH_BYTES) return TR_E_WORKSPACE;
+    void* ws = nullptr;
+    if (noalloc_scratch(&ws) != hipSuccess) {
+        (void)hipGetLastError();
+        return TR_E_HIP;
+    }
+    return tr_run_ex(p, c, t_dev, steps, loss_out, dev_status, ws, (size_t)TR_NOALLOC_SCRATCH_BYTES, stream, opts);
 }
 
 size_t tr_batch_table_size(int32_t count) { return count > 0 ? align_up((size_t)count * sizeof(tr_batch_item)) : 0; }
