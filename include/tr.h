@@ -339,6 +339,51 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                     double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
                     tr_stream_t stream, const tr_run_opts* opts);
 
+/* ------------------------------------------------------------------ */
+/* The paper's comparison methods, one sweep over the cores at a time   */
+/* ------------------------------------------------------------------ */
+
+/*   TR_METHOD_GD:          TR-GD, the update rule after eq:gradient:
+ *                          G_n -= alpha grad_n f for every n, all from the
+ *                          iterate the sweep starts at.
+ *   TR_METHOD_SCALED_GD:   TR-ScaledGD (eq:scaled_gd): G_n -= alpha grad_n f
+ *                          ((G^{!=n}_[2])^T G^{!=n}_[2] + J_n damping I)^{-1},
+ *                          all n from the sweep's starting iterate.
+ *   TR_METHOD_ALS:         TR-ALS (Algorithm alg:tr_als): n = 1..N in turn,
+ *                          G_n <- the least-squares solution with the other
+ *                          cores at their latest values (= TR-ScaledGD's
+ *                          block step at alpha = 1).
+ *   TR_METHOD_ALS_SAMPLED: TR-ALS-Sampled (the sampled ALS subproblem after
+ *                          Algorithm alg:tr_als): the same sweep on m fibers
+ *                          drawn by Algorithm SSDTP under ``law`` (U, L or E)
+ *                          with the rows weighted by 1/sqrt(m p_f), i.e. the
+ *                          TR-ScaledBRSGD step at alpha = 1 with H_n = F_n.
+ * The full-batch methods run the sampled-step kernels on every column of
+ * X_[n] once (p = 1/J_n: the stochastic gradient of eq:S_gradient is then
+ * grad f / J_n exactly); J_n must not exceed 2^24. */
+typedef enum { TR_METHOD_GD = 0, TR_METHOD_SCALED_GD = 1, TR_METHOD_ALS = 2,
+               TR_METHOD_ALS_SAMPLED = 3 } tr_method;
+
+typedef struct {
+    int32_t method;     /* tr_method                                           */
+    int32_t m;          /* TR-ALS-Sampled: fibers per block; otherwise unused   */
+    int32_t law;        /* TR-ALS-Sampled: TR_LAW_UNIFORM/LEVERAGE/EUCLID       */
+    int32_t prec;       /* tr_prec of the contractions                         */
+    double alpha;       /* TR-GD / TR-ScaledGD step size (> 0)                 */
+    double damping;     /* eta added to the normalised Hessian factor          */
+    uint64_t seed;      /* TR-ALS-Sampled draws                                */
+} tr_sweep_config;
+
+/* Enqueue ``sweeps`` sweeps; each is N block updates in the order
+ * n = 0..N-1 and advances *t_dev by one per block (TR-ALS-Sampled draws block
+ * n of a sweep at step t = *t_dev with mode n fixed).  Cores are updated in
+ * place; dev_status collects TR_DEV_* bits.  Graph-capturable.  ws: device
+ * workspace of tr_sweep_workspace_size bytes, 256-byte aligned.  Laws L and E
+ * need the problem's per-mode CDF buffers. */
+size_t tr_sweep_workspace_size(const tr_problem* p, const tr_sweep_config* c);
+tr_status tr_sweep_run(const tr_problem* p, const tr_sweep_config* c, uint64_t* t_dev, int32_t sweeps,
+                       int32_t* dev_status, void* ws, size_t ws_bytes, tr_stream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): tr_run_ex
  * with the library's own device scratch instead of a caller workspace.  The

@@ -74,6 +74,21 @@ class tr_config(C.Structure):
     ]
 
 
+TR_METHOD_GD, TR_METHOD_SCALED_GD, TR_METHOD_ALS, TR_METHOD_ALS_SAMPLED = 0, 1, 2, 3
+
+
+class tr_sweep_config(C.Structure):
+    _fields_ = [
+        ("method", C.c_int32),
+        ("m", C.c_int32),
+        ("law", C.c_int32),
+        ("prec", C.c_int32),
+        ("alpha", C.c_double),
+        ("damping", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
 VP = C.c_void_p
 PVP = C.POINTER(C.c_void_p)
 
@@ -137,6 +152,8 @@ _SIGS = {
     "tr_run_noalloc": (I32, [C.POINTER(tr_problem), C.POINTER(tr_config), VP, I32, VP, VP, VP,
                              C.POINTER(tr_run_opts)]),
     "tr_run_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_config)]),
+    "tr_sweep_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_sweep_config)]),
+    "tr_sweep_run": (I32, [C.POINTER(tr_problem), C.POINTER(tr_sweep_config), VP, I32, VP, VP, SZ, VP]),
     "tr_batch_table_size": (SZ, [I32]),
     "tr_batch_upload": (I32, [C.POINTER(tr_batch_item), I32, VP, SZ, VP]),
     "tr_batch_run": (I32, [VP, I32, I32, I32, I32, VP]),

@@ -218,6 +218,15 @@ def tr_run_noalloc(problem: L.tr_problem, config: L.tr_config, t_dev, steps, los
                                                  C.byref(opts) if opts is not None else None))
 
 
+def tr_sweep_run(problem: L.tr_problem, config: L.tr_sweep_config, t_dev, sweeps, status, ws):
+    check("tr_sweep_run", lib().tr_sweep_run(C.byref(problem), C.byref(config), _p(t_dev), sweeps, _p(status),
+                                             _p(ws), ws.numel(), _stream()))
+
+
+def tr_sweep_workspace_size(problem, config) -> int:
+    return lib().tr_sweep_workspace_size(C.byref(problem), C.byref(config))
+
+
 def tr_run_workspace_size(problem, config) -> int:
     return lib().tr_run_workspace_size(C.byref(problem), C.byref(config))
 

@@ -142,6 +142,45 @@ static RunWs run_layout(const tr_problem* p, const tr_config* c) {
     return L;
 }
 
+// Workspace of tr_sweep_run: the step driver's layout for the largest block
+// (every column J_n for the full-batch methods, m for TR-ALS-Sampled), then
+// a copy of every core (the iterate a TR-GD / TR-ScaledGD sweep starts from).
+struct SweepRunWs {
+    RunWs r;
+    size_t snap, total;
+    size_t snap_off[kMaxOrder];
+};
+
+static bool sweep_full(int method) { return method == TR_METHOD_GD || method == TR_METHOD_SCALED_GD || method == TR_METHOD_ALS; }
+
+static tr_config sweep_as_config(const tr_problem* p, const tr_sweep_config* c) {
+    tr_config r{};
+    r.m = sweep_full(c->method) ? (int)shape_of(p->desc).maxJ : c->m;
+    r.m_H = 0;
+    r.law = sweep_full(c->method) ? TR_LAW_UNIFORM : c->law;
+    r.scaled = c->method != TR_METHOD_GD;
+    r.prec = c->prec;
+    r.damping = c->damping;
+    r.seed = c->seed;
+    return r;
+}
+
+static SweepRunWs sweep_layout(const tr_problem* p, const tr_sweep_config* c) {
+    SweepRunWs L{};
+    const tr_config rc = sweep_as_config(p, c);
+    L.r = run_layout(p, &rc);
+    const tr_desc& d = p->desc;
+    const size_t es = dtype_size(d.core_dtype);
+    size_t o = L.r.total;
+    L.snap = o;
+    for (int k = 0; k < d.N; ++k) {
+        L.snap_off[k] = o;
+        o += align_up((size_t)d.I[k] * d.R[k] * d.R[ring_next(k, d.N)] * es);
+    }
+    L.total = o;
+    return L;
+}
+
 }  // namespace trk
 
 using namespace trk;
@@ -546,6 +585,117 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
         if (e == hipSuccess && refresh)   // the law's last kernel also advances the step counter
             e = launch_dist(d, ms, true, 0, c->law, cores, p->cdf, dev_status, w + L.dist, st, t_dev);
     }
+    return hip_status(e);
+}
+
+static tr_status check_sweep(const tr_problem* p, const tr_sweep_config* c) {
+    if (!p || !c) return TR_E_ARG;
+    const tr_desc& d = p->desc;
+    tr_status s = validate_desc(&d);
+    if (s != TR_OK) return s;
+    if ((s = check_cores(&d, const_cast<const void* const*>(p->cores))) != TR_OK) return s;
+    if (!p->X) return TR_E_ARG;
+    if (c->method < TR_METHOD_GD || c->method > TR_METHOD_ALS_SAMPLED) return TR_E_ARG;
+    if ((s = check_prec(&d, c->prec)) != TR_OK) return s;
+    if (!(c->damping >= 0.0)) return TR_E_ARG;
+    if (sweep_full(c->method)) {
+        if (shape_of(d).maxJ > kMaxM) return TR_E_SHAPE;
+        if (c->method == TR_METHOD_GD && !(c->alpha > 0.0)) return TR_E_ARG;
+        if (c->method == TR_METHOD_SCALED_GD && !(c->alpha > 0.0)) return TR_E_ARG;
+    } else {
+        if (c->m < 1 || c->m > kMaxM) return TR_E_SHAPE;
+        if (c->law != TR_LAW_UNIFORM && c->law != TR_LAW_LEVERAGE && c->law != TR_LAW_EUCLID) return TR_E_UNSUPPORTED;
+        if (c->law != TR_LAW_UNIFORM)
+            for (int k = 0; k < d.N; ++k)
+                if (!p->cdf[k]) return TR_E_ARG;
+    }
+    return TR_OK;
+}
+
+size_t tr_sweep_workspace_size(const tr_problem* p, const tr_sweep_config* c) {
+    if (check_sweep(p, c) != TR_OK) return 0;
+    return sweep_layout(p, c).total;
+}
+
+tr_status tr_sweep_run(const tr_problem* p, const tr_sweep_config* c, uint64_t* t_dev, int32_t sweeps,
+                       int32_t* dev_status, void* ws, size_t ws_bytes, tr_stream_t stream) {
+    tr_status s = check_sweep(p, c);
+    if (s != TR_OK) return s;
+    if (!t_dev || sweeps < 0) return TR_E_ARG;
+    const SweepRunWs SL = sweep_layout(p, c);
+    if (!ws || ws_bytes < SL.total) return TR_E_WORKSPACE;
+    if (!aligned(ws, 256)) return TR_E_ALIGN;
+    if (sweeps == 0) return TR_OK;
+    const RunWs& L = SL.r;
+    const tr_desc& d = p->desc;
+    const tr_config rc = sweep_as_config(p, c);
+    hipStream_t st = (hipStream_t)stream;
+    char* w = static_cast<char*>(ws);
+    int32_t* idx = reinterpret_cast<int32_t*>(w + L.idx);
+    double* pF = reinterpret_cast<double*>(w + L.pF);
+    void* S = w + L.S;
+    void* g = w + L.g;
+    double* gram = reinterpret_cast<double*>(w + L.gram);
+    double* lossw = reinterpret_cast<double*>(w + L.loss);
+    const bool full = sweep_full(c->method);
+    const bool jacobi = c->method == TR_METHOD_GD || c->method == TR_METHOD_SCALED_GD;
+    const bool refresh = !full && (c->law == TR_LAW_LEVERAGE || c->law == TR_LAW_EUCLID);
+    const size_t es = dtype_size(d.core_dtype);
+    Ptrs live{}, rd{};
+    MutPtrs mcores{}, acc{};
+    CdfPtrs cdf{};
+    XSrc xs{};
+    xs.X = p->X;
+    for (int k = 0; k < d.N; ++k) {
+        live.p[k] = p->cores[k];
+        mcores.p[k] = p->cores[k];
+        rd.p[k] = jacobi ? static_cast<const void*>(w + SL.snap_off[k]) : p->cores[k];
+        xs.rep[k] = p->Xrep[k];
+        if (refresh) cdf.p[k] = p->cdf[k];
+    }
+    hipError_t e = hipSuccess;
+    if (refresh)
+        for (int k = 0; k < d.N && e == hipSuccess; ++k)
+            e = launch_dist(d, ModeSrc{nullptr, 0, k, 0}, false, k, c->law, live, p->cdf, dev_status, w + L.dist, st);
+    for (int sw = 0; sw < sweeps && e == hipSuccess; ++sw) {
+        if (jacobi)   // the iterate every block of this sweep is computed from
+            for (int k = 0; k < d.N && e == hipSuccess; ++k)
+                e = hipMemcpyAsync(w + SL.snap_off[k], p->cores[k],
+                                   (size_t)d.I[k] * d.R[k] * d.R[ring_next(k, d.N)] * es, hipMemcpyDeviceToDevice, st);
+        for (int n = 0; n < d.N && e == hipSuccess; ++n) {
+            const ModeSrc ms{t_dev, 0, n, c->seed, nullptr, nullptr};
+            const int64_t Jn = J_of(d, n);
+            const int m = full ? (int)Jn : c->m;
+            e = launch_sample_subchain_mode(d, ms, m, cdf, nullptr, TR_STREAM_IDX, rd, idx, pF, S, full ? 2 : 1, true,
+                                            st);
+            if (e == hipSuccess) e = launch_grad_partial(d, ms, rd, xs, idx, S, pF, m, c->prec, w + L.grad, L.gl, st);
+            if (e != hipSuccess) break;
+            if (c->method == TR_METHOD_GD) {
+                // g = grad f / J_n over every column: G -= alpha grad f is the
+                // rule's fixed step alpha J_n along p = -g
+                tr_step rule{};
+                rule.kind = 0;
+                rule.alpha = c->alpha * (double)Jn;
+                e = launch_grad_reduce(d, ms, w + L.grad, L.gl, nullptr, lossw, true, mcores, acc, rule, dev_status,
+                                       st);
+            } else {
+                tr_step rule{};
+                rule.kind = 0;
+                rule.alpha = c->method == TR_METHOD_SCALED_GD ? c->alpha : 1.0;
+                e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, lossw, false, MutPtrs{}, MutPtrs{}, rule,
+                                       dev_status, st);
+                if (e == hipSuccess) e = launch_gram(d, ms, S, pF, m, gram, w + L.gramws, L.ml, st);
+                if (e == hipSuccess)
+                    e = launch_scaled_update(d, ms, gram, c->damping, g, mcores, acc, rule, dev_status, w + L.upd,
+                                             L.ul, st);
+            }
+            if (e == hipSuccess) e = launch_bump(t_dev, st);
+            if (e == hipSuccess && refresh)
+                e = launch_dist(d, ModeSrc{nullptr, 0, n, 0}, false, n, c->law, live, p->cdf, dev_status, w + L.dist,
+                                st);
+        }
+    }
+    (void)rc;
     return hip_status(e);
 }
 

@@ -26,6 +26,12 @@ hipError_t launch_sample_subchain(const tr_desc& d, ModeSrc ms, int m, CdfPtrs c
                                   const uint64_t* cdf_J, int stream_tag, Ptrs cores,
                                   int32_t* idx, double* pF, void* S, bool do_sample,
                                   bool do_subchain, hipStream_t st);
+// sample_mode 0: indices given in idx; 1: drawn; 2: every column of X_[n]
+// once (m = J_n, p = 1/J_n, column order of the cyclic unfolding).
+hipError_t launch_sample_subchain_mode(const tr_desc& d, ModeSrc ms, int m, CdfPtrs cdf,
+                                       const uint64_t* cdf_J, int stream_tag, Ptrs cores,
+                                       int32_t* idx, double* pF, void* S, int sample_mode,
+                                       bool do_subchain, hipStream_t st);
 
 // a5/a6: partial gradients and loss.  Layout of the workspace returned by
 // grad_ws_layout.

@@ -10,6 +10,8 @@ namespace trk {
 // A block takes SB samples.  Phase 1: one thread per (sample, mode) draws
 // the index (the optimal law: one thread per sample draws over J_n); the
 // probabilities are multiplied per sample in the order n+1, ..., n-1.
+// do_sample == 2 enumerates instead: sample f is column j = f of X_[n]
+// (every column once, m = J_n), decoded in the cyclic order, p = 1/J_n.
 // Phase 2: the N-1 core slices of every sample are copied to LDS in one
 // batch (a slice G_k(i) is row i of G_k(2): R_k R_{k+1} contiguous values).
 // Phase 3: the chain products M <- M G_k(i_k), the last product written
@@ -51,7 +53,21 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
     }
     int mr = 0;   // largest rank: stride of the product buffers
     for (int k = 0; k < N; ++k) mr = max(mr, d.R[k]);
-    if (do_sample) {
+    if (do_sample == 2) {
+        const int64_t J = J_of(d, n);
+        for (int fl = tid; fl < nb; fl += blockDim.x) {
+            int64_t j = f0 + fl;
+            sp[fl * kMaxOrder] = 1.0 / (double)J;
+            for (int q = 0; q < N - 1; ++q) {
+                const int k = (n + 1 + q) % N;
+                sidx[fl * kMaxOrder + k] = (int)(j % d.I[k]);
+                j /= d.I[k];
+            }
+            sidx[fl * kMaxOrder + n] = -1;
+            sok[fl] = 1;
+        }
+        __syncthreads();
+    } else if (do_sample) {
         if (cdf_J) {
             for (int fl = tid; fl < nb; fl += blockDim.x) {
                 const int64_t f = f0 + fl;
@@ -118,7 +134,7 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
         for (int fl = tid; fl < nb; fl += blockDim.x) {
             const int64_t f = f0 + fl;
             double p;
-            if (cdf_J) {
+            if (cdf_J || do_sample == 2) {
                 p = sp[fl * kMaxOrder];
             } else {
                 p = 1.0;
@@ -317,6 +333,14 @@ hipError_t launch_sample_subchain(const tr_desc& d, ModeSrc ms, int m, CdfPtrs c
                                   const uint64_t* cdf_J, int stream_tag, Ptrs cores,
                                   int32_t* idx, double* pF, void* S, bool do_sample,
                                   bool do_subchain, hipStream_t st) {
+    return launch_sample_subchain_mode(d, ms, m, cdf, cdf_J, stream_tag, cores, idx, pF, S, do_sample ? 1 : 0,
+                                       do_subchain, st);
+}
+
+hipError_t launch_sample_subchain_mode(const tr_desc& d, ModeSrc ms, int m, CdfPtrs cdf,
+                                       const uint64_t* cdf_J, int stream_tag, Ptrs cores,
+                                       int32_t* idx, double* pF, void* S, int sample_mode,
+                                       bool do_subchain, hipStream_t st) {
     if (m <= 0) return hipSuccess;
     const Shape sh = shape_of(d);
     const size_t es = d.core_dtype == TR_F64 ? 8 : 4;
@@ -325,11 +349,11 @@ hipError_t launch_sample_subchain(const tr_desc& d, ModeSrc ms, int m, CdfPtrs c
     const dim3 grid((unsigned)((m + SB - 1) / SB));
     if (d.core_dtype == TR_F64)
         hipLaunchKernelGGL(k_sample_subchain<double>, grid, dim3(256), lds, st, d, ms, m, SB, cdf, cdf_J,
-                           stream_tag, cores, idx, pF, static_cast<double*>(S), (int)do_sample,
+                           stream_tag, cores, idx, pF, static_cast<double*>(S), sample_mode,
                            (int)do_subchain);
     else
         hipLaunchKernelGGL(k_sample_subchain<float>, grid, dim3(256), lds, st, d, ms, m, SB, cdf, cdf_J,
-                           stream_tag, cores, idx, pF, static_cast<float*>(S), (int)do_sample,
+                           stream_tag, cores, idx, pF, static_cast<float*>(S), sample_mode,
                            (int)do_subchain);
     return hipGetLastError();
 }

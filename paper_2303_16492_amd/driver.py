@@ -118,6 +118,32 @@ class TRSolver:
         return int(self.t_dev.item())
 
 
+METHOD = {"gd": L.TR_METHOD_GD, "scaled-gd": L.TR_METHOD_SCALED_GD, "als": L.TR_METHOD_ALS,
+          "als-sampled": L.TR_METHOD_ALS_SAMPLED}
+
+
+class TRSweeper(TRSolver):
+    """The paper's comparison methods (TR-GD, TR-ScaledGD, TR-ALS,
+    TR-ALS-Sampled) on the same problem buffers, advanced by whole sweeps
+    through ``tr_sweep_run``."""
+
+    def __init__(self, cores, X, I, R, method="als", m=0, law="U", prec="f32", alpha=1.0, damping=0.0, seed=0,
+                 replicas=True):
+        super().__init__(cores, X, I, R, max(m, 1), law=law, scaled=False, prec=prec, seed=seed, replicas=replicas,
+                         overlap=False)
+        sc = L.tr_sweep_config()
+        sc.method, sc.m, sc.law, sc.prec = METHOD[method], m, LAW[law], PREC[prec]
+        sc.alpha, sc.damping, sc.seed = alpha, damping, seed
+        self.sweep_config = sc
+        need = api.tr_sweep_workspace_size(self.problem, sc)
+        if need == 0:
+            raise ValueError("invalid sweep configuration")
+        self.sweep_ws = api.workspace(need, X.device)
+
+    def sweep(self, sweeps: int = 1):
+        api.tr_sweep_run(self.problem, self.sweep_config, self.t_dev, sweeps, self.status, self.sweep_ws)
+
+
 class TRBatch:
     """Many independent problems advanced together by ``tr_batch_run``.
 
