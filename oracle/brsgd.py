@@ -47,7 +47,9 @@ class Config:
     eta: float = 1e-2          # AdaGrad eta
     b: float = 0.0
     eps: float = 0.0
-    damping: float = 0.0       # eta^t of the amended preconditioner (constant)
+    damping: float = 0.0       # eta^0 of the amended preconditioner
+    damping_schedule: str = "constant"   # constant | harmonic | geometric
+    damping_tau: float = 1.0   # harmonic: eta^t = eta^0 / (1 + t/tau); geometric: eta^t = eta^0 tau^t
     m_H: int | None = None     # None: H_n = F_n
     seed: int = 0
 
@@ -132,6 +134,18 @@ def scaled_direction(g: np.ndarray, h: np.ndarray):
     return np.zeros_like(g), DEV_NOT_SPD
 
 
+def damping_at(cfg: Config, t: int) -> float:
+    """eta^t of the amended preconditioner (the remark after
+    ``eq:scaledsg_direction``: a damping specific to iteration t, >= 0).
+    The paper fixes no schedule; besides a constant, a harmonic decay
+    eta^0 / (1 + t/tau) and a geometric decay eta^0 tau^t (0 < tau <= 1)."""
+    if cfg.damping_schedule == "harmonic":
+        return cfg.damping / (1.0 + t / cfg.damping_tau)
+    if cfg.damping_schedule == "geometric":
+        return cfg.damping * cfg.damping_tau ** t
+    return cfg.damping
+
+
 def update(Gn2: np.ndarray, p: np.ndarray, cfg: Config, t: int, accum: np.ndarray | None):
     """New G_{n(2)} (and AdaGrad accumulator) from the direction p."""
     if cfg.rule == "adagrad":
@@ -170,7 +184,7 @@ def step(state: State, X: np.ndarray, cfg: Config, n: int | None = None, trace: 
         else:
             idx_H, p_H = sampling.draw(cfg.seed, state.t, n, cfg.m_H, sizes, w_modes, w_J, STREAM_H)
             S_H = subchain_rows(cores, n, idx_H)
-        h = stoch_hessian(S_H, p_H, Jn, cfg.damping)
+        h = stoch_hessian(S_H, p_H, Jn, damping_at(cfg, state.t))
         p, st = scaled_direction(g, h)
         state.status |= st
     else:

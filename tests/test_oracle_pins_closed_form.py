@@ -157,3 +157,33 @@ def test_positive_definite_h_is_not_damped():
     p, st = brsgd.scaled_direction(g, h)
     assert st == 0
     assert np.allclose(p, -g / np.diag(h)[None, :], rtol=1e-15)
+
+
+# ------------------------------------------------------- damping schedule ----
+
+def test_damping_schedules_hand_values():
+    """eta^t of the amended preconditioner: harmonic eta^0 = 2, tau = 4 gives
+    2, 1.6, 1 at t = 0, 1, 4; geometric eta^0 = 8, tau = 1/2 gives 8, 4, 1 at
+    t = 0, 1, 3; constant stays at eta^0."""
+    c = brsgd.Config(m=1, damping=2.0, damping_schedule="harmonic", damping_tau=4.0)
+    assert [brsgd.damping_at(c, t) for t in (0, 1, 4)] == [2.0, 1.6, 1.0]
+    c = brsgd.Config(m=1, damping=8.0, damping_schedule="geometric", damping_tau=0.5)
+    assert [brsgd.damping_at(c, t) for t in (0, 1, 3)] == [8.0, 4.0, 1.0]
+    c = brsgd.Config(m=1, damping=0.3)
+    assert brsgd.damping_at(c, 10 ** 6) == 0.3
+
+
+def test_scheduled_step_equals_constant_damping_at_that_step():
+    """A scaled step at t = 3 under the geometric schedule (eta^0 = 8,
+    tau = 1/2) is the step under the constant damping 1 at the same t (the
+    schedule only picks eta^t)."""
+    cores = ti.gaussian_cores(5, 3, [6, 5, 7], [2, 3, 2])
+    X = tr.full_tensor(ti.gaussian_cores(6, 3, [6, 5, 7], [2, 3, 2]))
+    outs = []
+    for cfg in (brsgd.Config(m=40, variant="scaled", alpha=0.5, damping=8.0, damping_schedule="geometric",
+                             damping_tau=0.5, seed=2),
+                brsgd.Config(m=40, variant="scaled", alpha=0.5, damping=1.0, seed=2)):
+        st = brsgd.State([c.copy() for c in cores], t=3)
+        n = brsgd.step(st, X, cfg)
+        outs.append(st.cores[n])
+    assert np.array_equal(outs[0], outs[1])
