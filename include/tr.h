@@ -62,7 +62,7 @@ extern "C" {
 
 typedef struct ihipStream_t* tr_stream_t;   /* a hipStream_t */
 
-#define TR_ABI_VERSION 1
+#define TR_ABI_VERSION 2
 #define TR_MAX_ORDER 8
 #define TR_MAX_RANK 16
 
@@ -281,9 +281,14 @@ typedef struct {
     int32_t law;        /* tr_law                                            */
     int32_t scaled;     /* 0: TR-BRSGD, 1: TR-ScaledBRSGD                    */
     int32_t prec;       /* tr_prec                                           */
-    double damping;     /* constant eta^t of the amended preconditioner      */
+    double damping;     /* eta^0 of the amended preconditioner h + eta^t I   */
     tr_step rule;
     uint64_t seed;
+    /* eta^t at step t (the remark after eq:scaledsg_direction asks only for
+     * eta^t >= 0): 0 constant eta^0; 1 harmonic eta^0 / (1 + t/damping_tau),
+     * damping_tau > 0; 2 geometric eta^0 damping_tau^t, 0 < damping_tau <= 1. */
+    int32_t damping_schedule;
+    double damping_tau;
 } tr_config;
 
 /* Enqueue ``steps`` iterations.  The step counter lives in device memory:

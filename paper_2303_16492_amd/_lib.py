@@ -71,6 +71,8 @@ class tr_config(C.Structure):
         ("damping", C.c_double),
         ("rule", tr_step),
         ("seed", C.c_uint64),
+        ("damping_schedule", C.c_int32),
+        ("damping_tau", C.c_double),
     ]
 
 

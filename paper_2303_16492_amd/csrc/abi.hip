@@ -440,6 +440,9 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
     if (c->rule.kind < 0 || c->rule.kind > 2) return TR_E_ARG;
     if (c->rule.kind == 2 && !(c->rule.tau > 0.0)) return TR_E_ARG;
     if (!(c->damping >= 0.0)) return TR_E_ARG;
+    if (c->damping_schedule < 0 || c->damping_schedule > 2) return TR_E_ARG;
+    if (c->damping_schedule == 1 && !(c->damping_tau > 0.0)) return TR_E_ARG;
+    if (c->damping_schedule == 2 && !(c->damping_tau > 0.0 && c->damping_tau <= 1.0)) return TR_E_ARG;
     if (c->rule.kind == 1)
         for (int k = 0; k < d.N; ++k)
             if (!p->accum[k]) return TR_E_ARG;
@@ -495,10 +498,13 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
     // The step's first kernel draws its mode from (seed, t) and publishes it;
     // the later kernels of the step read it instead of drawing it again.
     int32_t* nslot = reinterpret_cast<int32_t*>(w + L.mode);
+    const bool sched = c->damping_schedule != 0;
+    const Damp damp(c->damping, c->damping_tau, c->damping_schedule);
     for (int it = 0; it < steps && e == hipSuccess; ++it) {
         const ModeSrc ms_draw{t_dev, 0, -1, c->seed, nullptr, nslot};
         const ModeSrc ms{t_dev, 0, -2, c->seed, nslot, nullptr};
-        const ModeSrc ms_shape = same_shape ? ModeSrc{nullptr, 0, 0, c->seed} : ms;
+        // a damping schedule needs t: then the shape-only kernels read it too
+        const ModeSrc ms_shape = same_shape ? ModeSrc{sched ? t_dev : nullptr, 0, 0, c->seed} : ms;
         double* loss = loss_out ? loss_out + it : lossw;
         if (c->law == TR_LAW_OPTIMAL)
             e = launch_dist_optimal(d, ms_draw, cores, xs_paper, p->cdf_J, dev_status, w + L.opt, st);
@@ -536,7 +542,7 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
             if (e == hipSuccess && o.ev_inv_begin && o.ev_inv_begin[it])
                 e = hipEventRecord((hipEvent_t)o.ev_inv_begin[it], hs);
             if (e == hipSuccess)
-                e = launch_sweep_inverse(d, ms_shape, gram, c->damping, L.ul, w + L.upd, dev_status, hs);
+                e = launch_sweep_inverse(d, ms_shape, gram, damp, L.ul, w + L.upd, dev_status, hs);
             if (e == hipSuccess && o.ev_inv_end && o.ev_inv_end[it]) e = hipEventRecord((hipEvent_t)o.ev_inv_end[it], hs);
             if (e == hipSuccess && fork) e = hipEventRecord((hipEvent_t)o.ev_join, hs);
             if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, (hipEvent_t)o.ev_gram, 0);
@@ -574,7 +580,7 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                     }
                 }
                 if (e == hipSuccess)
-                    e = launch_scaled_update(d, ms, gram, c->damping, g, mcores, acc, c->rule, dev_status, w + L.upd,
+                    e = launch_scaled_update(d, ms, gram, damp, g, mcores, acc, c->rule, dev_status, w + L.upd,
                                              L.ul, st);
                 if (e == hipSuccess && fused.t) e = launch_bump(t_dev, st);
             } else {

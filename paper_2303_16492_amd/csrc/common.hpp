@@ -88,6 +88,22 @@ struct ModeSrc {
     int32_t* n_pub;          // n == -1: where the step's first kernel publishes the mode it drew
 };
 
+// Damping eta^t of the amended preconditioner h + eta^t I (the remark after
+// eq:scaledsg_direction): kind 0 constant eta0, 1 harmonic eta0 / (1 + t/tau),
+// 2 geometric eta0 tau^t.  A plain double converts to the constant kind.
+struct Damp {
+    double eta0 = 0.0, tau = 1.0;
+    int32_t kind = 0;
+    Damp() = default;
+    __host__ __device__ Damp(double e) : eta0(e) {}
+    __host__ __device__ Damp(double e, double ta, int32_t k) : eta0(e), tau(ta), kind(k) {}
+    __host__ __device__ double at(uint64_t t) const {
+        if (kind == 1) return eta0 / (1.0 + (double)t / tau);
+        if (kind == 2) return eta0 * pow(tau, (double)t);
+        return eta0;
+    }
+};
+
 // The two loads (step counter, published mode) are independent, so a
 // kernel that needs both waits for one memory round trip.
 __device__ inline void resolve_mode(const ModeSrc& ms, int N, uint64_t* t, int* n) {

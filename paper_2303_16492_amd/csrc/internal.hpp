@@ -127,17 +127,17 @@ struct UpdWs {
     size_t L_off, dinv_off, flag_off, total;
 };
 UpdWs upd_ws_layout(const tr_desc& d);
-hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping,
+hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, Damp damping,
                                 const void* g, MutPtrs cores, MutPtrs accum, tr_step rule,
                                 int32_t* status, void* ws, const UpdWs& L, hipStream_t st);
 // The same for RR <= 128 through the blocked sweep (g already reduced).
 bool sweep_supported(const tr_desc& d);
-hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* g,
+hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, Damp damping, const void* g,
                                double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status, void* ws,
                                const UpdWs& L, StepBump step, hipStream_t st);
 // The two halves: -(gram + damping I)^{-1} (one workgroup) and the
 // row-parallel p = g (-M^{-1}) with the rule.
-hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const UpdWs& L,
+hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, Damp damping, const UpdWs& L,
                                 void* ws, int32_t* status, hipStream_t st, double rank_tol = 0.0);
 hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossParts lp, double* loss, MutPtrs cores,
                               MutPtrs accum, tr_step rule, int32_t* status, void* ws, const UpdWs& L, StepBump step,

@@ -274,9 +274,11 @@ __device__ __forceinline__ void fill_tiles(dbl4 (&acc)[tpw<NT>()], const double*
     }
 }
 
-// -M^{-1} into hm (both triangles), with the deferred -2 on the diagonal.
+// -M^{-1} into hm (both triangles), with the deferred -2 on the diagonal,
+// scaled back by sc (the sweep ran on sc M).
 template <int NT, int WV>
-__device__ __forceinline__ void store_tiles(const dbl4 (&acc)[tpw<NT>()], double* __restrict__ hm, int RR) {
+__device__ __forceinline__ void store_tiles(const dbl4 (&acc)[tpw<NT>()], double* __restrict__ hm, int RR,
+                                            double sc) {
     const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
 #pragma unroll
     for (int k = 0; k < tpw<NT>(); ++k) {
@@ -286,8 +288,8 @@ __device__ __forceinline__ void store_tiles(const dbl4 (&acc)[tpw<NT>()], double
         for (int j = 0; j < 4; ++j) {
             const int r = 16 * rt + 4 * j + lr, c = 16 * ct + lc;
             if (r < RR && c < RR) {
-                hm[(int64_t)r * RR + c] = acc[k][j] - (r == c ? 2.0 : 0.0);
-                if (rt != ct) hm[(int64_t)c * RR + r] = acc[k][j];
+                hm[(int64_t)r * RR + c] = (acc[k][j] - (r == c ? 2.0 : 0.0)) * sc;
+                if (rt != ct) hm[(int64_t)c * RR + r] = acc[k][j] * sc;
             }
         }
     }
@@ -345,21 +347,21 @@ __device__ __forceinline__ bool sweep_step(dbl4 (&acc)[tpw<NT>()], SweepShared& 
 // and reads the same verdicts, so every wavefront returns the same value.
 // rank_tol > 0: a rank test instead of the ladder; one attempt, and a pivot
 // not above rank_tol * max_i h_ii fails it.
+//
+// The sweep runs on sc (h + eta I) with sc the power of two that puts the
+// largest diagonal entry in [0.5, 1) (exact), and the inverse is scaled back
+// by sc when stored: the pivot block of every step is held as 2 I - B until
+// the deferred -2 I, which keeps B's digits only while B is not far below
+// 1, i.e. while the matrix is not far above 1.
 template <int NT, int WV>
 __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int RR, double damping, double rank_tol,
                                           double* __restrict__ hm, SweepShared& sh) {
     const int npiv = (RR + 7) >> 3;
+    const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
     dbl4 acc[tpw<NT>()];
     double base = 0.0;   // tr(h + damping I) / RR, needed only once a factorisation has failed
     double tol = 0.0;
-    if (rank_tol > 0.0) {
-        double mx = 0.0;
-        for (int c = threadIdx.x; c < RR; c += blockDim.x) mx = fmax(mx, gram[(int64_t)c * RR + c]);
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = mx;
-        __syncthreads();
-        tol = rank_tol * fmax(fmax(sh.red[0], sh.red[1]), fmax(sh.red[2], sh.red[3]));
-    }
+    double sc = 1.0;
     const int attempts = rank_tol > 0.0 ? 1 : 8;
     for (int attempt = 0; attempt < attempts; ++attempt) {
         if (attempt == 1) {
@@ -369,16 +371,49 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
         }
         const double eta = attempt == 0 ? damping : damping + pow(10.0, (double)(attempt - 1 - 10)) * base;
         __syncthreads();   // the previous attempt's readers are done with the shared buffers
+        double xb[2];      // factor wavefront: entry (u, v) of pivot blocks 0 and 1 of h + eta I
         if (WV == kFactorWave) {
-            // pivot blocks 0 and 1 of h + eta I straight from memory
-            const int l = threadIdx.x & 63;
             const int u = l >> 3, v = l & 7;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int r = 8 * b + u, c = 8 * b + v;
                 const int rc = r < RR ? r : RR - 1, cc = c < RR ? c : RR - 1;
                 const double gv = gram[(int64_t)rc * RR + cc];
-                const double x = (r < RR && c < RR ? gv : 0.0) + (r == c ? (r < RR ? eta : 1.0) : 0.0);
+                xb[b] = (r < RR && c < RR ? gv : 0.0) + (r == c ? (r < RR ? eta : 1.0) : 0.0);
+            }
+        } else {
+            fill_tiles<NT, WV>(acc, gram, RR, eta);
+        }
+        if (attempt == 0) {   // largest diagonal entry, from the update wavefronts' diagonal tiles
+            double mx = 0.0;
+            if (WV != kFactorWave) {
+#pragma unroll
+                for (int k = 0; k < tpw<NT>(); ++k) {
+                    if (!s_ok<NT>(WV, k) || s_rt<NT>(WV, k) != s_ct<NT>(WV, k)) continue;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int r = 16 * s_rt<NT>(WV, k) + 4 * j + lr, c = 16 * s_ct<NT>(WV, k) + lc;
+                        if (r == c && r < RR) mx = fmax(mx, acc[k][j]);
+                    }
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+            if (l == 0) sh.red[WV] = mx;
+            __syncthreads();
+            const double mxa = fmax(fmax(sh.red[0], sh.red[1]), fmax(sh.red[2], sh.red[3]));
+            int ex = 0;
+            if (mxa > 0.0 && isfinite(mxa)) {
+                (void)frexp(mxa, &ex);
+                sc = ldexp(1.0, -ex);
+            }
+            if (rank_tol > 0.0) tol = rank_tol * mxa * sc;
+        }
+        if (WV == kFactorWave) {
+            const int u = l >> 3, v = l & 7;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int r = 8 * b + u, c = 8 * b + v;
+                const double x = (r < RR && c < RR) ? xb[b] * sc : xb[b];
                 if (b == 0) sh.Dn[u * 8 + v] = x;
                 else sh.D8[1][u * 8 + v] = x;
             }
@@ -388,9 +423,17 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const bool g = sweep8(sh.Dn, sh.Bw[0], tol);
-            if ((threadIdx.x & 63) == 0) sh.good[0] = g ? 1 : 0;
+            if (l == 0) sh.good[0] = g ? 1 : 0;
         } else {
-            fill_tiles<NT, WV>(acc, gram, RR, eta);
+#pragma unroll
+            for (int k = 0; k < tpw<NT>(); ++k) {
+                const int rt = s_rt<NT>(WV, k), ct = s_ct<NT>(WV, k);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = 16 * rt + 4 * j + lr, c = 16 * ct + lc;
+                    acc[k][j] = (r < RR && c < RR) ? acc[k][j] * sc : acc[k][j];
+                }
+            }
             publish_rows<NT, WV, 0>(acc, 0, sh.Vt[0]);
         }
         __syncthreads();
@@ -401,7 +444,7 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
             if (good && q + 1 < npiv) good = sweep_step<NT, WV, 1>(acc, sh, q + 1, npiv, tol);
         }
         if (good) {
-            if (WV != kFactorWave) store_tiles<NT, WV>(acc, hm, RR);
+            if (WV != kFactorWave) store_tiles<NT, WV>(acc, hm, RR, sc);
             return attempt;
         }
     }
@@ -414,11 +457,12 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
 // rank_tol * max_i gram_ii, i.e. the Gram is taken as singular.  256 threads.
 template <int NT>
 __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const double* __restrict__ gram,
-                                               double damping, double rank_tol, double* __restrict__ hm,
+                                               Damp dmp, double rank_tol, double* __restrict__ hm,
                                                int* __restrict__ flag, int32_t* status) {
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    const double damping = dmp.at(t);
     const int RR = d.R[n] * d.R[ring_next(n, d.N)];
     __shared__ SweepShared sh;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -535,7 +579,7 @@ __global__ __launch_bounds__(64) void k_scaled_apply(tr_desc d, ModeSrc ms, cons
 
 bool sweep_supported(const tr_desc& d) { return shape_of(d).maxRR <= 128; }
 
-hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const UpdWs& L,
+hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram, Damp damping, const UpdWs& L,
                                 void* ws, int32_t* status, hipStream_t st, double rank_tol) {
     const Shape sh = shape_of(d);
     if (sh.maxRR > 128) return hipErrorInvalidValue;
@@ -595,7 +639,7 @@ hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossP
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* g,
+hipError_t launch_sweep_update(const tr_desc& d, ModeSrc ms, const double* gram, Damp damping, const void* g,
                                double* loss, MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status, void* ws,
                                const UpdWs& L, StepBump step, hipStream_t st) {
     hipError_t e = launch_sweep_inverse(d, ms, gram, damping, L, ws, status, st);

@@ -145,12 +145,13 @@ __device__ inline int chol_blocked(double* A, double* dinv, int RR, int P) {
 // far slower than LDS instructions.
 template <bool USE_LDS>
 __global__ __launch_bounds__(256) void k_chol(tr_desc d, ModeSrc ms, const double* __restrict__ gram,
-                                              double damping, double* __restrict__ Lout,
+                                              Damp dmp, double* __restrict__ Lout,
                                               double* __restrict__ dinv_out, int* __restrict__ flag,
                                               int32_t* status) {
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    const double damping = dmp.at(t);
     const int RR = d.R[n] * d.R[ring_next(n, d.N)];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int P = USE_LDS ? RR + 1 : RR;
@@ -343,7 +344,7 @@ UpdWs upd_ws_layout(const tr_desc& d) {
     return L;
 }
 
-hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, double damping, const void* g,
+hipError_t launch_scaled_update(const tr_desc& d, ModeSrc ms, const double* gram, Damp damping, const void* g,
                                 MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status, void* ws,
                                 const UpdWs& L, hipStream_t st) {
     if (sweep_supported(d))

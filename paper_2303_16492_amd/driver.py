@@ -42,8 +42,11 @@ def cores_to_host(cores2, R):
 
 
 class TRSolver:
+    SCHEDULE = {"constant": 0, "harmonic": 1, "geometric": 2}
+
     def __init__(self, cores, X, I, R, m, law="U", scaled=False, prec="f32", rule=None,
-                 damping=0.0, m_H=0, seed=0, replicas=True, overlap=True):
+                 damping=0.0, m_H=0, seed=0, replicas=True, overlap=True, damping_schedule="constant",
+                 damping_tau=1.0):
         self.I, self.R = list(I), list(R)
         self.N = len(I)
         self.cores = cores
@@ -76,6 +79,7 @@ class TRSolver:
         c = L.tr_config()
         c.m, c.m_H, c.law, c.scaled, c.prec = m, m_H, LAW[law], int(scaled), PREC[prec]
         c.damping, c.rule, c.seed = float(damping), self.rule, seed
+        c.damping_schedule, c.damping_tau = self.SCHEDULE[damping_schedule], float(damping_tau)
         self.config = c
         self.ws = api.workspace(api.tr_run_workspace_size(p, c), dev)
         self.rse_ws = None

@@ -64,7 +64,7 @@ def test_host_mode_pick_equals_oracle():
 def test_abi_version_and_status_strings():
     from paper_2303_16492_amd import _lib
     h = _lib.lib()
-    assert h.tr_abi_version() == 1
+    assert h.tr_abi_version() == 2
     for s in (0, -1, -2, -3, -4, -5, -6, -7, -99):
         assert len(h.tr_status_str(s)) > 0
 

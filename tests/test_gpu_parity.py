@@ -206,6 +206,33 @@ def test_adagrad_update_with_b_and_eps(dtype, b, eps):
     assert int(st) == 0
 
 
+@pytest.mark.parametrize("scale", [1e-8, 1e4, 1e8])
+@pytest.mark.parametrize("R", [[3, 4, 3], [12, 12, 12]])
+def test_scaled_update_scale_invariant(scale, R):
+    """p = -g (h + eta I)^{-1} does not change when h, eta and g are all
+    multiplied by the same factor: the inverse (sweep route, and the
+    Cholesky route at R_n R_{n+1} = 144) keeps its digits whether the
+    Hessian's entries are far below or far above 1 (FP64, against the
+    oracle's Cholesky on the scaled inputs)."""
+    dtype = torch.float64
+    I = [40, 30, 35] if R[0] == 3 else [20, 16, 18]
+    I, R, cores, X, dcores, dX = problem(5, 3, I, R, dtype)
+    desc = api.make_desc(I, R, dtype)
+    n, m = 1, 400
+    idx, pF = api.tr_sample(desc, 6, 0, n, m)
+    S = api.tr_subchain(desc, n, dcores, idx, m)
+    g, _, gram = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, L.TR_PREC_F64, want_gram=True)
+    eta = 0.2 * float(torch.diagonal(gram).mean())
+    core = dcores[n].clone()
+    say("scaled update at scale", scale, R)
+    st = api.tr_update(desc, n, core, g * scale, gram=gram * scale, damping=eta * scale,
+                       rule=api.step_rule("fixed", alpha=1.0), t=0)
+    h = gram.cpu().numpy() * scale + eta * scale * np.eye(gram.shape[0])
+    p, _ = brsgd.scaled_direction(g.cpu().numpy() * scale, h)
+    assert int(st) == 0
+    assert rel(core.cpu().numpy() - unfold(cores[n]), p) < 1e-15 * np.linalg.cond(h) + 1e-13
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("damping", [0.0, 0.3])
 def test_scaled_update_parity(dtype, damping):

@@ -315,3 +315,54 @@ def test_benchmarked_configuration_full_size(prec):
             if k != n:
                 assert np.array_equal(sol.cores[k].double().cpu().numpy(), unfold(before[k]))
     assert int(sol.status.item()) == 0
+
+
+@pytest.mark.parametrize("schedule,eta0,tau", [("harmonic", 0.4, 3.0), ("geometric", 0.8, 0.7)])
+@pytest.mark.parametrize("I,R", [([30, 25, 28], [3, 3, 3]), ([20, 20, 20], [3, 3, 3]), ([14, 13, 15], [12, 12, 12])])
+def test_damping_schedule_run_fp64(schedule, eta0, tau, I, R):
+    """Scaled runs with an iteration-specific damping eta^t (amended
+    preconditioner): 12 FP64 steps against the oracle on the sweep route with
+    unequal and equal mode shapes (the shape-only kernels then read t for
+    eta^t) and on the Cholesky route (R_n R_{n+1} = 144)."""
+    dtype = torch.float64
+    X, _, init = planted(3, I, R, dtype, seed=2, noise_db=40.0)
+    dX = to_dev(flat_paper(X), dtype)
+    sol = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, I, R, 300, scaled=True, prec="f64",
+                   rule=api.step_rule("fixed", alpha=0.6), damping=eta0, damping_schedule=schedule,
+                   damping_tau=tau, seed=2)
+    g = sol.capture(5)             # one eager step, then a 5-step graph
+    g.replay()
+    g.replay()
+    torch.cuda.synchronize()
+    assert sol.t == 11
+    st = brsgd.State(init)
+    cfg = brsgd.Config(m=300, variant="scaled", alpha=0.6, damping=eta0, damping_schedule=schedule,
+                       damping_tau=tau, seed=2)
+    for _ in range(11):
+        brsgd.step(st, X, cfg)
+    for k in range(3):
+        e = rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k]))
+        say("schedule", schedule, I, R, k, e)
+        assert e < 1e-10, (k, e)
+
+
+def test_large_damping_interpolates_to_the_plain_step():
+    """eta^t -> infinity turns the scaled step into the plain one: with
+    eta = 1e8 and alpha = eta alpha_0 the scaled GPU run follows the plain
+    GPU run with alpha_0 (the limit named in the amended preconditioner's
+    remark)."""
+    dtype = torch.float64
+    I, R = [30, 25, 28], [3, 3, 3]
+    X, _, init = planted(3, I, R, dtype, seed=4, noise_db=40.0)
+    dX = to_dev(flat_paper(X), dtype)
+    eta, a0 = 1e8, 0.05
+    runs = []
+    for scaled in (True, False):
+        s = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, I, R, 200, scaled=scaled, prec="f64",
+                     rule=api.step_rule("fixed", alpha=eta * a0 if scaled else a0), damping=eta if scaled else 0.0,
+                     seed=4)
+        s.run(8)
+        torch.cuda.synchronize()
+        runs.append([c.cpu().numpy() for c in s.cores])
+    for a, b in zip(*runs):
+        assert rel(a, b) < 1e-6
