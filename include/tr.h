@@ -420,8 +420,9 @@ tr_status tr_entry_fwd(const tr_desc* d, const void* const* cores, const int32_t
                        const void* x, int32_t B, float* resid, double* loss,
                        void* ws, size_t ws_bytes, tr_stream_t stream);
 /* grads[k] (host array of N device pointers, G_{k(2)} layout, FP32) =
- * scale * (*scale_dev) * sum_b resid_b * dTrace/dG_k at i^b, i.e. the
- * block gradient of eq:gradient restricted to the sampled entries
+ * scale * (*scale_dev) * dL/dG_k = scale * (*scale_dev) * (1/B) *
+ * sum_b resid_b * dTrace/dG_k at i^b, i.e. the block gradient of
+ * eq:gradient restricted to the sampled entries
  * (dTrace/dG_k(i_k) is the transposed product of the other N-1 slices in
  * ring order, recomputed per entry from the cores, not stored).
  * scale_dev: device float64 multiplier (an upstream gradient) or NULL.
@@ -430,6 +431,36 @@ tr_status tr_entry_bwd(const tr_desc* d, const void* const* cores, const int32_t
                        const float* resid, int32_t B, double scale, const double* scale_dev,
                        void* const* grads, void* ws, size_t ws_bytes, tr_stream_t stream);
 size_t tr_entry_workspace_size(const tr_desc* d, int32_t B);
+
+/* Tensor completion in the ring format with a ridge regulariser (uses of
+ * the framework named in the concluding remarks): minimise over the cores
+ *     1/(2|Omega|) sum_{i in Omega} (TR(G)(i) - x_i)^2 + lambda/2 sum_k ||G_k||^2
+ * from the observed entries Omega alone.  Each step draws B observed
+ * entries uniformly with replacement (position floor(r |Omega| / 2^64) of
+ * Omega, r the Philox word of counter (t, b, 0, TR_STREAM_ENTRY)), evaluates
+ * the batch loss L = 1/(2B) sum_b r_b^2 + lambda/2 sum_k ||G_k||^2 and its
+ * gradient (tr_entry_fwd / tr_entry_bwd's kernels: the block gradient of
+ * eq:gradient restricted to the drawn entries, plus lambda G_k), and applies
+ * p_k = -dL/dG_k with ``rule`` to every core, or with block = 1 to core n
+ * only, n the step's mode (the block choice of Algorithm TR-BRSGD).
+ * obs_idx: int32 [n_obs][N]; obs_x: [n_obs] in the x dtype (F32 or F16);
+ * cores FP32 in place; accum: per-core AdaGrad accumulators (rule kind 1),
+ * else may be NULL; loss_out: device float64 [steps] (each step's L before
+ * its update) or NULL.  An observed index outside the tensor, when drawn,
+ * gives a NaN residual and loss for that step and no gradient contribution.
+ * *t_dev advances by one per step.  Graph-capturable. */
+typedef struct {
+    int32_t B;          /* observed entries drawn per step                    */
+    int32_t block;      /* 1: only the step's mode moves; 0: every core       */
+    double lambda;      /* ridge weight (>= 0)                                */
+    tr_step rule;
+    uint64_t seed;
+} tr_completion_config;
+size_t tr_completion_workspace_size(const tr_desc* d, const tr_completion_config* c);
+tr_status tr_completion_run(const tr_desc* d, void* const* cores, void* const* accum, const int32_t* obs_idx,
+                            const void* obs_x, int64_t n_obs, const tr_completion_config* c, uint64_t* t_dev,
+                            int32_t steps, double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                            tr_stream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* a11: many independent problems in one persistent launch             */

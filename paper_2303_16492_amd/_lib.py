@@ -91,6 +91,16 @@ class tr_sweep_config(C.Structure):
     ]
 
 
+class tr_completion_config(C.Structure):
+    _fields_ = [
+        ("B", C.c_int32),
+        ("block", C.c_int32),
+        ("lam", C.c_double),
+        ("rule", tr_step),
+        ("seed", C.c_uint64),
+    ]
+
+
 VP = C.c_void_p
 PVP = C.POINTER(C.c_void_p)
 
@@ -155,6 +165,9 @@ _SIGS = {
                              C.POINTER(tr_run_opts)]),
     "tr_run_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_config)]),
     "tr_sweep_workspace_size": (SZ, [C.POINTER(tr_problem), C.POINTER(tr_sweep_config)]),
+    "tr_completion_workspace_size": (SZ, [PDESC, C.POINTER(tr_completion_config)]),
+    "tr_completion_run": (I32, [PDESC, PVP, PVP, VP, VP, C.c_int64, C.POINTER(tr_completion_config), VP, I32, VP,
+                                VP, VP, SZ, VP]),
     "tr_sweep_run": (I32, [C.POINTER(tr_problem), C.POINTER(tr_sweep_config), VP, I32, VP, VP, SZ, VP]),
     "tr_batch_table_size": (SZ, [I32]),
     "tr_batch_upload": (I32, [C.POINTER(tr_batch_item), I32, VP, SZ, VP]),

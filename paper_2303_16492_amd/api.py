@@ -227,6 +227,30 @@ def tr_sweep_workspace_size(problem, config) -> int:
     return lib().tr_sweep_workspace_size(C.byref(problem), C.byref(config))
 
 
+def completion_config(B, block=False, lam=0.0, rule=None, seed=0) -> L.tr_completion_config:
+    c = L.tr_completion_config()
+    c.B, c.block, c.lam = int(B), int(bool(block)), float(lam)
+    c.rule = rule if rule is not None else step_rule()
+    c.seed = seed
+    return c
+
+
+def tr_completion_run(desc, cores, accum, obs_idx, obs_x, config, t_dev, steps, loss_out=None, status=None,
+                      ws=None):
+    dev = obs_idx.device
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    need = lib().tr_completion_workspace_size(C.byref(desc), C.byref(config))
+    if ws is None:
+        ws = workspace(need, dev)
+    acc = C.cast(_parr(accum), L.PVP) if accum is not None else None
+    check("tr_completion_run", lib().tr_completion_run(C.byref(desc), C.cast(_parr(cores), L.PVP), acc,
+                                                       _p(obs_idx), _p(obs_x), int(obs_x.numel()), C.byref(config),
+                                                       _p(t_dev), steps, _p(loss_out), _p(status), _p(ws),
+                                                       ws.numel(), _stream()))
+    return status
+
+
 def tr_run_workspace_size(problem, config) -> int:
     return lib().tr_run_workspace_size(C.byref(problem), C.byref(config))
 

@@ -27,7 +27,7 @@ class TRContract(torch.autograd.Function):
         idx, resid, *cores = ctx.saved_tensors
         B = idx.shape[0]
         g = gloss.detach().to(torch.float64).contiguous()
-        grads = api.tr_entry_bwd(ctx.desc, cores, idx, resid, B, scale=1.0 / B, scale_dev=g)
+        grads = api.tr_entry_bwd(ctx.desc, cores, idx, resid, B, scale_dev=g)
         return (None, None, None, *grads)
 
 

@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kEntBlock) void k_entry_bwd_acc(tr_desc d, Ptrs cor
     float* sres = reinterpret_cast<float*>(sidx + SB * N);            // [SB]
     float* G = gpart + (int64_t)blockIdx.x * slice_len;
     for (int64_t e = threadIdx.x; e < slice_len; e += blockDim.x) G[e] = 0.f;
-    const float sc = scale * (dscale ? (float)*dscale : 1.f);
+    // dL/dG_k of L = 1/(2B) sum r^2: the 1/B of the mean applied here
+    const float sc = (float)((double)scale * (dscale ? *dscale : 1.0) / (double)B);
     const int64_t b0 = (int64_t)blockIdx.x * EPB;
     const int64_t b1 = min((int64_t)B, b0 + EPB);
     for (int64_t bs = b0; bs < b1; bs += SB) {
@@ -223,6 +224,93 @@ static EntryPlan entry_plan(const tr_desc& d, int B) {
     return P;
 }
 
+// ------------------------------------------------------------ completion --
+//
+// Tensor completion with a ridge term on the sampled-entry loss: per step,
+// B observed entries drawn uniformly with replacement (position
+// floor(r |Omega| / 2^64), r from Philox counter (t, b, 0, TR_STREAM_ENTRY)),
+// the forward and backward above, then G_k <- rule(G_k, p) with
+// p = -(dL/dG_k + lambda G_k) for every core, or for core n = the step's
+// mode only.
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_completion_draw(tr_desc d, const uint64_t* __restrict__ t_dev,
+                                                         uint64_t seed, const int32_t* __restrict__ obs_idx,
+                                                         const TX* __restrict__ obs_x, int64_t n_obs, int B,
+                                                         int32_t* __restrict__ bidx, TX* __restrict__ bx) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const uint64_t t = *t_dev;
+    const int64_t j = (int64_t)mulhi64(draw_word(seed, t, (uint64_t)b, 0, TR_STREAM_ENTRY), (uint64_t)n_obs);
+    for (int k = 0; k < d.N; ++k) bidx[(int64_t)b * d.N + k] = obs_idx[j * d.N + k];
+    bx[b] = obs_x[j];
+}
+
+// loss = 1/(2B) sum r^2 (the forward's block partials, in block order) +
+// lambda/2 sum_k ||G_k||^2 (strided per thread, then the block tree).
+__global__ __launch_bounds__(256) void k_completion_loss(tr_desc d, const double* __restrict__ part, int nb, int B,
+                                                         Ptrs cores, double lam, double* __restrict__ loss) {
+    __shared__ double red[4];
+    double s = 0.0;
+    if (lam != 0.0)
+        for (int k = 0; k < d.N; ++k) {
+            const float* G = static_cast<const float*>(cores.p[k]);
+            const int64_t len = (int64_t)d.I[k] * d.R[k] * d.R[ring_next(k, d.N)];
+            for (int64_t e = threadIdx.x; e < len; e += blockDim.x) s += (double)G[e] * (double)G[e];
+        }
+    const double ridge = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        double data = 0.0;
+        for (int q = 0; q < nb; ++q) data += part[q];
+        *loss = data / (2.0 * (double)B) + 0.5 * lam * ridge;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_completion_update(tr_desc d, const uint64_t* __restrict__ t_dev,
+                                                           uint64_t seed, int block, MutPtrs cores, MutPtrs accum,
+                                                           const float* __restrict__ grads, int64_t slice_len,
+                                                           double lam, tr_step rule, int32_t* status) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= slice_len) return;
+    const uint64_t t = *t_dev;
+    int k = 0;
+    int64_t base = 0;
+    for (; k < d.N; ++k) {
+        const int64_t len = (int64_t)d.I[k] * d.R[k] * d.R[ring_next(k, d.N)];
+        if (e < base + len) break;
+        base += len;
+    }
+    if (block && k != pick_mode(seed, t, d.N)) return;
+    float* G = static_cast<float*>(cores.p[k]);
+    float* A = static_cast<float*>(accum.p[k]);
+    const int64_t o = e - base;
+    const double p = -((double)grads[e] + lam * (double)G[o]);
+    apply_rule(G, A, o, p, rule, t, status);
+}
+
+struct CompletionWs {
+    EntryPlan P;
+    size_t bidx, bx, resid, grads, loss, total;
+};
+
+static CompletionWs completion_layout(const tr_desc& d, int B) {
+    CompletionWs L{};
+    L.P = entry_plan(d, B);
+    size_t o = align_up(L.P.total);
+    L.bidx = o;
+    o += align_up((size_t)B * d.N * 4);
+    L.bx = o;
+    o += align_up((size_t)B * 4);
+    L.resid = o;
+    o += align_up((size_t)B * 4);
+    L.grads = o;
+    o += align_up((size_t)L.P.slice_len * 4);
+    L.loss = o;
+    o += align_up(8);
+    L.total = o;
+    return L;
+}
+
 }  // namespace trk
 
 using namespace trk;
@@ -300,6 +388,89 @@ tr_status tr_entry_bwd(const tr_desc* d, const void* const* cores, const int32_t
     hipLaunchKernelGGL(k_entry_bwd_reduce, dim3((unsigned)((P.slice_len + 255) / 256)), dim3(256), 0, st, *d, gpart,
                        P.bwd_blocks, P.slice_len, gp);
     return hipGetLastError() == hipSuccess ? TR_OK : TR_E_HIP;
+}
+
+static tr_status completion_checks(const tr_desc* d, const tr_completion_config* c) {
+    tr_status s = validate_desc(d);
+    if (s != TR_OK) return s;
+    if (!c) return TR_E_ARG;
+    if (d->core_dtype != TR_F32) return TR_E_DTYPE;
+    if (d->x_dtype != TR_F32 && d->x_dtype != TR_F16) return TR_E_DTYPE;
+    if (c->B < 1 || c->B > (1 << 26)) return TR_E_SHAPE;
+    if (!(c->lambda >= 0.0)) return TR_E_ARG;
+    if (c->rule.kind < 0 || c->rule.kind > 2) return TR_E_ARG;
+    if (c->rule.kind == 2 && !(c->rule.tau > 0.0)) return TR_E_ARG;
+    return TR_OK;
+}
+
+size_t tr_completion_workspace_size(const tr_desc* d, const tr_completion_config* c) {
+    if (completion_checks(d, c) != TR_OK) return 0;
+    return completion_layout(*d, c->B).total;
+}
+
+tr_status tr_completion_run(const tr_desc* d, void* const* cores, void* const* accum, const int32_t* obs_idx,
+                            const void* obs_x, int64_t n_obs, const tr_completion_config* c, uint64_t* t_dev,
+                            int32_t steps, double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                            tr_stream_t stream) {
+    tr_status s = completion_checks(d, c);
+    if (s != TR_OK) return s;
+    if (!cores || !obs_idx || !obs_x || !t_dev || n_obs < 1 || steps < 0) return TR_E_ARG;
+    for (int k = 0; k < d->N; ++k) {
+        if (!cores[k]) return TR_E_ARG;
+        if (c->rule.kind == 1 && (!accum || !accum[k])) return TR_E_ARG;
+    }
+    const CompletionWs L = completion_layout(*d, c->B);
+    if (!ws || ws_bytes < L.total) return TR_E_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return TR_E_ALIGN;
+    if (steps == 0) return TR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    char* w = static_cast<char*>(ws);
+    double* part = reinterpret_cast<double*>(w + L.P.part_off);
+    float* gpart = reinterpret_cast<float*>(w + L.P.gpart_off);
+    int32_t* bidx = reinterpret_cast<int32_t*>(w + L.bidx);
+    float* resid = reinterpret_cast<float*>(w + L.resid);
+    float* grads = reinterpret_cast<float*>(w + L.grads);
+    double* lossw = reinterpret_cast<double*>(w + L.loss);
+    Ptrs cp{};
+    MutPtrs mc{}, ac{}, gp{};
+    int64_t off = 0;
+    for (int k = 0; k < d->N; ++k) {
+        cp.p[k] = cores[k];
+        mc.p[k] = cores[k];
+        ac.p[k] = accum ? accum[k] : nullptr;
+        gp.p[k] = grads + off;
+        off += (int64_t)d->I[k] * d->R[k] * d->R[ring_next(k, d->N)];
+    }
+    const int B = c->B;
+    const dim3 gd((unsigned)((B + 255) / 256));
+    const dim3 gu((unsigned)((L.P.slice_len + 255) / 256));
+    for (int it = 0; it < steps; ++it) {
+        double* loss = loss_out ? loss_out + it : lossw;
+        if (d->x_dtype == TR_F32) {
+            float* bx = reinterpret_cast<float*>(w + L.bx);
+            hipLaunchKernelGGL(k_completion_draw<float>, gd, dim3(256), 0, st, *d, t_dev, c->seed, obs_idx,
+                               static_cast<const float*>(obs_x), n_obs, B, bidx, bx);
+            hipLaunchKernelGGL(k_entry_fwd<float>, dim3(L.P.fwd_blocks), dim3(kEntBlock), 0, st, *d, cp, bidx, bx, B,
+                               resid, part);
+        } else {
+            __half* bx = reinterpret_cast<__half*>(w + L.bx);
+            hipLaunchKernelGGL(k_completion_draw<__half>, gd, dim3(256), 0, st, *d, t_dev, c->seed, obs_idx,
+                               static_cast<const __half*>(obs_x), n_obs, B, bidx, bx);
+            hipLaunchKernelGGL(k_entry_fwd<__half>, dim3(L.P.fwd_blocks), dim3(kEntBlock), 0, st, *d, cp, bidx, bx,
+                               B, resid, part);
+        }
+        hipLaunchKernelGGL(k_completion_loss, dim3(1), dim3(256), 0, st, *d, part, L.P.fwd_blocks, B, cp, c->lambda,
+                           loss);
+        hipLaunchKernelGGL(k_entry_bwd_acc, dim3(L.P.bwd_blocks), dim3(kEntBlock), L.P.bwd_shm, st, *d, cp, bidx,
+                           resid, B, L.P.EPB, L.P.SB, 1.0f, nullptr, gpart, L.P.slice_len);
+        hipLaunchKernelGGL(k_entry_bwd_reduce, dim3((unsigned)((L.P.slice_len + 255) / 256)), dim3(256), 0, st, *d,
+                           gpart, L.P.bwd_blocks, L.P.slice_len, gp);
+        hipLaunchKernelGGL(k_completion_update, gu, dim3(256), 0, st, *d, t_dev, c->seed, (int)c->block, mc, ac,
+                           grads, L.P.slice_len, c->lambda, c->rule, dev_status);
+        if (hipGetLastError() != hipSuccess) return TR_E_HIP;
+        if (launch_bump(t_dev, st) != hipSuccess) return TR_E_HIP;
+    }
+    return TR_OK;
 }
 
 }  // extern "C"

@@ -44,7 +44,7 @@ def test_entry_forward_backward_parity(N, I, R, B):
     lref, rref = entry.entry_loss(cores, idx, x)
     assert rel(resid.cpu().numpy(), rref) < 1e-5
     assert abs(float(loss) - lref) <= 1e-5 * lref
-    grads = api.tr_entry_bwd(desc, dc, didx, resid, B, scale=1.0 / B)
+    grads = api.tr_entry_bwd(desc, dc, didx, resid, B)
     gref = entry.entry_grads(cores, idx, x)
     for k in range(N):
         assert rel(grads[k].cpu().numpy(), unfold(gref[k])) < 1e-5
@@ -85,7 +85,7 @@ def test_backward_is_bitwise_reproducible():
     dc = [to_dev(unfold(c), torch.float32) for c in cores]
     didx = to_dev(idx, torch.int32)
     resid, _ = api.tr_entry_fwd(desc, dc, didx, to_dev(x, torch.float32), 8192)
-    a = api.tr_entry_bwd(desc, dc, didx, resid, 8192, scale=1 / 8192)
-    b = api.tr_entry_bwd(desc, dc, didx, resid, 8192, scale=1 / 8192)
+    a = api.tr_entry_bwd(desc, dc, didx, resid, 8192)
+    b = api.tr_entry_bwd(desc, dc, didx, resid, 8192)
     for u, v in zip(a, b):
         assert torch.equal(u, v)

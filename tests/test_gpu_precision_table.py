@@ -1,0 +1,127 @@
+"""The precision policy's error per result against the FP64 oracle:
+normwise relative error of the sampled subchain rows S, the stochastic
+gradient g (eq:S_gradient), the stochastic Hessian h (eq:S_hessian), the
+scaled direction p (eq:scaledsg_direction), the loss estimate and the RSE,
+for the FP32, BF16-mixed and FP16-mixed forms at the full 400^3, rank-10
+ill-conditioned workload (|F_n| = 4096), and for the batched FP16 path
+(g and the loss on the 64-problem workload's largest-R_nR_{n+1} and
+largest problems).  The oracle runs in FP64 from the same rounded cores and
+tensor (its own S, g, h, p); the table is printed and each entry held to its
+bar (FP32 1e-5; 16-bit 5e-3; p and the RSE also scaled by the conditioning
+they inherit)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import tr_inputs as ti
+from oracle import brsgd, sampling, tr
+from gpu_util import TOL, flat_paper, fold, rel, rounded, say, to_dev, unfold
+
+pytestmark = pytest.mark.gpu
+
+from paper_2303_16492_amd import _lib as L  # noqa: E402
+from paper_2303_16492_amd import api  # noqa: E402
+from paper_2303_16492_amd.driver import TRBatch  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+PRECS = [("fp32", L.TR_PREC_F32, TOL[torch.float32]), ("bf16-mixed", L.TR_PREC_BF16, 5e-3),
+         ("fp16-mixed", L.TR_PREC_F16, 5e-3)]
+
+
+def _table(rows, title):
+    lines = [f"### {title}", "", "| form | S | g | h | p | loss | RSE | cond(h) |", "|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append("| " + " | ".join([r[0]] + [("—" if v is None else f"{v:.2e}") for v in r[1:]]) + " |")
+    text = "\n".join(lines)
+    say(text)
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "precision_table.md"), "a") as fh:
+        fh.write(text + "\n\n")
+
+
+def test_error_per_result_at_full_size():
+    dtype = torch.float32
+    N, I, R, m = 3, 400, 10, 4096
+    true3 = ti.illcond_cores(0, N, I, R, 1e4)
+    X = tr.full_tensor(true3)
+    X = rounded(X / np.sqrt(np.mean(X * X)), dtype)
+    init = [rounded(c, dtype) for c in ti.gaussian_cores(1, N, I, R, scale=(1.0 / R ** N) ** (1 / (2 * N)))]
+    desc = api.make_desc([I] * N, [R] * N, dtype)
+    dX = to_dev(flat_paper(X), dtype)
+    n, t = api.tr_mode(0, 0, N), 0
+    idx, pF = api.tr_sample(desc, 0, t, n, m)
+    ridx, rpF = sampling.draw(0, t, n, m, [I] * N)
+    assert np.array_equal(idx.cpu().numpy(), ridx) and np.array_equal(pF.cpu().numpy(), rpF)
+    Jn = I * I
+    S_ref = brsgd.subchain_rows(init, n, ridx)
+    XF = brsgd.gather_fibers(X, n, ridx)
+    Gn = unfold(init[n])
+    g_ref, loss_ref = brsgd.stoch_grad(Gn, S_ref, XF, rpF, Jn)
+    h_ref = brsgd.stoch_hessian(S_ref, rpF, Jn)
+    p_ref, _ = brsgd.scaled_direction(g_ref, h_ref)
+    cond = float(np.linalg.cond(h_ref))
+    rse_ref = tr.rse(init, X)
+    dcores = [to_dev(unfold(c), dtype) for c in init]
+    rse = float(api.tr_relerr(desc, dcores, dX))
+    S = api.tr_subchain(desc, n, dcores, idx, m)
+    eS = rel(S.cpu().numpy(), S_ref)
+    rows = []
+    for name, prec, bar in PRECS:
+        say("precision table", name)
+        g, loss, gram = api.tr_grad(desc, n, dcores[n], dX, idx, S, pF, m, prec, want_gram=True)
+        core = dcores[n].clone()
+        api.tr_update(desc, n, core, g, gram=gram, rule=api.step_rule("fixed", alpha=1.0), t=t)
+        p = core.double().cpu().numpy() - Gn
+        row = [name, eS, rel(g.cpu().numpy(), g_ref), rel(gram.cpu().numpy(), h_ref), rel(p, p_ref),
+               abs(float(loss) - loss_ref) / loss_ref, abs(rse - rse_ref) / rse_ref, cond]
+        rows.append(row)
+        assert row[1] < TOL[dtype] and row[3] < TOL[dtype]          # S and h: FP32 rows, FP64 sums
+        assert row[2] < bar and row[5] < bar
+        assert row[4] < max(bar, 2.0 ** -22 * cond)
+        assert row[6] < TOL[dtype]
+    _table(rows, "400^3, ranks 10, kappa 1e4, |F_n| = 4096 (one step from the initial cores)")
+
+
+def test_error_per_result_batched_fp16():
+    """The batched kernel takes one fixed step alpha p = -alpha g on every
+    problem; g is read back from the change of core n."""
+    inst = ti.batched_instances(0)
+    rr = [max(b.R[k] * b.R[(k + 1) % b.N] for k in range(b.N)) for b in inst]
+    pick = sorted({int(np.argmax(rr)), int(np.argmax([int(np.prod(b.I)) for b in inst]))})
+    m = 1024
+    probs, host = [], []
+    for q in pick:
+        b = inst[q]
+        Xt = tr.full_tensor(ti.gaussian_cores(b.seed, b.N, b.I, b.R))
+        X = rounded(brsgd.add_noise(Xt, ti.standard_normal(b.seed + 5, Xt.shape), 40.0), torch.float16)
+        del Xt
+        init = [rounded(c, torch.float32) for c in ti.gaussian_cores(b.seed + 1, b.N, b.I, b.R,
+                                                                    scale=brsgd.init_scale(X, b.R))]
+        desc = api.make_desc(b.I, b.R, torch.float32, torch.float16)
+        dX = to_dev(flat_paper(X), torch.float16)
+        reps = [api.tr_x_replicate(desc, dX, k) for k in range(b.N)]
+        del dX
+        # the oracle's step first: alpha makes the change of core n a tenth
+        # of its norm, far above the FP32 rounding of the core
+        st = brsgd.State([c.copy() for c in init])
+        trace = {}
+        n = brsgd.step(st, X, brsgd.Config(m=m, alpha=1.0, seed=b.seed), trace=trace)
+        alpha = 0.1 * np.linalg.norm(unfold(init[n])) / np.linalg.norm(trace["g"])
+        probs.append(dict(cores=[to_dev(unfold(c), torch.float32) for c in init], Xrep=reps, I=b.I, R=b.R, m=m,
+                          rule=api.step_rule("fixed", alpha=alpha), seed=b.seed))
+        host.append((init, b, n, trace, alpha))
+        del X
+    B = TRBatch(probs)
+    B.run(1, chunk=64, waves=8, splits=4)
+    torch.cuda.synchronize()
+    rows = []
+    for p, (init, b, n, trace, alpha) in enumerate(host):
+        got = probs[p]["cores"][n].cpu().numpy().astype(np.float64)
+        g = -(got - unfold(init[n])) / alpha
+        eg = rel(g, trace["g"])
+        el = abs(float(B.loss[p]) - trace["loss"]) / trace["loss"]
+        rows.append([f"batched fp16, N={b.N} I={b.I} R={b.R}", None, eg, None, None, el, None, float("nan")])
+        assert eg < 5e-3 and el < 5e-3, (p, eg, el)
+    _table(rows, "64-problem workload, FP16 tensors, m = 1024 (one fixed step)")
