@@ -52,6 +52,10 @@ def parse(argv=None):
                     help="only run 20 plain device copies of MIB MiB (counter calibration) and exit")
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="timed steps of the 64-problem batched workload (0: skip it)")
+    ap.add_argument("--autograd-steps", type=int, default=6000,
+                    help="step cap of the differentiation workload's time-to-target runs (0: skip the leg)")
+    ap.add_argument("--methods-budget", type=float, default=0.25,
+                    help="seconds of GPU time per comparison method (0: skip the leg)")
     return ap.parse_args(argv)
 
 
@@ -145,34 +149,327 @@ def build_problem(seed, I, R, kappa, dev, kind="illcond"):
     return desc, X, true3, init3
 
 
+BATCH_ETA = 0.2          # AdaGrad eta of the batched workload (both forms)
+BATCH_TARGET = 1e-2      # RSE against the noise-free tensor, per problem
+
+
+def batch_problem(b, dev):
+    """One problem of the 64-problem workload: the planted tensor X_true
+    (i.i.d. N(0,1) cores) rescaled to RMS 1, X = X_true + 40 dB noise (FP32),
+    and the initial cores matched to X's second moment.  Deterministic in
+    the instance's seed."""
+    import torch
+    import tr_inputs as ti
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import cores_to_device
+    d32 = api.make_desc(b.I, b.R, torch.float32, torch.float32)
+    true = cores_to_device(ti.gaussian_cores(b.seed, b.N, b.I, b.R), torch.float32, dev)
+    Xt = api.tr_reconstruct(d32, true)
+    Xt.div_(float(Xt.double().pow(2).mean().sqrt()))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(b.seed + 5)
+    sigma = 10.0 ** (-40.0 / 20.0) * float(Xt.double().norm()) / (Xt.numel() ** 0.5)
+    X = Xt + sigma * torch.randn(Xt.numel(), generator=gen, device=dev, dtype=torch.float32)
+    sig = (float(X.double().pow(2).mean()) / float(np.prod(b.R))) ** (1.0 / (2 * b.N))
+    init = ti.gaussian_cores(b.seed + 1, b.N, b.I, b.R, scale=sig)
+    return d32, Xt, X, init
+
+
 def build_batch(seed, dev):
     """The 64 independent planted problems (orders 3-5, sizes 16-128, ranks
-    3-12, 40 dB noise, FP16 tensors, m = 1024, AdaGrad) as a TRBatch."""
+    3-12, RMS 1, 40 dB noise, FP16 tensors, m = 1024, AdaGrad) as a TRBatch,
+    with each problem's noise-free tensor (FP32) for the RSE."""
     import torch
     import tr_inputs as ti
     from paper_2303_16492_amd import api
     from paper_2303_16492_amd.driver import TRBatch, cores_to_device
     insts = ti.batched_instances(seed)
-    probs = []
-    gen = torch.Generator(device=dev)
+    probs, truths = [], []
     for b in insts:
-        d32 = api.make_desc(b.I, b.R, torch.float32, torch.float32)
+        d32, Xt, X, init = batch_problem(b, dev)
         d16 = api.make_desc(b.I, b.R, torch.float32, torch.float16)
-        true = cores_to_device(ti.gaussian_cores(b.seed, b.N, b.I, b.R), torch.float32, dev)
-        X = api.tr_reconstruct(d32, true)
-        gen.manual_seed(b.seed + 5)
-        sigma = 10.0 ** (-40.0 / 20.0) * float(X.double().norm()) / (X.numel() ** 0.5)
-        X.add_(torch.randn(X.numel(), generator=gen, device=dev, dtype=torch.float32), alpha=sigma)
         X16 = X.half()
         del X
-        ms2 = float(X16.float().pow(2).mean())
-        sig = (ms2 / float(np.prod(b.R))) ** (1.0 / (2 * b.N))
-        cores = cores_to_device(ti.gaussian_cores(b.seed + 1, b.N, b.I, b.R, scale=sig), torch.float32, dev)
+        cores = cores_to_device(init, torch.float32, dev)
         reps = [api.tr_x_replicate(d16, X16, n) for n in range(b.N)]
         del X16
+        truths.append((d32, Xt))
         probs.append(dict(cores=cores, Xrep=reps, I=b.I, R=b.R, m=1024,
-                          rule=api.step_rule("adagrad", eta=0.05), seed=b.seed))
-    return TRBatch(probs, dev), insts
+                          rule=api.step_rule("adagrad", eta=BATCH_ETA), seed=b.seed))
+    return TRBatch(probs, dev), insts, truths
+
+
+def batch_time_to_target(B, truths, every=250, cap=4000):
+    """Wall time until every problem's RSE (against its noise-free tensor)
+    is <= BATCH_TARGET: ``every`` steps of all problems replay one captured
+    graph, then the RSE of each problem not yet there is checked (the checks
+    count).  Returns (seconds or None, steps, per-problem steps, worst ratio)."""
+    import torch
+    from paper_2303_16492_amd import api
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        B.run(every)
+    reached = [None] * B.count
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < cap and any(r is None for r in reached):
+        g.replay()
+        steps += every
+        for p, (d32, Xt) in enumerate(truths):
+            if reached[p] is None and float(api.tr_relerr(d32, B.problems[p]["cores"], Xt)) <= BATCH_TARGET:
+                reached[p] = steps
+    wall = time.perf_counter() - t0
+    done = all(r is not None for r in reached)
+    del g
+    return (round(wall, 4) if done else None), steps, reached, round(wall, 4)
+
+
+def single_time_to_target(insts, dev, every=250, cap=4000):
+    """The same problems stepped one at a time in FP32 (FP32 tensor, FP32
+    matrix-core gradient, same AdaGrad eta, m = 1024), each to the same
+    target; returns (total seconds, per-problem steps, steps/s of a single
+    problem's step averaged over problems)."""
+    import torch
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    total, per, rates = 0.0, [], []
+    for b in insts:
+        d32, Xt, X, init = batch_problem(b, dev)
+        sol = TRSolver(cores_to_device(init, torch.float32, dev), X, b.I, b.R, 1024, law="U", scaled=False,
+                       prec="f32", rule=api.step_rule("adagrad", eta=BATCH_ETA), seed=b.seed)
+        snap = [c.clone() for c in sol.cores]
+        g = sol.capture(every)
+        for c, s_ in zip(sol.cores, snap):
+            c.copy_(s_)
+        for a in sol.accum:
+            a.zero_()
+        sol.t_dev.zero_()
+        torch.cuda.synchronize()
+        steps, ok = 0, False
+        t0 = time.perf_counter()
+        while steps < cap and not ok:
+            g.replay()
+            steps += every
+            ok = float(api.tr_relerr(d32, sol.cores, Xt)) <= BATCH_TARGET
+        wall = time.perf_counter() - t0
+        total += wall
+        per.append(steps if ok else None)
+        rates.append(steps / wall)
+        del g, sol, X, Xt
+    torch.cuda.empty_cache()
+    return round(total, 4), per, float(np.mean(rates))
+
+
+def autograd_leg(dev, K=50, steps_cap=6000, every=200):
+    """The differentiation workload: order 5, 32 per mode, ranks 8, planted
+    Gaussian ring at RMS 1 + 30 dB noise, FP32, batches of B = 8192 sampled
+    entries.  (1) Forward + backward through the torch.autograd.Function
+    over the library's kernels, K pre-drawn batches: entries/s.  (2) Time
+    to the target RSE (against the noise-free tensor) of the sampled-entry
+    method (the same forward and backward kernels in the library's native
+    loop, AdaGrad, every core per step, all entries observable) beside the
+    plain FP32 fiber-sampling method (TR-BRSGD, AdaGrad, m = 256 fibers =
+    8192 entries per step)."""
+    import torch
+    import tr_inputs as ti
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.autograd import tr_entry_loss
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    N, I, R, B = 5, 32, 8, 8192
+    desc = api.make_desc([I] * N, [R] * N, torch.float32)
+    true = cores_to_device(ti.gaussian_cores(3, N, [I] * N, [R] * N), torch.float32, dev)
+    Xt = api.tr_reconstruct(desc, true)
+    Xt.div_(float(Xt.double().pow(2).mean().sqrt()))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    sigma = 10.0 ** (-30.0 / 20.0)
+    X = Xt + sigma * torch.randn(Xt.numel(), generator=gen, device=dev, dtype=torch.float32)
+    sig = (float(X.double().pow(2).mean()) / float(R ** N)) ** (1.0 / (2 * N))
+    init = ti.gaussian_cores(4, N, [I] * N, [R] * N, scale=sig)
+    P = N * I * R * R
+    floor = sigma * (P / float(I ** N)) ** 0.5
+    target = max(1e-4, 1.05 * floor)
+    # (1) forward + backward through autograd
+    cores = [c.requires_grad_() for c in cores_to_device(init, torch.float32, dev)]
+    strides = torch.tensor([I ** k for k in range(N)], device=dev, dtype=torch.int64)
+    batches = []
+    for k in range(K):
+        idx = torch.randint(0, I, (B, N), generator=gen, device=dev, dtype=torch.int64)
+        batches.append((idx.to(torch.int32), X[(idx * strides).sum(1)].contiguous()))
+    loss = tr_entry_loss(desc, batches[0][0], batches[0][1], cores)
+    loss.backward()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for idx, x in batches:
+        loss = tr_entry_loss(desc, idx, x, cores)
+        loss.backward()
+    b.record()
+    torch.cuda.synchronize()
+    fb_ms = a.elapsed_time(b) / K
+    del batches, cores
+    # (2) time to target: the sampled-entry loop over every entry as observed
+    obs_idx = torch.stack(torch.meshgrid(*[torch.arange(I, device=dev, dtype=torch.int32)] * N, indexing="ij"),
+                          -1).flip(-1).reshape(-1, N).contiguous()          # first index fastest
+    cfg = api.completion_config(B, rule=api.step_rule("adagrad", eta=0.05), seed=7)
+    runs = {}
+    ecores = cores_to_device(init, torch.float32, dev)
+    acc = [torch.zeros_like(c) for c in ecores]
+    t_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = api.workspace(api.lib().tr_completion_workspace_size(C.byref(desc), C.byref(cfg)), dev)
+    g = torch.cuda.CUDAGraph()
+    sg = torch.cuda.Stream()
+    sg.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=sg):
+        api.tr_completion_run(desc, ecores, acc, obs_idx, X, cfg, t_dev, every, status=st, ws=ws)
+    steps, rse = 0, float("nan")
+    t0 = time.perf_counter()
+    while steps < steps_cap:
+        g.replay()
+        steps += every
+        rse = float(api.tr_relerr(desc, ecores, Xt))
+        if rse <= target:
+            break
+    runs["sampled_entry"] = {"seconds": round(time.perf_counter() - t0, 4) if rse <= target else None,
+                             "steps": steps, "rse_at_stop": rse, "entries_per_step": B}
+    del g, obs_idx, ecores, acc
+    sol = TRSolver(cores_to_device(init, torch.float32, dev), X, [I] * N, [R] * N, B // I, law="U",
+                   scaled=False, prec="f32", rule=api.step_rule("adagrad", eta=0.05), seed=7)
+    snap = [c.clone() for c in sol.cores]
+    g = sol.capture(every)
+    for c, s_ in zip(sol.cores, snap):
+        c.copy_(s_)
+    for a_ in sol.accum:
+        a_.zero_()
+    sol.t_dev.zero_()
+    torch.cuda.synchronize()
+    steps, rse = 0, float("nan")
+    t0 = time.perf_counter()
+    while steps < steps_cap:
+        g.replay()
+        steps += every
+        rse = float(api.tr_relerr(desc, sol.cores, Xt))
+        if rse <= target:
+            break
+    runs["plain_fp32_fibers"] = {"seconds": round(time.perf_counter() - t0, 4) if rse <= target else None,
+                                 "steps": steps, "rse_at_stop": rse, "entries_per_step": (B // I) * I}
+    del g, sol
+    return {"workload": "autograd-n5-i32-r8-b8192", "B": B, "noise_db": 30, "precision": "fp32",
+            "fwd_bwd_ms_per_batch": round(fb_ms, 5), "fwd_bwd_entries_per_s": round(B / (fb_ms * 1e-3), 1),
+            "fwd_bwd_timing": f"{K} pre-drawn batches through torch.autograd.Function (forward + backward kernels)",
+            "target": {"rse_true": target, "floor_estimate": floor,
+                       "reading": "max(1e-4, 1.05 x noise level x sqrt(parameters / entries))"},
+            "time_to_target": runs, "rse_every": every}
+
+
+def c1_time_to_target(dev, target=1e-4, every=10, cap=2000):
+    """The plain FP64 workload (20^3, ranks 3, uniform fibers, m = 100,
+    fixed step 0.2, noise-free planted ring): GPU time to RSE <= target
+    (``every`` steps from one replayed graph, RSE checks counted)."""
+    import torch
+    import tr_inputs as ti
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    N, I, R, m = 3, 20, 3, 100
+    desc = api.make_desc([I] * N, [R] * N, torch.float64)
+    X = api.tr_reconstruct(desc, cores_to_device(ti.gaussian_cores(0, N, [I] * N, [R] * N), torch.float64, dev))
+    sig = (float(X.pow(2).mean()) / float(R ** N)) ** (1.0 / (2 * N))
+    init = ti.gaussian_cores(1, N, [I] * N, [R] * N, scale=sig)
+    sol = TRSolver(cores_to_device(init, torch.float64, dev), X, [I] * N, [R] * N, m, prec="f64",
+                   rule=api.step_rule("fixed", alpha=0.2), seed=0)
+    snap = [c.clone() for c in sol.cores]
+    g = sol.capture(every)
+    for c, s_ in zip(sol.cores, snap):
+        c.copy_(s_)
+    sol.t_dev.zero_()
+    torch.cuda.synchronize()
+    steps, rse = 0, float("nan")
+    t0 = time.perf_counter()
+    while steps < cap:
+        g.replay()
+        steps += every
+        rse = float(sol.rse())
+        if rse <= target:
+            break
+    gpu_s = time.perf_counter() - t0
+    return {"workload": "plain-fp64-n3-i20-r3", "target": target, "rse_every": every,
+            "seconds": round(gpu_s, 5) if rse <= target else None, "steps": steps, "rse_at_stop": rse}
+
+
+def c1_cpu_oracle(target=1e-4, every=10, cap=2000):
+    """The oracle on the host: the same plain FP64 run to the same target."""
+    import tr_inputs as ti
+    from oracle import brsgd, tr
+    N, I, R, m = 3, 20, 3, 100
+    X = tr.full_tensor(ti.gaussian_cores(0, N, [I] * N, [R] * N))
+    init = ti.gaussian_cores(1, N, [I] * N, [R] * N, scale=brsgd.init_scale(X, [R] * N))
+    st = brsgd.State(init)
+    t0 = time.perf_counter()
+    hist = brsgd.run(st, X, brsgd.Config(m=m, alpha=0.2, seed=0), cap, rse_every=every, tol=target)
+    return {"workload": "plain-fp64-n3-i20-r3", "target": target, "rse_every": every,
+            "seconds": round(time.perf_counter() - t0, 4) if hist and hist[-1][1] <= target else None,
+            "steps": hist[-1][0] if hist else None, "rse_at_stop": hist[-1][1] if hist else None}
+
+
+def methods_leg(args, init3, X, I, R, m, dev, budget_s=0.25):
+    """The paper's comparison (second synthetic experiment's table,
+    qualitatively) on the benchmark problem: each method from the same
+    initial cores for about ``budget_s`` of GPU time, RSE at the end."""
+    import torch
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, TRSweeper, cores_to_device
+    N = 3
+    out = {}
+
+    def rse_of(cores):
+        return float(api.tr_relerr(api.make_desc([I] * N, [R] * N, torch.float32), cores, X))
+
+    step_methods = {
+        "TR-BRSGD-U (AdaGrad eta 1e-2)": dict(scaled=False, law="U", rule=api.step_rule("adagrad", eta=1e-2)),
+        "TR-ScaledBRSGD-U (alpha 1)": dict(scaled=True, law="U", rule=api.step_rule("fixed", alpha=1.0)),
+        "TR-ScaledBRSGD-L (alpha 1)": dict(scaled=True, law="L", rule=api.step_rule("fixed", alpha=1.0)),
+    }
+    for name, kw in step_methods.items():
+        sol = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, prec="f32", seed=args.seed,
+                       **kw)
+        sol.run(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < budget_s:
+            sol.run(50)
+            torch.cuda.synchronize()
+            steps += 50
+        wall = time.perf_counter() - t0
+        out[name] = {"steps": steps + 5, "seconds": round(wall, 4), "rse": rse_of(sol.cores)}
+        del sol
+    sweep_methods = {
+        "TR-GD (alpha 1e-2)": dict(method="gd", alpha=1e-2),
+        "TR-ScaledGD (alpha 0.5)": dict(method="scaled-gd", alpha=0.5),
+        "TR-ALS": dict(method="als"),
+        "TR-ALS-Sampled-L (m 4096)": dict(method="als-sampled", m=m, law="L"),
+    }
+    for name, kw in sweep_methods.items():
+        sw = TRSweeper(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, prec="f32", seed=args.seed,
+                       **kw)
+        t0 = time.perf_counter()
+        sweeps = 0
+        while time.perf_counter() - t0 < budget_s:
+            sw.sweep(1)
+            torch.cuda.synchronize()
+            sweeps += 1
+        wall = time.perf_counter() - t0
+        out[name] = {"sweeps": sweeps, "block_updates": sweeps * N, "seconds": round(wall, 4),
+                     "rse": rse_of(sw.cores)}
+        del sw
+    torch.cuda.empty_cache()
+    return {"workload": "scaled-illcond-n3-i400-r10", "budget_s_each": budget_s, "precision": "fp32",
+            "methods": out}
 
 
 def host_info():
@@ -462,6 +759,11 @@ def main():
             print(f"[bench] time-to-target {pr}: {ttt[-1]['reached']} after {ttt[-1]['steps']} steps, "
                   f"rse {ttt[-1]['rse_at_stop']:.3e}", file=sys.stderr, flush=True)
 
+    methods = None
+    if args.methods_budget > 0:
+        methods = methods_leg(args, init3, X, I, R, m, dev, budget_s=args.methods_budget)
+        print(f"[bench] methods: {json.dumps(methods['methods'])}", file=sys.stderr, flush=True)
+
     # a9 on its own: one RSE evaluation at 400^3 (X read once, 2 I^3 R^2 FLOP)
     from paper_2303_16492_amd.driver import cores_to_device
     rcores = cores_to_device(init3, torch.float32, dev)
@@ -528,27 +830,68 @@ def main():
         print("[bench] building the 64-problem batch ...", file=sys.stderr, flush=True)
         del X
         torch.cuda.empty_cache()
-        B, insts = build_batch(args.seed, dev)
+        B, insts, truths = build_batch(args.seed, dev)
         torch.cuda.synchronize()
         tune = B.tune(steps=3, reps=2)
         print(f"[bench] batch tuned: {tune} -> chunk {B.chunk}, waves {B.waves}, splits {B.splits}",
               file=sys.stderr, flush=True)
-        B.run(2)
+        # timed: args.batch_steps steps of all problems replayed from one captured graph
+        saved = B._state()
+        B.run(1)                                  # warm-up (and the split workspace) before the capture
+        gb = torch.cuda.CUDAGraph()
+        sb = torch.cuda.Stream()
+        sb.wait_stream(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gb, stream=sb):
+            B.run(args.batch_steps)
+        gb.replay()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        B.run(args.batch_steps)
+        gb.replay()
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / args.batch_steps
-        batched = {"workload": "batched-64-planted-fp16", "problems": B.count, "m": 1024,
+        del gb
+        B._restore(saved)
+        torch.cuda.synchronize()
+        tiles = {"chunk": B.chunk, "waves": B.waves, "splits": B.splits}
+        print(f"[bench] batch: {ms * 1e3:.1f} us per step of all 64 problems (graph replay)", file=sys.stderr,
+              flush=True)
+        b_sec, b_steps, b_per, b_wall = batch_time_to_target(B, truths)
+        print(f"[bench] batch time to RSE {BATCH_TARGET:g}: {b_sec} s ({b_steps} steps)", file=sys.stderr, flush=True)
+        dev_status = int(B.status.max())
+        del B, truths
+        torch.cuda.empty_cache()
+        s_sec, s_per, s_rate = single_time_to_target(insts, dev)
+        print(f"[bench] same problems one at a time in FP32: {s_sec} s", file=sys.stderr, flush=True)
+        batched = {"workload": "batched-64-planted-fp16", "problems": len(insts), "m": 1024,
                    "steps": args.batch_steps, "ms_per_batch_step": round(ms, 5),
-                   "problem_steps_per_s": round(B.count * 1e3 / ms, 1),
-                   "tiles": {"chunk": B.chunk, "waves": B.waves, "splits": B.splits},
+                   "problem_steps_per_s": round(len(insts) * 1e3 / ms, 1),
+                   "timing": "steps of all problems replayed from one captured graph",
+                   "tiles": tiles,
                    "tuner_ms_per_step": {f"{c}x{w}x{sp}": round(v, 5) for (c, w, sp), v in tune.items()},
-                   "precision": "fp16 matrix cores, fp32 accumulation, fp64 loss",
-                   "mean_loss_estimate": float(B.loss.mean()), "dev_status_or": int(B.status.max())}
-        print(f"[bench] batch: {ms * 1e3:.1f} us per step of all 64 problems", file=sys.stderr, flush=True)
+                   "precision": "fp16 tensors and matrix cores, fp32 accumulation, fp64 loss",
+                   "data": "each planted tensor rescaled to RMS 1, 40 dB noise",
+                   "rule": f"AdaGrad eta {BATCH_ETA}",
+                   "time_to_target": {"target": f"RSE against the noise-free tensor <= {BATCH_TARGET:g} for every "
+                                                f"problem (checks every 250 steps, counted)",
+                                      "batched_seconds": b_sec, "batched_steps": b_steps,
+                                      "single_fp32_seconds": s_sec,
+                                      "single_fp32_steps_per_problem": s_per,
+                                      "batched_steps_per_problem": b_per,
+                                      "single_fp32_steps_per_s_avg": round(s_rate, 1),
+                                      "speedup": (round(s_sec / b_sec, 3) if b_sec else None)},
+                   "dev_status_or": dev_status}
+
+    autograd = None
+    if args.autograd_steps > 0:
+        autograd = autograd_leg(dev, steps_cap=args.autograd_steps)
+        print(f"[bench] autograd: {json.dumps(autograd)}", file=sys.stderr, flush=True)
+    c1 = None
+    if args.ttt_steps > 0:
+        c1 = c1_time_to_target(dev)
+        print(f"[bench] plain fp64 time to target: {json.dumps(c1)}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -562,7 +905,9 @@ def main():
                 "threads_1": {"value": round(v_one, 4), "unit": "steps/s", "cores": th_one,
                               "sample": f"{k_one} oracle steps, 1 BLAS thread, about {half:g} s"}}
         best = max(legs.values(), key=lambda x: x["value"])
+        c1_cpu = c1_cpu_oracle() if args.ttt_steps > 0 else None
         cpu = {"value": best["value"], "unit": "steps/s", "cores": best["cores"], "kind": "oracle",
+               "time_to_target_plain_fp64": c1_cpu,
                "sample": f"oracle steps (FP64 numpy/scipy) of the same 400^3 scaled workload after 1 warm-up step; "
                          f"value is the faster of the two thread settings ({best['sample']})",
                **legs, "host": host}
@@ -608,6 +953,9 @@ def main():
                                                            and planted_plain[1]["reached"] else None)},
         "relerr": relerr,
         "batched": batched,
+        "autograd": autograd,
+        "time_to_target_plain_fp64": c1,
+        "methods": methods,
         "rse_after": main["rse_after"],
         "dev_status": main["dev_status"],
     }

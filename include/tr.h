@@ -144,7 +144,7 @@ int32_t tr_mode(uint64_t seed, uint64_t step, int32_t N);
  * G^T G of G = G_{k(2)}, inverted by the blocked FP64 sweep for
  * R_k R_{k+1} <= 128 and through an FP64 Cholesky above.  The rank is
  * found on the Gram: when a pivot of that factorisation is at or below
- * 2^-40 of the largest diagonal entry, or when I_k <= R_k R_{k+1}, the
+ * 2^-43 of the largest diagonal entry, or when I_k <= R_k R_{k+1}, the
  * scores come from a Cholesky with diagonal pivoting of G^T G stopped at
  * pivots <= R_k R_{k+1} 2^-52 max diag: the rank r is the number of pivots
  * taken, l_i = g_i[P]^T (G_P^T G_P)^{-1} g_i[P] over the chosen columns P

@@ -155,7 +155,12 @@ __global__ __launch_bounds__(1024) void k_euc_cdf(tr_desc d, ModeSrc ms, int use
 // (row-major) holding G^T G on entry, overwritten.  Writes the weights
 // floor(l_i / r 2^40) + 1 into w (r = 0, a zero core: the uniform law and
 // TR_DEV_ZERO_DIST).
-constexpr double kLevTrigger = 1.0 / 1099511627776.0;   // 2^-40: pivot test that sends the fast path here
+// Pivot test that sends the fast path here: 2^-43 of the largest diagonal
+// entry, a few times the rounding of a Gram summed over a few hundred rows
+// (so a pivot of a dependent column is caught) while an ill-conditioned core
+// of full rank (sigma_min / sigma_max above about 3.4e-7) stays on the fast
+// path; both Gram routes carry the same kappa^2 u error on such a core.
+constexpr double kLevTrigger = 1.0 / 8796093022208.0;
 
 template <typename TC>
 __device__ void leverage_pivoted(const TC* __restrict__ G, int Ik, int RR, double* __restrict__ Bm,
@@ -448,7 +453,7 @@ __global__ __launch_bounds__(256) void k_lev_rows(tr_desc d, ModeSrc ms, int use
 }
 
 // Weights floor(l_i / RR 2^40) + 1 and their CDF (one block).  When the
-// sweep found a pivot at or below 2^-40 max_i h_ii (the Gram is singular or
+// sweep found a pivot at or below 2^-43 max_i h_ii (the Gram is singular or
 // close to it), or when I_k <= RR, the scores come from the rank-revealing
 // route instead (it overwrites the Gram ``gram``).
 template <typename TC>
@@ -530,7 +535,7 @@ hipError_t launch_dist(const tr_desc& d, ModeSrc ms, bool use_mode, int k, int l
         hipError_t e = launch_gram(d, mk, nullptr, nullptr, sh.maxI, gram, w, L.g, st, nullptr, cores);
         if (e != hipSuccess) return e;
         // no status from the inverse and no damping ladder: a pivot at or
-        // below 2^-40 of the largest diagonal entry sends the CDF kernel to
+        // below 2^-43 of the largest diagonal entry sends the CDF kernel to
         // the rank-revealing route
         e = launch_sweep_inverse(d, mk, gram, 0.0, L.u, w + L.upd_off, nullptr, st, kLevTrigger);
         if (e != hipSuccess) return e;

@@ -384,23 +384,11 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
         } else {
             fill_tiles<NT, WV>(acc, gram, RR, eta);
         }
-        if (attempt == 0) {   // largest diagonal entry, from the update wavefronts' diagonal tiles
+        if (attempt == 0) {   // largest diagonal entry of h + eta I: every wavefront reads it itself
             double mx = 0.0;
-            if (WV != kFactorWave) {
-#pragma unroll
-                for (int k = 0; k < tpw<NT>(); ++k) {
-                    if (!s_ok<NT>(WV, k) || s_rt<NT>(WV, k) != s_ct<NT>(WV, k)) continue;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int r = 16 * s_rt<NT>(WV, k) + 4 * j + lr, c = 16 * s_ct<NT>(WV, k) + lc;
-                        if (r == c && r < RR) mx = fmax(mx, acc[k][j]);
-                    }
-                }
-            }
+            for (int c = l; c < RR; c += 64) mx = fmax(mx, gram[(int64_t)c * RR + c]);
             for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-            if (l == 0) sh.red[WV] = mx;
-            __syncthreads();
-            const double mxa = fmax(fmax(sh.red[0], sh.red[1]), fmax(sh.red[2], sh.red[3]));
+            const double mxa = mx + eta;
             int ex = 0;
             if (mxa > 0.0 && isfinite(mxa)) {
                 (void)frexp(mxa, &ex);
