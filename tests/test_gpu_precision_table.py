@@ -41,13 +41,21 @@ def _table(rows, title):
         fh.write(text + "\n\n")
 
 
-def test_error_per_result_at_full_size():
+@pytest.mark.parametrize("oracle_steps", [0, 40])
+def test_error_per_result_at_full_size(oracle_steps):
+    """At the initial cores, and after 40 oracle steps of the scaled method
+    (alpha = 1) from them, where the Hessian is worse conditioned."""
     dtype = torch.float32
     N, I, R, m = 3, 400, 10, 4096
     true3 = ti.illcond_cores(0, N, I, R, 1e4)
     X = tr.full_tensor(true3)
     X = rounded(X / np.sqrt(np.mean(X * X)), dtype)
     init = [rounded(c, dtype) for c in ti.gaussian_cores(1, N, I, R, scale=(1.0 / R ** N) ** (1 / (2 * N)))]
+    if oracle_steps:
+        st0 = brsgd.State(init)
+        for _ in range(oracle_steps):
+            brsgd.step(st0, X, brsgd.Config(m=m, variant="scaled", alpha=1.0, seed=3))
+        init = [rounded(c, dtype) for c in st0.cores]
     desc = api.make_desc([I] * N, [R] * N, dtype)
     dX = to_dev(flat_paper(X), dtype)
     n, t = api.tr_mode(0, 0, N), 0
@@ -81,7 +89,8 @@ def test_error_per_result_at_full_size():
         assert row[2] < bar and row[5] < bar
         assert row[4] < max(bar, 2.0 ** -22 * cond)
         assert row[6] < TOL[dtype]
-    _table(rows, "400^3, ranks 10, kappa 1e4, |F_n| = 4096 (one step from the initial cores)")
+    where = "the initial cores" if not oracle_steps else f"the cores after {oracle_steps} oracle steps"
+    _table(rows, f"400^3, ranks 10, kappa 1e4, |F_n| = 4096 (one step from {where})")
 
 
 def test_error_per_result_batched_fp16():
