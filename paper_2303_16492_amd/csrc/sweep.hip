@@ -87,15 +87,17 @@ __device__ __forceinline__ double rcp_nr(double p) {
 
 // Symmetric sweep of the 8 x 8 SPD block D8 (row-major, both triangles):
 // -D8^{-1}, lower triangle packed by rows (tri8(i) + j) into Bw.  Lane
-// 8 i + j of the wavefront holds entry (i, j).  Pivot k takes a_kk from its
-// lane and column k (c_x = entry (max(x, k), min(x, k)), lower triangle) by
-// lane permutes, then every lane updates its own entry:
+// 8 i + j of the wavefront holds entry (i, j).  Pivot k takes column k
+// (c_x = entry (max(x, k), min(x, k)), lower triangle) by lane permutes,
+// then every lane updates its own entry:
 //     a_ij -= (c_i / a_kk) c_j,  a_ik <- c_i / a_kk,  a_kj <- c_j / a_kk,
 //     a_kk <- -1 / a_kk,
 // the classical symmetric sweep.  Only lower-triangle entries are read, so
 // the lanes of the lower triangle compute exactly the operations of the
-// sequential algorithm on that triangle.  False on a pivot not above ``tol``
-// (0: not positive) or not finite; every lane reaches the same verdict.
+// sequential algorithm on that triangle.  The reciprocal of each next pivot
+// is formed one pivot ahead (below), off the chain of lane permutes.  False
+// on a pivot not above ``tol`` (0: not positive) or not finite; every lane
+// reaches the same verdict.
 __device__ __forceinline__ double permute_lane(double v, int src) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
@@ -103,30 +105,48 @@ __device__ __forceinline__ double permute_lane(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Pivot K, dk = 1/a_kk arriving from the previous pivot.  The next pivot
+// and its reciprocal are formed here from the two entries they depend on
+// (read before this pivot's update, with the very operations lane 9(K+1)
+// applies to its entry, so the value is the same bit for bit), and the
+// reciprocal chain of pivot K+1 runs while this pivot waits for its lane
+// permutes.
 template <int K>
-__device__ __forceinline__ void sweep8_pivot(double& a, bool& good, int i, int j, double tol) {
-    const double p = readlane_f64(a, 9 * K);
+__device__ __forceinline__ void sweep8_pivot(double& a, double& dk, bool& good, int i, int j, double tol) {
     const double ci = permute_lane(a, i > K ? 8 * i + K : 8 * K + i);
     const double cj = permute_lane(a, j > K ? 8 * j + K : 8 * K + j);
-    good = good && (p > tol) && isfinite(p);
-    const double dk = rcp_nr(p);
-    const double ti = ci * dk, tj = cj * dk;
-    const double up = __builtin_fma(-ti, cj, a);
-    a = (i != K) ? ((j != K) ? up : ti) : ((j != K) ? tj : -dk);   // selects, no branches
+    double pn = 0.0, dkn = 0.0;
+    if (K < 7) {
+        const double c1 = readlane_f64(a, 8 * (K + 1) + K);   // entry (K+1, K)
+        const double a11 = readlane_f64(a, 9 * (K + 1));
+        pn = __builtin_fma(-(c1 * dk), c1, a11);
+        dkn = rcp_nr(pn);
+    }
+    double ti = ci * dk, tj = cj * dk;
+    double up = __builtin_fma(-ti, cj, a);
+    double nd = -dk;
+    asm volatile("" : "+v"(ti), "+v"(tj), "+v"(up), "+v"(nd));   // all four ready: selects, no branches
+    a = (i != K) ? ((j != K) ? up : ti) : ((j != K) ? tj : nd);
+    if (K < 7) {
+        good = good && (pn > tol) && isfinite(pn);
+        dk = dkn;
+    }
 }
 
 __device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw, double tol) {
     const int l = threadIdx.x & 63, i = l >> 3, j = l & 7;
     double a = D8[i * 8 + j];
-    bool good = true;
-    sweep8_pivot<0>(a, good, i, j, tol);
-    sweep8_pivot<1>(a, good, i, j, tol);
-    sweep8_pivot<2>(a, good, i, j, tol);
-    sweep8_pivot<3>(a, good, i, j, tol);
-    sweep8_pivot<4>(a, good, i, j, tol);
-    sweep8_pivot<5>(a, good, i, j, tol);
-    sweep8_pivot<6>(a, good, i, j, tol);
-    sweep8_pivot<7>(a, good, i, j, tol);
+    const double p = readlane_f64(a, 0);
+    double dk = rcp_nr(p);
+    bool good = (p > tol) && isfinite(p);
+    sweep8_pivot<0>(a, dk, good, i, j, tol);
+    sweep8_pivot<1>(a, dk, good, i, j, tol);
+    sweep8_pivot<2>(a, dk, good, i, j, tol);
+    sweep8_pivot<3>(a, dk, good, i, j, tol);
+    sweep8_pivot<4>(a, dk, good, i, j, tol);
+    sweep8_pivot<5>(a, dk, good, i, j, tol);
+    sweep8_pivot<6>(a, dk, good, i, j, tol);
+    sweep8_pivot<7>(a, dk, good, i, j, tol);
     if (j <= i) Bw[tri8(i) + j] = a;
     return good;
 }
@@ -371,6 +391,15 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
         }
         const double eta = attempt == 0 ? damping : damping + pow(10.0, (double)(attempt - 1 - 10)) * base;
         __syncthreads();   // the previous attempt's readers are done with the shared buffers
+        double dg[2] = {0.0, 0.0};   // diagonal entries l and l + 64, loaded with the tiles
+        if (attempt == 0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int c = l + 64 * u, cc = c < RR ? c : RR - 1;
+                const double v = gram[(int64_t)cc * RR + cc];
+                dg[u] = c < RR ? v : 0.0;
+            }
+        }
         double xb[2];      // factor wavefront: entry (u, v) of pivot blocks 0 and 1 of h + eta I
         if (WV == kFactorWave) {
             const int u = l >> 3, v = l & 7;
@@ -385,8 +414,7 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
             fill_tiles<NT, WV>(acc, gram, RR, eta);
         }
         if (attempt == 0) {   // largest diagonal entry of h + eta I: every wavefront reads it itself
-            double mx = 0.0;
-            for (int c = l; c < RR; c += 64) mx = fmax(mx, gram[(int64_t)c * RR + c]);
+            double mx = fmax(dg[0], dg[1]);
             for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
             const double mxa = mx + eta;
             int ex = 0;
