@@ -9,7 +9,8 @@ inverse and update (every row of the single-problem hot path).
 
 Prints one JSON line: steps/s of the --prec form (whole job), the same for
 the other form (FP32 vs BF16 mixed), the dominant kernel's roofline (HIP
-events around each launch inside the timed region), time to RSE 1e-4 for
+start/stop events recorded by each dispatch of the kernel itself), time
+to RSE 1e-4 for
 both forms (capped), the 64-problem batched workload (problem-steps/s with
 the tuner's tile choice), and the CPU oracle timed on a bounded sample.
 """
@@ -563,9 +564,9 @@ def measured_traffic(kernel):
 
 def timed_run(args, prec, init3, X, I, R, m, dev, K, warmup, G=50, E=200):
     """The scaled method in precision ``prec`` from the initial cores:
-    (1) E eager steps with HIP events recorded around the gradient and the
-    inverse kernel of every step, on the streams they run on (per-launch
-    kernel durations); (2) exactly K timed steps replayed from HIP graphs
+    (1) E eager steps whose gradient and inverse dispatches record HIP
+    start/stop events themselves (per-launch kernel execution times, as a
+    kernel trace reports them); (2) exactly K timed steps replayed from HIP graphs
     (``graph_schedule``: graphs of min(G, K) steps plus a remainder graph),
     whose rate is the result."""
     import torch
@@ -950,8 +951,9 @@ def main():
                           "gradient_us": round(alt["grad_us"], 3),
                           "inverse_us": None if alt["inv_us"] is None else round(alt["inv_us"], 3)}},
         "timing": "value: K steps replayed from a captured HIP graph of 50 steps (the Gram/inverse branch forks "
-                  "and joins as graph edges); kernel durations: HIP events around every launch of the inverse and "
-                  "gradient kernels over 200 eager steps of the same run, on the streams they run on",
+                  "and joins as graph edges); kernel durations: HIP start/stop events recorded by every dispatch of "
+                  "the inverse and gradient kernels themselves (hipExtLaunchKernelGGL) over 200 eager steps of the "
+                  "same run",
         "eager_steps_per_s": round(1e3 / main["eager_ms_per_step"], 2),
         "forms_plain_method": plain,
         "forms_laws": laws,

@@ -222,8 +222,10 @@ size_t tr_gram_workspace_size(const tr_desc* d, int32_t m_H);
 /* ------------------------------------------------------------------ */
 
 /* Direction p = -g (gram == NULL) or p = -g (h + damping I)^{-1} with
- * h = gram (eq:scaledsg_direction and the amended preconditioner), solved
- * by an FP64 Cholesky and two triangular solves.  If h + damping I is not
+ * h = gram (eq:scaledsg_direction and the amended preconditioner): for
+ * RR <= 128 the FP64 blocked symmetric sweep forms -(h + damping I)^{-1}
+ * and a row-parallel product applies it; for RR > 128 an FP64 Cholesky
+ * and two triangular solves.  If h + damping I is not
  * positive definite the solve retries with damping + 10^(k-10) tr(h)/RR,
  * k = 0..6 (TR_DEV_DAMPED), else leaves the core unchanged
  * (TR_DEV_NOT_SPD).  Then core_n is updated in place by ``rule`` at step t;
@@ -302,11 +304,12 @@ tr_status tr_run(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32
                  tr_stream_t stream);
 size_t tr_run_workspace_size(const tr_problem* p, const tr_config* c);
 
-/* tr_run with HIP events (hipEvent_t handles created by the caller)
- * recorded on ``stream`` right before and right after the dominant kernel
- * of step i (the fused fiber-gather / gradient contraction): ev_begin[i],
- * ev_end[i] for i < steps; NULL arrays or entries are skipped.  Lets a
- * caller time that kernel inside a real run. */
+/* tr_run with HIP events (hipEvent_t handles created by the caller) as the
+ * start and stop events of the dispatch of the dominant kernel of step i
+ * (the fused fiber-gather / gradient contraction): ev_begin[i], ev_end[i]
+ * for i < steps; NULL arrays or entries are skipped.  The dispatch records
+ * them itself, so their elapsed time is that kernel's execution inside a
+ * real run, without the queueing around it. */
 tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev, int32_t steps,
                         double* loss_out, int32_t* dev_status, void* ws, size_t ws_bytes,
                         void* const* ev_begin, void* const* ev_end, tr_stream_t stream);
@@ -326,8 +329,8 @@ tr_status tr_run_events(const tr_problem* p, const tr_config* c, uint64_t* t_dev
  *     fork/join is graph-capturable; results are bitwise those of the
  *     one-stream run.  All four must be set together, or all NULL.
  *   ev_begin, ev_end: as in tr_run_events.
- *   ev_inv_begin, ev_inv_end: the same around the RR x RR inverse of step i
- *     (scaled steps with RR <= 128), recorded on the stream it runs on. */
+ *   ev_inv_begin, ev_inv_end: the same for the dispatch of the RR x RR
+ *     inverse of step i (scaled steps with RR <= 128). */
 typedef struct {
     tr_stream_t aux;
     void* ev_fork;

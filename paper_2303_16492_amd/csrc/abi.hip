@@ -539,17 +539,18 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                                     fork ? (hipEvent_t)o.ev_gram : nullptr);
                 }
             }
-            if (e == hipSuccess && o.ev_inv_begin && o.ev_inv_begin[it])
-                e = hipEventRecord((hipEvent_t)o.ev_inv_begin[it], hs);
-            if (e == hipSuccess)
+            if (e == hipSuccess) {
+                TimedDispatch td(o.ev_inv_begin ? (hipEvent_t)o.ev_inv_begin[it] : nullptr,
+                                 o.ev_inv_end ? (hipEvent_t)o.ev_inv_end[it] : nullptr);
                 e = launch_sweep_inverse(d, ms_shape, gram, damp, L.ul, w + L.upd, dev_status, hs);
-            if (e == hipSuccess && o.ev_inv_end && o.ev_inv_end[it]) e = hipEventRecord((hipEvent_t)o.ev_inv_end[it], hs);
+            }
             if (e == hipSuccess && fork) e = hipEventRecord((hipEvent_t)o.ev_join, hs);
             if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, (hipEvent_t)o.ev_gram, 0);
-            if (e == hipSuccess && ev_begin && ev_begin[it]) e = hipEventRecord((hipEvent_t)ev_begin[it], st);
-            if (e == hipSuccess)
+            if (e == hipSuccess) {
+                TimedDispatch td(ev_begin ? (hipEvent_t)ev_begin[it] : nullptr,
+                                 ev_end ? (hipEvent_t)ev_end[it] : nullptr);
                 e = launch_grad_partial(d, ms, cores, xs, idx, S, pF, c->m, c->prec, w + L.grad, L.gl, st);
-            if (e == hipSuccess && ev_end && ev_end[it]) e = hipEventRecord((hipEvent_t)ev_end[it], st);
+            }
             if (e == hipSuccess)
                 e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, loss, false, MutPtrs{}, MutPtrs{}, c->rule,
                                        dev_status, st);
@@ -558,10 +559,11 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                 e = launch_sweep_apply(d, ms, g, LossParts{}, nullptr, mcores, acc, c->rule, dev_status, w + L.upd,
                                        L.ul, fused, st);
         } else {
-            if (e == hipSuccess && ev_begin && ev_begin[it]) e = hipEventRecord((hipEvent_t)ev_begin[it], st);
-            if (e == hipSuccess)
+            if (e == hipSuccess) {
+                TimedDispatch td(ev_begin ? (hipEvent_t)ev_begin[it] : nullptr,
+                                 ev_end ? (hipEvent_t)ev_end[it] : nullptr);
                 e = launch_grad_partial(d, ms, cores, xs, idx, S, pF, c->m, c->prec, w + L.grad, L.gl, st);
-            if (e == hipSuccess && ev_end && ev_end[it]) e = hipEventRecord((hipEvent_t)ev_end[it], st);
+            }
             if (e != hipSuccess) break;
             if (c->scaled) {   // RR > 128: Cholesky path
                 e = launch_grad_reduce(d, ms, w + L.grad, L.gl, g, loss, false, MutPtrs{}, MutPtrs{}, c->rule,

@@ -242,10 +242,10 @@ hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
         const size_t shm = (size_t)(TF * RRp + TI * RRp + TI * (TF + 1) + TF + 1) * 8 + TF * 16;
         if (d.x_dtype != TR_F64) return hipErrorInvalidValue;
         if (!allow_lds(reinterpret_cast<const void*>(&k_grad_partial<double, double>), shm)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_grad_partial<double, double>), grid, dim3(256), shm, st, d, ms, cores, xs,
-                           idx, static_cast<const double*>(S), pF, m, L.groups, L.row_tiles, RRp,
-                           reinterpret_cast<double*>(w + L.gpart_off),
-                           reinterpret_cast<double*>(w + L.lpart_off), maxIRR);
+        launch_timed(k_grad_partial<double, double>, grid, dim3(256), shm, st, d, ms, cores, xs, idx,
+                     static_cast<const double*>(S), pF, m, L.groups, L.row_tiles, RRp,
+                     reinterpret_cast<double*>(w + L.gpart_off), reinterpret_cast<double*>(w + L.lpart_off),
+                     maxIRR);
     } else if (prec == TR_PREC_BF16 || prec == TR_PREC_F16) {
         return launch_grad_mixed(d, ms, cores, xs, idx, static_cast<const float*>(S), pF, m, prec, L.groups,
                                  L.row_tiles, reinterpret_cast<float*>(w + L.gpart_off),

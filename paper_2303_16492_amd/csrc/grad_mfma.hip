@@ -252,8 +252,8 @@ static hipError_t launch_ctf(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, 
     int rr_fixed = d.R[0] * d.R[1 % d.N];
     for (int k = 1; k < d.N; ++k)
         if (d.R[k] * d.R[(k + 1) % d.N] != rr_fixed) rr_fixed = 0;
-    hipLaunchKernelGGL((k_grad_mfma_f32<TX, CT, TF>), grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m,
-                       groups, row_tiles, gp, lp, maxIRR, rr_fixed);
+    launch_timed(k_grad_mfma_f32<TX, CT, TF>, grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
+                 row_tiles, gp, lp, maxIRR, rr_fixed);
     return hipGetLastError();
 }
 

@@ -282,8 +282,8 @@ static hipError_t launch_mx_ct(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
                                int maxIRR, hipStream_t st) {
     constexpr size_t shm = MixGeom<CT>::lds();
     if (!allow_lds(reinterpret_cast<const void*>(&k_grad_mixed<T16, TX, CT>), shm)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_grad_mixed<T16, TX, CT>), grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
-                       row_tiles, gp, lp, maxIRR);
+    launch_timed(k_grad_mixed<T16, TX, CT>, grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
+                 row_tiles, gp, lp, maxIRR);
     return hipGetLastError();
 }
 

@@ -1,9 +1,36 @@
 // Internal launchers shared by the C-ABI wrappers and the multi-step driver.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 namespace trk {
+
+// Start/stop events carried by the next timed dispatch of this host thread
+// (set for one launcher call by a TimedDispatch scope).  The dispatch packet
+// records them itself (hipExtLaunchKernelGGL), so their elapsed time is the
+// kernel's execution alone, without the queueing around it.
+struct DispatchEvents {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+inline thread_local DispatchEvents g_dispatch_events;
+struct TimedDispatch {
+    TimedDispatch(hipEvent_t t0, hipEvent_t t1) { g_dispatch_events = DispatchEvents{t0, t1}; }
+    ~TimedDispatch() { g_dispatch_events = DispatchEvents{}; }
+    TimedDispatch(const TimedDispatch&) = delete;
+    TimedDispatch& operator=(const TimedDispatch&) = delete;
+};
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, size_t shm, hipStream_t st, Args... args) {
+    DispatchEvents& ev = g_dispatch_events;
+    if (ev.t0 || ev.t1) {
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, st, ev.t0, ev.t1, 0u, args...);
+        ev = DispatchEvents{};
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+    }
+}
 
 // Fiber source: the tensor in the strides of the descriptor, and optional
 // mode-major replicas (X_[n] column-major) that make every fiber contiguous.

@@ -612,8 +612,8 @@ hipError_t launch_sweep_inverse(const tr_desc& d, ModeSrc ms, const double* gram
 #define TRK_SWEEP(NTV)                                                                                          \
     do {                                                                                                        \
         const size_t dyn = allow_lds(reinterpret_cast<const void*>(&k_sweep<NTV>), reserve) ? reserve : 0;     \
-        hipLaunchKernelGGL(k_sweep<NTV>, dim3(1), dim3(256), dyn, st, d, ms, gram, damping, rank_tol, hm, \
-                           flag, status);                                                               \
+        launch_timed(k_sweep<NTV>, dim3(1), dim3(256), dyn, st, d, ms, gram, damping, rank_tol, hm, flag,   \
+                     status);                                                                         \
     } while (0)
     switch (nt) {
         case 1: TRK_SWEEP(1); break;
