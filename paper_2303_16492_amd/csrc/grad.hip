@@ -47,6 +47,8 @@ __global__ __launch_bounds__(256) void k_grad_partial(tr_desc d, ModeSrc ms, Ptr
                                                       int groups, int row_tiles_max, int RRp,
                                                       TC* __restrict__ gpart,
                                                       double* __restrict__ lpart, int maxIRR) {
+    int rtile, grp;
+    if (!xcd_tile_group(row_tiles_max, groups, rtile, grp)) return;
     constexpr int TI = GradCfg<TC>::TI, TF = GradCfg<TC>::TF;
     constexpr int MAXO = TI * kMaxRR / 256;
     uint64_t t;
@@ -55,8 +57,7 @@ __global__ __launch_bounds__(256) void k_grad_partial(tr_desc d, ModeSrc ms, Ptr
     const int N = d.N;
     const int In = d.I[n];
     const int RR = d.R[n] * d.R[ring_next(n, N)];
-    const int i0 = blockIdx.x * TI;
-    const int grp = blockIdx.y;
+    const int i0 = rtile * TI;
     if (i0 >= In) return;
     const int tid = threadIdx.x;
 
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void k_grad_partial(tr_desc d, ModeSrc ms, Ptr
     }
     __shared__ double red[4];
     const double tot = block_sum(lsum, red);
-    if (tid == 0) lpart[(int64_t)grp * row_tiles_max + blockIdx.x] = tot;
+    if (tid == 0) lpart[(int64_t)grp * row_tiles_max + rtile] = tot;
 }
 
 // Fixed-order sum of the partials; optional plain update G += rule(-g).
@@ -234,7 +235,7 @@ hipError_t launch_grad_partial(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
                                const GradWs& L, hipStream_t st) {
     const Shape sh = shape_of(d);
     const int RRp = sh.maxRR | 1;   // odd row pitch: rows of sG/sS fall in different LDS banks
-    const dim3 grid(L.row_tiles, L.groups);
+    const dim3 grid(xcd_grid(L.row_tiles, L.groups));
     char* w = static_cast<char*>(ws);
     const int maxIRR = sh.maxI * sh.maxRR;
     if (d.core_dtype == TR_F64) {
@@ -282,7 +283,9 @@ hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, cons
 // ------------------------------------------------------------------ Gram --
 // gram[c][c'] = sum_f S[f][c] S[f][c'] / (m J_n pF_f), products and sums in
 // FP64 from the stored S.  Blocks take the lower-triangular 32 x 32 tiles
-// of the RR x RR output times groups of samples: a block fetches its
+// of the RR x RR output times groups of samples (the tiles of one group on
+// one XCD, so the group's rows of S come from that XCD's L2 after the first
+// tile fetched them): a block fetches its
 // samples' S columns and weights in one batch (FP32 S stays FP32 in LDS),
 // then each wavefront accumulates one 16 x 16 quadrant of the tile on the
 // FP64 matrix cores.  A second kernel adds the
@@ -315,7 +318,8 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
         m = d.I[n];
     }
     const int tpd = (RR + kGramT - 1) / kGramT;
-    const int tile = blockIdx.x;
+    int tile, grp;
+    if (!xcd_tile_group(tiles_max, groups, tile, grp)) return;
     if (tile >= tpd * (tpd + 1) / 2) return;
     int ct, et;
     gram_tile(tile, ct, et);
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
     const int tid = threadIdx.x;
     const double wbase = pF ? 1.0 / ((double)m * (double)J_of(d, n)) : 1.0;
     const int per = (m + groups - 1) / groups;
-    const int fb = blockIdx.y * per, fe = min(m, fb + per);
+    const int fb = grp * per, fe = min(m, fb + per);
     // wavefront w computes the 16 x 16 quadrant (qr, qc) of the tile on the
     // FP64 matrix cores, K = 4 samples per instruction (lane l: A[l % 16][l / 16],
     // B[l / 16][l % 16], D[4 j + l / 16][l % 16])
@@ -366,13 +370,12 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
     }
-    double* out = part + (int64_t)blockIdx.y * maxRR2;
+    double* out = part + (int64_t)grp * maxRR2;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int c = c0 + 16 * qr + 4 * j + lk, e = e0 + 16 * qc + lc;
         if (c < RR && e < RR) out[(int64_t)c * RR + e] = acc[j];
     }
-    (void)tiles_max;
 }
 
 // gram = sum of the group partials in group order; entries above the
@@ -411,8 +414,10 @@ GramWs gram_ws_layout(const tr_desc& d, int m) {
     const int tpd = (sh.maxRR + kGramT - 1) / kGramT;
     L.tiles = tpd * (tpd + 1) / 2;
     // at most one block per CU (256), so that every block runs in the first
-    // and only round; at least 16 samples per group
-    int groups = 256 / L.tiles;
+    // and only round: with the XCD-aware order (a group's tiles on one XCD
+    // of 32 CUs) a multiple of 8 groups with at most 32 blocks per XCD;
+    // at least 16 samples per group
+    int groups = L.tiles <= 32 ? 8 * (32 / L.tiles) : 256 / L.tiles;
     const int gmax = (m + 15) / 16;
     groups = groups > gmax ? gmax : groups;
     groups = groups < 1 ? 1 : groups;
@@ -429,7 +434,7 @@ hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double
     const Shape sh = shape_of(d);
     const int maxRR2 = sh.maxRR * sh.maxRR;
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + L.part_off);
-    const dim3 grid(L.tiles, L.groups);
+    const dim3 grid(xcd_grid(L.tiles, L.groups));
     if (d.core_dtype == TR_F64)
         hipLaunchKernelGGL(k_gram_partial<double>, grid, dim3(256), 0, st, d, ms,
                            static_cast<const double*>(S), pF, m, L.groups, L.tiles, part, maxRR2, rows);

@@ -31,13 +31,15 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
                                                        const double* __restrict__ pF, int m, int groups,
                                                        int row_tiles_max, float* __restrict__ gpart,
                                                        double* __restrict__ lpart, int maxIRR, int rr_fixed) {
+    int rtile, sgrp;
+    if (!xcd_tile_group(row_tiles_max, groups, rtile, sgrp)) return;
     const int N = d.N;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     constexpr int SB = (16 * CT + 63) / 64;   // 64-column strips of a staged row
     constexpr int EP = TF + 4;   // row pitch of the staged E tile
     const int nchunks = (m + TF - 1) / TF;
     const int cpg = (nchunks + groups - 1) / groups;
-    const int cbeg = blockIdx.y * cpg, cend = min(nchunks, cbeg + cpg);
+    const int cbeg = sgrp * cpg, cend = min(nchunks, cbeg + cpg);
     // The next chunk's operands are held in registers until its turn: S rows
     // (TF / 4 per wavefront), the sample's indices and probability (every
     // thread loads those of sample tid % TF; the first TF use them).  Clamped
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
     // move the accumulators between registers around every instruction.
     constexpr int KQ = 4 * CT, RRT = 16 * CT;
     constexpr int RRs = mf_pitch(RRT);
-    const int i0 = blockIdx.x * kMfTI;
+    const int i0 = rtile * kMfTI;
     if (i0 >= In) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
             }
         }
     }
-    float* out = gpart + (int64_t)blockIdx.y * maxIRR;
+    float* out = gpart + (int64_t)sgrp * maxIRR;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
         const int col = 16 * c + lr;
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
     }
     __shared__ double red[4];
     const double tot = block_sum(lsum, red);
-    if (tid == 0) lpart[(int64_t)blockIdx.y * row_tiles_max + blockIdx.x] = tot;
+    if (tid == 0) lpart[(int64_t)sgrp * row_tiles_max + rtile] = tot;
 }
 
 template <int CT, int TF>
@@ -299,7 +301,7 @@ hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc x
                                 const float* S, const double* pF, int m, int groups, int row_tiles, float* gp,
                                 double* lp, int tf, hipStream_t st) {
     const Shape sh = shape_of(d);
-    const dim3 grid(row_tiles, groups);
+    const dim3 grid(xcd_grid(row_tiles, groups));
     const int maxIRR = sh.maxI * sh.maxRR;
     switch (d.x_dtype) {
         case TR_F32:

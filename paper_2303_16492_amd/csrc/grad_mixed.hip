@@ -58,6 +58,8 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
                                                     const double* __restrict__ pF, int m, int groups,
                                                     int row_tiles_max, float* __restrict__ gpart,
                                                     double* __restrict__ lpart, int maxIRR) {
+    int rtile, sgrp;
+    if (!xcd_tile_group(row_tiles_max, groups, rtile, sgrp)) return;
     typedef MixGeom<CT> Gm;
     typedef typename Mf16<T16>::v8 v8;
     constexpr int KS = Gm::KS, KP = Gm::KP, NC = Gm::NC, SB = Gm::SB;
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
     const int N = d.N;
     const int In = d.I[n];
     const int RR = d.R[n] * d.R[ring_next(n, N)];
-    const int i0 = blockIdx.x * kMxTI;
+    const int i0 = rtile * kMxTI;
     if (i0 >= In) return;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
 
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
     const double wbase = 1.0 / ((double)m * (double)J_of(d, n));
     const int nchunks = (m + kMxTF - 1) / kMxTF;
     const int cpg = (nchunks + groups - 1) / groups;
-    const int cbeg = blockIdx.y * cpg, cend = min(nchunks, cbeg + cpg);
+    const int cbeg = sgrp * cpg, cend = min(nchunks, cbeg + cpg);
     const int erow = 16 * w + 4 * lk;
 
     for (int ch = cbeg; ch < cend; ++ch) {
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
             }
         }
     }
-    float* out = gpart + (int64_t)blockIdx.y * maxIRR;
+    float* out = gpart + (int64_t)sgrp * maxIRR;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
         const int col = 16 * c + lr;
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(256) void k_grad_mixed(tr_desc d, ModeSrc ms, Ptrs 
     }
     __shared__ double red[4];
     const double tot = block_sum(lsum, red);
-    if (tid == 0) lpart[(int64_t)blockIdx.y * row_tiles_max + blockIdx.x] = tot;
+    if (tid == 0) lpart[(int64_t)sgrp * row_tiles_max + rtile] = tot;
 }
 
 template <typename T16, typename TX, int CT>
@@ -313,7 +315,7 @@ hipError_t launch_grad_mixed(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, 
                              const double* pF, int m, int prec, int groups, int row_tiles, float* gp, double* lp,
                              hipStream_t st) {
     const Shape sh = shape_of(d);
-    const dim3 grid(row_tiles, groups);
+    const dim3 grid(xcd_grid(row_tiles, groups));
     const int maxIRR = sh.maxI * sh.maxRR;
     if (prec == TR_PREC_BF16) {
         if (d.x_dtype == TR_F32)

@@ -60,6 +60,30 @@ hipError_t launch_sample_subchain_mode(const tr_desc& d, ModeSrc ms, int m, CdfP
                                        int32_t* idx, double* pF, void* S, int sample_mode,
                                        bool do_subchain, hipStream_t st);
 
+// Row tile and sample group of a gradient block, XCD-aware.  Workgroups go
+// to the eight XCDs round-robin by linear id (block b on XCD b mod 8), each
+// with its own L2; the T row tiles of a sample group take consecutive slots
+// of one XCD, so the group's rows of S are fetched into that L2 once and
+// read from there by the other tiles.  With fewer than eight groups (XCDs
+// would idle) the blocks keep the plain order.  Grid: xcd_grid(T, G)
+// blocks; false for the padding blocks past the last group (they exit at
+// once).
+inline unsigned xcd_grid(int T, int G) {
+    return G >= 8 ? 8u * (unsigned)T * (unsigned)((G + 7) / 8) : (unsigned)(T * G);
+}
+__device__ inline bool xcd_tile_group(int T, int G, int& tile, int& grp) {
+    const int b = (int)blockIdx.x;
+    if (G < 8) {
+        grp = b / T;
+        tile = b - grp * T;
+        return true;
+    }
+    const int slot = b >> 3, gl = slot / T;
+    tile = slot - gl * T;
+    grp = (b & 7) + 8 * gl;
+    return grp < G;
+}
+
 // a5/a6: partial gradients and loss.  Layout of the workspace returned by
 // grad_ws_layout.
 struct GradWs {
