@@ -211,8 +211,13 @@ GradWs grad_ws_layout(const tr_desc& d, int m, int prec) {
     L.ti = f64 ? GradCfg<double>::TI : 64;   // FP32 runs the matrix-core kernel (64-row tiles)
     L.tf = f64 ? GradCfg<double>::TF : 64;
     L.row_tiles = (sh.maxI + L.ti - 1) / L.ti;
-    // about one block per CU: fewer partial slices to add afterwards
+    // about one block per CU (two for FP64): fewer partial slices to add
+    // afterwards.  With the XCD-aware order (a group's row tiles on one XCD
+    // of 32 CUs) a multiple of 8 groups with at most that many blocks per
+    // XCD, so that no XCD takes a second round of blocks.
+    const int per_xcd = f64 ? 64 : 32;
     int groups = ((f64 ? 512 : 256) + L.row_tiles - 1) / L.row_tiles;
+    if (L.row_tiles <= per_xcd && groups >= 8) groups = 8 * (per_xcd / L.row_tiles);
     // FP32 with R_n R_{n+1} <= 128: chunks of 128 samples when that still
     // gives at least half of those blocks
     if (!f64 && sh.maxRR <= 128 && 2 * ((m + 127) / 128) >= groups) L.tf = 128;
