@@ -28,8 +28,14 @@ def _case(seed, N, I, R, B, snr_db=30.0):
     return I, R, cores, idx, x
 
 
+# the C4 shape; mixed ranks under each rank bound 4, 8, 12 and 16 of the
+# backward's padded slices; a gradient slice too large for LDS (700 rows,
+# accumulated in global memory); 50000 entries (several index slabs per
+# workgroup); B = 1
 CASES = [(5, 32, 8, 8192), (3, [7, 9, 5], [2, 3, 4], 100), (4, [6, 5, 7, 4], [3, 1, 2, 5], 1),
-         (2, [11, 13], [12, 7], 333), (6, [3, 2, 4, 3, 2, 3], [2, 2, 3, 1, 2, 2], 777)]
+         (2, [11, 13], [12, 7], 333), (6, [3, 2, 4, 3, 2, 3], [2, 2, 3, 1, 2, 2], 777),
+         (3, [9, 8, 10], [16, 13, 15], 517), (3, [700, 40, 50], [4, 6, 5], 2000),
+         (3, [5, 6, 7], [2, 3, 2], 50000)]
 
 
 @pytest.mark.parametrize("N,I,R,B", CASES)
@@ -89,3 +95,31 @@ def test_backward_is_bitwise_reproducible():
     b = api.tr_entry_bwd(desc, dc, didx, resid, 8192)
     for u, v in zip(a, b):
         assert torch.equal(u, v)
+
+
+def test_invalid_indices_give_nan_residuals_and_no_gradient():
+    """Entries with an index outside the tensor: NaN residual in the forward,
+    no contribution in the backward (whose 1/B still counts every entry)."""
+    N, I, R, B = 3, [7, 9, 5], [2, 3, 4], 300
+    I, R, cores, idx, x = _case(5, N, I, R, B)
+    bad = np.array([0, 17, 123, 299])
+    idx = idx.copy()
+    idx[bad[0], 0] = -1
+    idx[bad[1], 1] = I[1]
+    idx[bad[2], 2] = I[2] + 5
+    idx[bad[3], 0] = -7
+    good = np.setdiff1d(np.arange(B), bad)
+    desc = api.make_desc(I, R, torch.float32)
+    dc = [to_dev(unfold(c), torch.float32) for c in cores]
+    say("entry invalid indices")
+    resid, _ = api.tr_entry_fwd(desc, dc, to_dev(idx, torch.int32), to_dev(x, torch.float32), B)
+    r = resid.cpu().numpy()
+    assert np.all(np.isnan(r[bad]))
+    _, rref = entry.entry_loss(cores, idx[good], x[good])
+    assert rel(r[good], rref) < 1e-5
+    grads = api.tr_entry_bwd(desc, dc, to_dev(idx, torch.int32), resid, B)
+    gref = entry.entry_grads(cores, idx[good], x[good])   # mean over the valid entries
+    for k in range(N):
+        g = grads[k].cpu().numpy()
+        assert np.all(np.isfinite(g))
+        assert rel(g, unfold(gref[k]) * (len(good) / B)) < 1e-5
