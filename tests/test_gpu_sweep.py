@@ -75,8 +75,12 @@ def test_full_batch_sweep_matches_oracle(method, I, R, dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("law", ["U", "L", "E"])
 def test_als_sampled_sweep_matches_oracle(law, dtype):
-    if dtype == torch.float32 and law != "U":
-        pytest.skip("laws L and E: FP32 weights may differ from the FP64 oracle's in their last units")
+    """Two TR-ALS-Sampled sweeps against the oracle.  Under laws L and E the
+    weights are recomputed from the updated cores each block; GPU and
+    oracle weights may differ in their last units of 2^40 (and in FP32 by
+    the cores' rounding), which moves the CDF and the Lemire bound by a few
+    units: a draw changes only if a variate lands that close to a boundary,
+    and p_F moves by that relative amount."""
     I, R = [30, 25, 28], [3, 4, 3]
     X, init = _case(I, R, dtype, seed=5)
     m = 200
