@@ -25,9 +25,9 @@
 // The fourth wavefront owns no tiles: it works one block ahead.  During
 // step q it forms pivot block q+1 as it will be after step q (the Schur
 // complement D - C^T B C of the block as published before step q, C the
-// pivot rows of step q at its columns) and sweeps that 8 x 8 block in
-// registers, so the pivot inverse of every step after the first is ready
-// when the step starts.  One barrier per step publishes the next pivot
+// pivot rows of step q at its columns, on the vector units) and sweeps that
+// 8 x 8 block in registers, so the pivot inverse of every step after the
+// first is ready when the step starts.  One barrier per step publishes the next pivot
 // rows, the next pivot inverse and its verdict together.
 #include "internal.hpp"
 
@@ -133,9 +133,9 @@ __device__ __forceinline__ void sweep8_pivot(double& a, double& dk, bool& good, 
     }
 }
 
-__device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw, double tol) {
+// The sweep of the block whose entry (i, j) lane 8 i + j holds in ``a``.
+__device__ __forceinline__ bool sweep8_reg(double a, double* Bw, double tol) {
     const int l = threadIdx.x & 63, i = l >> 3, j = l & 7;
-    double a = D8[i * 8 + j];
     const double p = readlane_f64(a, 0);
     double dk = rcp_nr(p);
     bool good = (p > tol) && isfinite(p);
@@ -149,6 +149,11 @@ __device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw
     sweep8_pivot<7>(a, dk, good, i, j, tol);
     if (j <= i) Bw[tri8(i) + j] = a;
     return good;
+}
+
+__device__ __forceinline__ bool sweep8(const double* __restrict__ D8, double* Bw, double tol) {
+    const int l = threadIdx.x & 63;
+    return sweep8_reg(D8[(l >> 3) * 8 + (l & 7)], Bw, tol);
 }
 
 // Pivot rows of block q = 2 tq + HQ of the current matrix, minus the
@@ -237,32 +242,49 @@ __device__ __forceinline__ dbl4 update_tile(const dbl4& a, const double* __restr
 
 // Pivot block q+1 after step q from the block D as published before step q:
 // Dn = D - C^T B C with C the pivot rows of step q at the block's columns
-// (Schur complement), on the matrix cores.
+// (Schur complement), on the vector units, entry (i, j) in lane 8 i + j (the
+// layout of sweep8_reg): w = B C (lane (i, j): row i of B, column j of C),
+// exchanged through ``Wt`` (64 doubles of the factor wavefront's own), then
+// (C^T w)(i, j) from column i of C and column j of w.  Two dependent 8-term
+// products, and the block goes straight into the sweep's registers.
 template <int NT>
-__device__ __forceinline__ void next_pivot_block(const double* __restrict__ Vt, const double* __restrict__ Bw,
-                                                 const double* __restrict__ D, int q, double* Dn) {
+__device__ __forceinline__ double next_pivot_entry(const double* __restrict__ Vt, const double* __restrict__ Bw,
+                                                   const double* __restrict__ D, int q, double* Wt) {
     constexpr int NP = 16 * NT;
-    const int l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
-    double a1[2], c[2];
+    const int l = threadIdx.x & 63, i = l >> 3, j = l & 7;
+    const int c0 = 8 * (q + 1);
+    double b[8], c[8];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const int j = 4 * s + lr;
-        const int hi = j > lc ? j : lc, lo = j > lc ? lc : j;
-        a1[s] = lc < 8 ? -Bw[tri8(hi & 7) + (lo & 7)] : 0.0;
-        c[s] = lc < 8 ? Vt[j * NP + 8 * (q + 1) + (lc & 7)] : 0.0;
+    for (int k = 0; k < 8; ++k) {
+        b[k] = -Bw[tri8(i > k ? i : k) + (i > k ? k : i)];
+        c[k] = Vt[k * NP + c0 + j];
     }
-    double dv[2];
+    const double dv = D[i * 8 + j];
+    double w0 = 0.0, w1 = 0.0;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) dv[j] = D[(4 * j + lr) * 8 + (lc & 7)];
-    const dbl4 zero = {0.0, 0.0, 0.0, 0.0};
-    dbl4 w = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[0], c[0], zero, 0, 0, 0);
-    w = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[1], c[1], w, 0, 0, 0);
-    dbl4 r = __builtin_amdgcn_mfma_f64_16x16x4f64(c[0], w[0], zero, 0, 0, 0);
-    r = __builtin_amdgcn_mfma_f64_16x16x4f64(c[1], w[1], r, 0, 0, 0);
-    if (lc < 8) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) Dn[(4 * j + lr) * 8 + lc] = dv[j] - r[j];
+    for (int k = 0; k < 8; k += 2) {
+        w0 = __builtin_fma(b[k], c[k], w0);
+        w1 = __builtin_fma(b[k + 1], c[k + 1], w1);
     }
+    Wt[l] = w0 + w1;
+    // this wavefront's LDS stores complete before its own reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double ci[8], wk[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        ci[k] = Vt[k * NP + c0 + i];
+        wk[k] = Wt[8 * k + j];
+    }
+    double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+        r0 = __builtin_fma(ci[k], wk[k], r0);
+        r1 = __builtin_fma(ci[k + 1], wk[k + 1], r1);
+    }
+    return dv - (r0 + r1);
 }
 
 // h + eta I into the wavefront's tiles (identity on the padding), every
@@ -319,7 +341,7 @@ struct SweepShared {
     double Vt[2][8 * 128];   // pivot rows of step q, by q & 1
     double Bw[2][40];        // packed -B of step q, by q & 1
     double D8[2][64];        // pivot block q+1 as published before step q, by (q + 1) & 1
-    double Dn[64];           // the factor wavefront's pivot block after the update
+    double Dn[64];           // factor wavefront: pivot block 0 in the prologue, then the exchange of w = B C
     double red[kSweepWaves];
     int good[2];             // verdict of the factorisation of step q's pivot block, by q & 1
 };
@@ -336,12 +358,8 @@ __device__ __forceinline__ bool sweep_step(dbl4 (&acc)[tpw<NT>()], SweepShared& 
     const bool more = q + 1 < npiv;
     if (WV == kFactorWave) {
         if (more) {
-            next_pivot_block<NT>(Vt, sh.Bw[HQ], sh.D8[HQ ^ 1], q, sh.Dn);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const bool g = sweep8(sh.Dn, sh.Bw[HQ ^ 1], tol);
+            const double a = next_pivot_entry<NT>(Vt, sh.Bw[HQ], sh.D8[HQ ^ 1], q, sh.Dn);
+            const bool g = sweep8_reg(a, sh.Bw[HQ ^ 1], tol);
             if ((threadIdx.x & 63) == 0) sh.good[HQ ^ 1] = g ? 1 : 0;
         }
     } else {
