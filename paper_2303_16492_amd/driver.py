@@ -157,7 +157,7 @@ class TRBatch:
     loss estimates and status words."""
 
     VARIANTS = ((32, 4), (32, 8), (64, 4), (64, 8))
-    SPLITS = (1, 4)
+    SPLITS = (1, 4, 8, 16)
 
     def __init__(self, problems, device="cuda"):
         self.count = len(problems)

@@ -65,7 +65,7 @@ def oracle_steps(host, m, steps, rule_kind="fixed", alpha=0.05, eta=0.02):
     return outs
 
 
-@pytest.mark.parametrize("splits", [1, 4])
+@pytest.mark.parametrize("splits", [1, 4, 16])
 @pytest.mark.parametrize("rule_kind", ["fixed", "adagrad"])
 def test_one_step_matches_oracle(rule_kind, splits):
     inst = small_instances(1, 6, big=True)
@@ -89,7 +89,7 @@ def test_one_step_matches_oracle(rule_kind, splits):
         assert abs(float(B.loss[p]) - losses[-1]) <= TOL16 * abs(losses[-1])
 
 
-@pytest.mark.parametrize("splits", [1, 4])
+@pytest.mark.parametrize("splits", [1, 4, 16])
 def test_each_problem_equals_itself_alone(splits):
     inst = small_instances(2, 5)
     probs, _ = build(inst, m=70, rule_kind="adagrad")
@@ -125,7 +125,7 @@ def test_tile_variants_agree():
                 assert rel(b, a) < 1e-5
 
 
-@pytest.mark.parametrize("splits", [1, 4])
+@pytest.mark.parametrize("splits", [1, 4, 16])
 def test_graph_replay_equals_eager_bitwise(splits):
     inst = small_instances(4, 4)
     pa, _ = build(inst, m=64, rule_kind="adagrad")
@@ -180,7 +180,7 @@ def unfold_back(G2, Rk, Rk1):
     return np.ascontiguousarray(G2.reshape(G2.shape[0], Rk1, Rk).transpose(2, 0, 1))
 
 
-@pytest.mark.parametrize("splits", [1, 4])
+@pytest.mark.parametrize("splits", [1, 4, 16])
 def test_full_batch_step_at_bench_configuration(splits):
     """The 64-problem workload the benchmark times (orders 3-5, sizes 16-128,
     ranks 3-12, FP16 tensors, m = 1024, AdaGrad) in its launch configuration
