@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kOptBlock) void k_opt_quantize(tr_desc d, ModeSrc m
     sc[threadIdx.x] = wv;
     __syncthreads();
     for (int o = 1; o < kOptBlock; o <<= 1) {
-        const uint64_t v = threadIdx.x >= o ? sc[threadIdx.x - o] : 0ull;
+        const uint64_t v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0ull;
         __syncthreads();
         sc[threadIdx.x] += v;
         __syncthreads();
