@@ -74,7 +74,7 @@ typedef enum {
     TR_E_ALIGN = -4,        /* pointer not aligned to its element size   */
     TR_E_WORKSPACE = -5,    /* workspace smaller than required           */
     TR_E_HIP = -6,          /* a HIP launch or runtime call failed       */
-    TR_E_UNSUPPORTED = -7   /* valid request this build does not serve   */
+    TR_E_UNSUPPORTED = -7   /* valid request this library does not serve */
 } tr_status;
 
 /* Sticky device status bits. */

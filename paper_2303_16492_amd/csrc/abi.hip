@@ -198,7 +198,7 @@ const char* tr_status_str(int32_t s) {
         case TR_E_ALIGN: return "pointer not aligned to its element size";
         case TR_E_WORKSPACE: return "workspace too small";
         case TR_E_HIP: return "HIP runtime or launch error";
-        case TR_E_UNSUPPORTED: return "request not supported by this build";
+        case TR_E_UNSUPPORTED: return "request not supported by this library";
         default: return "unknown status";
     }
 }
