@@ -540,7 +540,8 @@ def cpu_baseline(seconds, seed, I, R, kappa, m, alpha, threads=None):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scaled-illcond-n3-i400-r10.txt")
-KERNEL_SOURCE = {"k_sweep": "sweep.hip", "k_grad_mfma_f32": "grad_mfma.hip", "k_grad_mixed": "grad_mixed.hip"}
+KERNEL_SOURCE = {"k_sweep": "sweep.hip", "k_grad_mfma_f32": "grad_mfma.hip", "k_grad_mfma_f32w": "grad_mfma.hip",
+                 "k_grad_mixed": "grad_mixed.hip"}
 
 
 def measured_traffic(kernel):
@@ -821,10 +822,11 @@ def main():
     bytes_alg = I * m * 4 + m * RR * 4 + I * RR * 4  # fibers + sampled rows + core
     peak, unit = PEAK[args.prec]
     g_ach = flops / (main["grad_us"] * 1e-6) / 1e12
-    gkern = "k_grad_mfma_f32" if args.prec == "f32" else "k_grad_mixed"
+    # FP32: the 16-byte-operand form (R_n R_{n+1} = 100, one 128-sample chunk per sample group)
+    gkern = "k_grad_mfma_f32w" if args.prec == "f32" else "k_grad_mixed"
     grad_roof = {"bound": "mfma", "achieved": round(g_ach, 3), "peak": peak, "unit": unit,
                  "frac": round(g_ach / peak, 5), "traffic": measured_traffic(gkern),
-                 "kernel": "k_grad_mfma_f32" if args.prec == "f32" else "k_grad_mixed",
+                 "kernel": gkern,
                  "kernel_avg_us": round(main["grad_us"], 3), "flops_per_launch": flops,
                  "alg_bytes_per_launch": bytes_alg,
                  "alg_hbm_gbs": round(bytes_alg / (main["grad_us"] * 1e-6) / 1e9, 1)}

@@ -240,6 +240,357 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
     if (tid == 0) lpart[(int64_t)sgrp * row_tiles_max + rtile] = tot;
 }
 
+// ------------------------------------------------------------------------
+// Wide-operand form, for R_n R_{n+1} a multiple of 4 in (32, 16 CT] (CT <= 8)
+// with S and G_{n(2)} 16-byte aligned.  The kernel above is bound by the
+// number of memory instructions, not by bytes or matrix-core time: one
+// float per lane per load, LDS write and LDS read.  Here every one of them
+// moves 16 bytes:
+//   staging   LDS rows of S have the compile-time pitch SP = 4 Q words,
+//             Q = 4 CT + 1 pieces of 16 bytes (Q odd: eight rows read
+//             together by eight lanes start in distinct groups of four banks;
+//             a run-time pitch would cost a register per operand address).
+//             Piece k of staged row f is piece f RR/4 + k of the chunk's
+//             rows in memory, so pieces past RR/4 continue into the next row
+//             and the staged area is a flat copy: piece e at byte 16 e, moved
+//             by direct memory-to-LDS loads (no registers, no LDS stores).
+//   GEMM1     K order: lane group lk (= l / 16) owns k = 4 CT lk + q for its K
+//             steps q < 4 CT, so four consecutive steps are one 16-byte read
+//             of an S row and the A operand (the lane's G row) is CT 16-byte
+//             loads; G is zero for k >= RR.
+//   GEMM2     output column of tile c and lane column lr: CW lr + c, so the B
+//             operands of one K step are CW consecutive floats of an S row;
+//             K order: lane group lk owns samples TF/4 lk + s, so the A operand
+//             (the residual, staged per wavefront as rows x samples) is read
+//             16 bytes at a time as well.  Columns >= RR are computed and
+//             dropped.
+// The residual never leaves its wavefront (no barrier between the products).
+// The products read up to 16 CT (GEMM1) and 16 CW (GEMM2) words from a row
+// start; the words of a row past RR (the next row's entries, staged pieces
+// past the last row, or the last piece of S where the addresses are
+// clamped) meet a zero of G or feed a dropped column, and every one is a
+// finite entry of S.  Rows past m hold such entries too; their residual is
+// zero.
+constexpr int kWideTF = 128;
+
+template <int CT>
+struct WideCfg {
+    static constexpr int TF = kWideTF;
+    static constexpr int CW = CT <= 4 ? 4 : 8;        // GEMM2 column tiles
+    static constexpr int Q = 4 * CT + 1;               // 16-byte pieces per staged row (odd)
+    static constexpr int SP = 4 * Q;                   // staged row pitch in words
+    static constexpr int TAIL = 16 * CW > SP ? 16 * CW - SP : 0;   // words read past the last row
+    // staged pieces: TF rows and the tail, in whole wavefront instructions
+    static constexpr int STAGE = (TF * Q + (TAIL + 3) / 4 + 63) / 64 * 64;
+    static constexpr int EP = TF + 4;                  // residual row pitch (EP / 4 odd)
+    static constexpr size_t shm() {
+        return (size_t)STAGE * 16 + (size_t)(4 * 16 * EP + TF) * 4 + (size_t)TF * 16 + 64;
+    }
+};
+
+__device__ __forceinline__ float4 mask4(float4 v, bool ok) {
+    const unsigned mk = ok ? 0xffffffffu : 0u;
+    return make_float4(__uint_as_float(__float_as_uint(v.x) & mk), __uint_as_float(__float_as_uint(v.y) & mk),
+                       __uint_as_float(__float_as_uint(v.z) & mk), __uint_as_float(__float_as_uint(v.w) & mk));
+}
+
+// Sum over a wavefront in a fixed order without LDS: pairs, quads, half
+// rows and rows by DPP lane moves, then the four row sums read from lanes
+// 0, 16, 32 and 48.  Valid in every lane.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_id) {
+    const long long b = __double_as_longlong(v);
+    int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    switch (ctrl_id) {
+        case 0: lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+        case 1: lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+        case 2: lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+        default: lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break; // row_mirror
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_f64(v, 0);
+    v += dpp_f64(v, 1);
+    v += dpp_f64(v, 2);
+    v += dpp_f64(v, 3);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// What the kernel needs of the step's mode, computed once on the host for
+// every mode: the element stride of each index in the fiber source (zero
+// for the mode itself, so an offset is the plain sum over all modes), the
+// sample weight's factor 1/(m J_n), and whether fibers are contiguous
+// whole 4-row groups at a 4-entry-aligned source.
+struct WideMode {
+    int64_t xs[kMaxOrder];
+    double wbase;
+    int32_t fast;
+};
+struct WideModes {
+    WideMode md[kMaxOrder];
+};
+
+template <typename TX, int CT>
+__global__ __launch_bounds__(256) void k_grad_mfma_f32w(tr_desc d, ModeSrc ms, Ptrs cores, XSrc xsrc,
+                                                        const int32_t* __restrict__ idx, const float* __restrict__ S,
+                                                        const double* __restrict__ pF, int m, int groups,
+                                                        int row_tiles_max, float* __restrict__ gpart,
+                                                        double* __restrict__ lpart, int maxIRR, int rr_fixed,
+                                                        WideModes tab) {
+    using C = WideCfg<CT>;
+    constexpr int TF = C::TF, CW = C::CW, EP = C::EP, SP = C::SP, NU = TF / 16, TQ = TF / 4;
+    int rtile, sgrp;
+    if (!xcd_tile_group(row_tiles_max, groups, rtile, sgrp)) return;
+    const int N = d.N;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    // One chunk of TF samples per sample group (the launcher has as many
+    // groups as chunks; a group past the last sample writes a zero partial).
+    const int f0 = sgrp * TF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* sS = reinterpret_cast<float*>(smem_raw);                 // [STAGE pieces]
+    float* sE = sS + 4 * C::STAGE;                                  // [4][16][EP]
+    float* sW = sE + 4 * 16 * EP;                                   // [TF], lane order
+    double* sL = reinterpret_cast<double*>(sW + TF);                // [TF], lane order
+    int64_t* sB = reinterpret_cast<int64_t*>(sL + TF);              // [TF], lane order
+    // The chunk's pieces of S (straight into LDS) and its samples' indices
+    // and probabilities go out first: before the step's mode is known when
+    // every mode has the same R_n R_{n+1}, and in one batch with the core
+    // rows otherwise, so that the block waits for memory once.  Clamped
+    // in-bounds addresses.
+    int ik[kMaxOrder];
+    double pf = 1.0;
+    const int wu = __builtin_amdgcn_readfirstlane(w);   // the wavefront index, in a scalar register
+    auto issue = [&](int RRl) {
+        const int q0 = RRl >> 2, base = f0 * q0, last = m * q0 - 1;   // < 2^30 pieces
+        // instruction c = 4 i + wu moves pieces 64 c .. 64 c + 63; this lane's
+        // piece e = 64 c + l is row f = e / Q, piece k = e % Q of that row,
+        // advanced by 256 pieces per instruction
+        int f = (64 * wu + l) / C::Q, k = (64 * wu + l) - f * C::Q;
+#pragma unroll
+        for (int i = 0; i < (C::STAGE / 64 + 3) / 4; ++i) {
+            const int c = 4 * i + wu;
+            if (c < C::STAGE / 64) {
+                int src = base + f * q0 + k;
+                src = src < last ? src : last;
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const float4*>(S) + src, sS + 4 * 64 * c, 16, 0, 0);
+            }
+            k += 256 % C::Q;
+            f += 256 / C::Q;
+            if (k >= C::Q) {
+                k -= C::Q;
+                ++f;
+            }
+        }
+        const int fi = f0 + (tid & (TF - 1));
+        const int64_t fc = fi < m ? fi : m - 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ik[k] = idx[fc * N + (k < N ? k : N - 1)];
+        if (N > 3) {
+#pragma unroll
+            for (int k = 3; k < kMaxOrder; ++k) ik[k] = idx[fc * N + (k < N ? k : N - 1)];
+        }
+        pf = pF[fc];
+    };
+    uint64_t t;
+    int n = 0;
+    if (rr_fixed <= 0) resolve_mode(ms, N, &t, &n);
+    issue(rr_fixed > 0 ? rr_fixed : d.R[n] * d.R[ring_next(n, N)]);
+    if (rr_fixed > 0) resolve_mode(ms, N, &t, &n);
+    const int In = d.I[n];
+    const int RR = d.R[n] * d.R[ring_next(n, N)];
+    const WideMode& wm = tab.md[n];
+    const int i0 = rtile * kMfTI;
+    if (i0 >= In) {
+        __builtin_amdgcn_s_waitcnt(0);   // no direct load outlives the block
+        return;
+    }
+    float* sEw = sE + w * 16 * EP;
+
+    // A operand of GEMM1: the lane's G row, K steps 4j..4j+3 in one piece
+    // (masked once the pieces of S are in LDS).
+    const float* Gn = static_cast<const float*>(cores.p[n]);
+    const int grow = i0 + 16 * w + lr, growc = grow < In ? grow : In - 1;
+    float4 ga[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        const int k0 = 4 * CT * lk + 4 * j;
+        ga[j] = *reinterpret_cast<const float4*>(Gn + (int64_t)growc * RR + (k0 < RR ? k0 : 0));
+    }
+    const TX* X = static_cast<const TX*>(xsrc.rep[n] ? xsrc.rep[n] : xsrc.X);
+    const int64_t xsn = xsrc.rep[n] ? 1 : d.x_stride[n];
+    const bool fast_fiber = wm.fast != 0;
+    const double wbase = wm.wbase, lbase = 0.5 / (double)m;
+    const int erow = 16 * w + 4 * lk;   // first of this lane's 4 D rows (block-local)
+
+    // Each sample's fiber offset and weights, stored in lane order (sample
+    // 16 u + r at slot 8 r + u) so that a lane's eight samples are adjacent.
+    if (tid < TF) {
+        const int f = f0 + tid;
+        bool ok = f < m;
+        int64_t off = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxOrder; ++k) {
+            if (k >= N) break;
+            if (k != n && (ik[k] < 0 || ik[k] >= d.I[k])) ok = false;
+            off += (int64_t)ik[k] * wm.xs[k];
+        }
+        off = ok ? off : 0;
+        const double rp = 1.0 / pf;
+        const int slot = 8 * (tid & 15) + (tid >> 4);
+        sB[slot] = ok ? off : 0;
+        sW[slot] = ok ? (float)(wbase * rp) : 0.f;
+        sL[slot] = ok ? lbase * rp : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < CT; ++j) ga[j] = mask4(ga[j], grow < In && 4 * CT * lk + 4 * j < RR);
+    __builtin_amdgcn_s_waitcnt(0);   // this wavefront's direct loads have landed
+    __syncthreads();
+    // fiber entries of this lane's 4 rows, in flight during GEMM1
+    float wv[NU];
+    int64_t bv[NU];
+#pragma unroll
+    for (int h = 0; h < NU / 4; ++h) {
+        const float4 q = *reinterpret_cast<const float4*>(sW + 8 * lr + 4 * h);
+        wv[4 * h] = q.x;
+        wv[4 * h + 1] = q.y;
+        wv[4 * h + 2] = q.z;
+        wv[4 * h + 3] = q.w;
+    }
+#pragma unroll
+    for (int h = 0; h < NU / 2; ++h) {
+        const longlong2 q = *reinterpret_cast<const longlong2*>(sB + 8 * lr + 2 * h);
+        bv[2 * h] = q.x;
+        bv[2 * h + 1] = q.y;
+    }
+    float xv[NU][4];
+    if (fast_fiber) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const bool ok4 = wv[u] != 0.f && i0 + erow < In;
+            load4(X + (ok4 ? bv[u] + i0 + erow : 0), xv[u]);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = i0 + erow + j;
+                const int64_t o = (wv[u] != 0.f && row < In) ? bv[u] + (int64_t)row * xsn : 0;
+                xv[u][j] = (float)to_f64(X[o]);
+            }
+        }
+    }
+    // GEMM1: P[erow + j][16u + lr], K step q of group lk is k = 4 CT lk + q
+    // (piece j of the K range outer, the 8 sample tiles inner: 32
+    // independent products per 8 reads)
+    // (piece j + 1's reads go out before piece j's products, in the order
+    // the scheduling groups keep)
+    __builtin_amdgcn_sched_barrier(0);
+    f32x4 p[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) p[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float* srow = sS + lr * SP + 4 * CT * lk;
+    float4 bc[NU], bn[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) bc[u] = *reinterpret_cast<const float4*>(srow + 16 * u * SP);
+    __builtin_amdgcn_sched_group_barrier(0x100, NU, 0);
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        if (j + 1 < CT) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) bn[u] = *reinterpret_cast<const float4*>(srow + 16 * u * SP + 4 * (j + 1));
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) p[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[j].x, bc[u].x, p[u], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) p[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[j].y, bc[u].y, p[u], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) p[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[j].z, bc[u].z, p[u], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) p[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[j].w, bc[u].w, p[u], 0, 0, 0);
+        if (j + 1 < CT) __builtin_amdgcn_sched_group_barrier(0x100, NU, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 4 * NU, 0);
+        if (j + 1 < CT) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) bc[u] = bn[u];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // E = X_F - P, scaled; loss estimate; E into the wavefront's rows
+    double lsum = 0.0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int fl = 16 * u + lr;
+        const float wf = wv[u];
+        const double lf = sL[8 * lr + u];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool ok = (i0 + erow + j < In) && wf != 0.f;
+            const float e = ok ? xv[u][j] - p[u][j] : 0.f;
+            lsum += (double)e * (double)e * lf;
+            sEw[(4 * lk + j) * EP + fl] = -e * wf;
+        }
+    }
+    // GEMM2: g[erow + j][CW lr + c] += sum_s E[.][TQ lk + s] S[TQ lk + s][.]
+    // (the residual rows are this wavefront's own: LDS operations of a
+    // wavefront complete in order, so no barrier)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);   // GEMM2's issue order below stays its own
+    f32x4 acc2[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) acc2[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // K step s + 1's operands are read before step s's products, and the
+    // scheduling groups keep that order (left alone, the compiler reads
+    // each step's operands right before they are used).
+    const float* erw = sEw + lr * EP + TQ * lk;
+    const float* scl = sS + (TQ * lk) * SP + CW * lr;
+    constexpr int RPS = CW / 4;   // 16-byte B reads per K step
+    float4 acur = *reinterpret_cast<const float4*>(erw), anxt = acur;
+    float4 bcur[RPS], bnxt[RPS];
+#pragma unroll
+    for (int h = 0; h < RPS; ++h) bcur[h] = *reinterpret_cast<const float4*>(scl + 4 * h);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1 + RPS, 0);
+#pragma unroll
+    for (int st = 0; st < TQ; ++st) {
+        if (st + 1 < TQ) {
+#pragma unroll
+            for (int h = 0; h < RPS; ++h) bnxt[h] = *reinterpret_cast<const float4*>(scl + (st + 1) * SP + 4 * h);
+            if ((st + 1) % 4 == 0) anxt = *reinterpret_cast<const float4*>(erw + (st + 1));
+        }
+        const float at = (st & 3) == 0 ? acur.x : (st & 3) == 1 ? acur.y : (st & 3) == 2 ? acur.z : acur.w;
+#pragma unroll
+        for (int h = 0; h < RPS; ++h) {
+            acc2[4 * h] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, bcur[h].x, acc2[4 * h], 0, 0, 0);
+            acc2[4 * h + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, bcur[h].y, acc2[4 * h + 1], 0, 0, 0);
+            acc2[4 * h + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, bcur[h].z, acc2[4 * h + 2], 0, 0, 0);
+            acc2[4 * h + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, bcur[h].w, acc2[4 * h + 3], 0, 0, 0);
+        }
+        if (st + 1 < TQ && (st + 1) % 4 == 0) __builtin_amdgcn_sched_group_barrier(0x100, RPS + 1, 0);
+        if (st + 1 < TQ && (st + 1) % 4 != 0) __builtin_amdgcn_sched_group_barrier(0x100, RPS, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, CW, 0);
+#pragma unroll
+        for (int h = 0; h < RPS; ++h) bcur[h] = bnxt[h];
+        if ((st + 1) % 4 == 0) acur = anxt;
+    }
+    float* out = gpart + (int64_t)sgrp * maxIRR;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int row = i0 + erow + j;
+#pragma unroll
+        for (int h = 0; h < CW / 4; ++h) {
+            const int col = CW * lr + 4 * h;
+            if (row < In && col < RR)
+                *reinterpret_cast<float4*>(out + (int64_t)row * RR + col) =
+                    make_float4(acc2[4 * h][j], acc2[4 * h + 1][j], acc2[4 * h + 2][j], acc2[4 * h + 3][j]);
+        }
+    }
+    __shared__ double red[4];
+    const double ws = wave_sum_dpp(lsum);
+    if (l == 0) red[w] = ws;
+    __syncthreads();
+    if (tid == 0) lpart[(int64_t)sgrp * row_tiles_max + rtile] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 template <int CT, int TF>
 static constexpr size_t grad_mfma_shm() {
     return (size_t)(TF * mf_pitch(16 * CT) + kMfTI * (TF + 4) + TF) * 4 + (size_t)TF * 16 + 64;
@@ -257,6 +608,72 @@ static hipError_t launch_ctf(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, 
     launch_timed(k_grad_mfma_f32<TX, CT, TF>, grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
                  row_tiles, gp, lp, maxIRR, rr_fixed);
     return hipGetLastError();
+}
+
+template <typename TX, int CT>
+static hipError_t launch_wide(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx, const float* S,
+                              const double* pF, int m, dim3 grid, int groups, int row_tiles, float* gp, double* lp,
+                              int maxIRR, hipStream_t st) {
+    constexpr size_t shm = WideCfg<CT>::shm();
+    if (!allow_lds(reinterpret_cast<const void*>(&k_grad_mfma_f32w<TX, CT>), shm)) return hipErrorInvalidValue;
+    int rr_fixed = d.R[0] * d.R[1 % d.N];
+    for (int k = 1; k < d.N; ++k)
+        if (d.R[k] * d.R[(k + 1) % d.N] != rr_fixed) rr_fixed = 0;
+    WideModes tab{};
+    for (int n = 0; n < d.N; ++n) {
+        WideMode& md = tab.md[n];
+        const void* src = xs.rep[n] ? xs.rep[n] : xs.X;
+        int64_t xsn;
+        if (xs.rep[n]) {   // mode-major replica: mode n fastest, then the ring order after n
+            int64_t s = d.I[n];
+            xsn = 1;
+            for (int q = 1, k = n; q < d.N; ++q) {
+                k = (k + 1) % d.N;
+                md.xs[k] = s;
+                s *= d.I[k];
+            }
+        } else {
+            for (int k = 0; k < d.N; ++k) md.xs[k] = d.x_stride[k];
+            xsn = d.x_stride[n];
+        }
+        md.xs[n] = 0;
+        md.wbase = 1.0 / ((double)m * (double)J_of(d, n));
+        md.fast = xsn == 1 && (d.I[n] & 3) == 0 &&
+                  (reinterpret_cast<uintptr_t>(src) & (4 * sizeof(TX) - 1)) == 0;
+    }
+    launch_timed(k_grad_mfma_f32w<TX, CT>, grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
+                 row_tiles, gp, lp, maxIRR, rr_fixed, tab);
+    return hipGetLastError();
+}
+
+// The wide-operand form applies: one chunk of 128 samples per sample group,
+// every R_n R_{n+1} a multiple of 4 with the largest in (32, 128], S, the
+// cores and the partials 16-byte aligned.
+static bool wide_applies(const tr_desc& d, Ptrs cores, const float* S, const float* gp, int m, int groups, int maxRR,
+                         int tf) {
+    if (tf != kWideTF || (m + kWideTF - 1) / kWideTF > groups || maxRR <= 32 || maxRR > 128) return false;
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    if (!al(S) || !al(gp)) return false;
+    for (int k = 0; k < d.N; ++k) {
+        if ((d.R[k] * d.R[(k + 1) % d.N]) % 4 != 0) return false;
+        if (cores.p[k] && !al(cores.p[k])) return false;
+    }
+    return true;
+}
+
+template <typename TX>
+static hipError_t launch_wide_tx(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs, const int32_t* idx,
+                                 const float* S, const double* pF, int m, dim3 grid, int groups, int row_tiles,
+                                 float* gp, double* lp, int maxIRR, int maxRR, hipStream_t st) {
+    switch ((maxRR + 15) / 16) {
+        case 3: return launch_wide<TX, 3>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st);
+        case 4: return launch_wide<TX, 4>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st);
+        case 5: return launch_wide<TX, 5>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st);
+        case 6: return launch_wide<TX, 6>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st);
+        case 7: return launch_wide<TX, 7>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st);
+        case 8: return launch_wide<TX, 8>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // Chunks of 128 samples (one pass per block over twice the samples, half
@@ -303,6 +720,14 @@ hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc x
     const Shape sh = shape_of(d);
     const dim3 grid(xcd_grid(row_tiles, groups));
     const int maxIRR = sh.maxI * sh.maxRR;
+    if (wide_applies(d, cores, S, gp, m, groups, sh.maxRR, tf)) {
+        if (d.x_dtype == TR_F32)
+            return launch_wide_tx<float>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
+                                         sh.maxRR, st);
+        if (d.x_dtype == TR_F16)
+            return launch_wide_tx<__half>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
+                                          sh.maxRR, st);
+    }
     switch (d.x_dtype) {
         case TR_F32:
             return launch_tx<float>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,

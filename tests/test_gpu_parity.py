@@ -103,6 +103,13 @@ GRAD_CASES = [
     (3, [70, 33, 130], [10, 12, 9], 300),     # RR in (64, 128]
     (3, [40, 20, 30], [16, 16, 16], 129),     # RR = 256
     (3, [1, 5, 7], [2, 3, 2], 65),            # a mode of size 1
+    # R_n R_{n+1} a multiple of 4 in every mode (the FP32 kernel's 16-byte
+    # operand form): RR = 100 with a ragged last chunk and odd I_n; RR of
+    # 128 and 64 (the widest staged rows); mixed RR in (32, 64]; one sample
+    (3, [70, 33, 65], [10, 10, 10], 300),
+    (3, [36, 24, 28], [8, 16, 8], 256),
+    (4, [9, 12, 10, 8], [2, 6, 10, 4], 129),
+    (3, [20, 21, 22], [6, 6, 6], 1),
 ]
 
 
