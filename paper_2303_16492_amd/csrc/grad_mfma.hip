@@ -13,7 +13,7 @@
 //
 // Operand layouts of v_mfma_f32_16x16x4_f32 (one wavefront, lane l):
 //   A: A[l % 16][l / 16]   B: B[l / 16][l % 16]   D: D[4 (l / 16) + j][l % 16], j < 4.
-#include "internal.hpp"
+#include "wide.hpp"
 
 namespace trk {
 
@@ -271,8 +271,6 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32(tr_desc d, ModeSrc ms, Pt
 // clamped) meet a zero of G or feed a dropped column, and every one is a
 // finite entry of S.  Rows past m hold such entries too; their residual is
 // zero.
-constexpr int kWideTF = 128;
-
 template <int CT>
 struct WideCfg {
     static constexpr int TF = kWideTF;
@@ -286,48 +284,6 @@ struct WideCfg {
     static constexpr size_t shm() {
         return (size_t)STAGE * 16 + (size_t)(4 * 16 * EP + TF) * 4 + (size_t)TF * 16 + 64;
     }
-};
-
-__device__ __forceinline__ float4 mask4(float4 v, bool ok) {
-    const unsigned mk = ok ? 0xffffffffu : 0u;
-    return make_float4(__uint_as_float(__float_as_uint(v.x) & mk), __uint_as_float(__float_as_uint(v.y) & mk),
-                       __uint_as_float(__float_as_uint(v.z) & mk), __uint_as_float(__float_as_uint(v.w) & mk));
-}
-
-// Sum over a wavefront in a fixed order without LDS: pairs, quads, half
-// rows and rows by DPP lane moves, then the four row sums read from lanes
-// 0, 16, 32 and 48.  Valid in every lane.
-__device__ __forceinline__ double dpp_f64(double v, int ctrl_id) {
-    const long long b = __double_as_longlong(v);
-    int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
-    switch (ctrl_id) {
-        case 0: lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
-        case 1: lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
-        case 2: lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
-        default: lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break; // row_mirror
-    }
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-    v += dpp_f64(v, 0);
-    v += dpp_f64(v, 1);
-    v += dpp_f64(v, 2);
-    v += dpp_f64(v, 3);
-    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
-}
-
-// What the kernel needs of the step's mode, computed once on the host for
-// every mode: the element stride of each index in the fiber source (zero
-// for the mode itself, so an offset is the plain sum over all modes), the
-// sample weight's factor 1/(m J_n), and whether fibers are contiguous
-// whole 4-row groups at a 4-entry-aligned source.
-struct WideMode {
-    int64_t xs[kMaxOrder];
-    double wbase;
-    int32_t fast;
-};
-struct WideModes {
-    WideMode md[kMaxOrder];
 };
 
 template <typename TX, int CT>
@@ -357,39 +313,12 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32w(tr_desc d, ModeSrc ms, P
     // every mode has the same R_n R_{n+1}, and in one batch with the core
     // rows otherwise, so that the block waits for memory once.  Clamped
     // in-bounds addresses.
-    int ik[kMaxOrder];
-    double pf = 1.0;
     const int wu = __builtin_amdgcn_readfirstlane(w);   // the wavefront index, in a scalar register
+    WideSample smp;
     auto issue = [&](int RRl) {
-        const int q0 = RRl >> 2, base = f0 * q0, last = m * q0 - 1;   // < 2^30 pieces
-        // instruction c = 4 i + wu moves pieces 64 c .. 64 c + 63; this lane's
-        // piece e = 64 c + l is row f = e / Q, piece k = e % Q of that row,
-        // advanced by 256 pieces per instruction
-        int f = (64 * wu + l) / C::Q, k = (64 * wu + l) - f * C::Q;
-#pragma unroll
-        for (int i = 0; i < (C::STAGE / 64 + 3) / 4; ++i) {
-            const int c = 4 * i + wu;
-            if (c < C::STAGE / 64) {
-                int src = base + f * q0 + k;
-                src = src < last ? src : last;
-                __builtin_amdgcn_global_load_lds(reinterpret_cast<const float4*>(S) + src, sS + 4 * 64 * c, 16, 0, 0);
-            }
-            k += 256 % C::Q;
-            f += 256 / C::Q;
-            if (k >= C::Q) {
-                k -= C::Q;
-                ++f;
-            }
-        }
-        const int fi = f0 + (tid & (TF - 1));
-        const int64_t fc = fi < m ? fi : m - 1;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) ik[k] = idx[fc * N + (k < N ? k : N - 1)];
-        if (N > 3) {
-#pragma unroll
-            for (int k = 3; k < kMaxOrder; ++k) ik[k] = idx[fc * N + (k < N ? k : N - 1)];
-        }
-        pf = pF[fc];
+        const int q0 = RRl >> 2;
+        wide_stage<C::Q, C::STAGE>(S, sS, q0, f0 * q0, m * q0 - 1, wu, l);   // < 2^30 pieces
+        smp = wide_sample_load(idx, pF, f0, m, N);
     };
     uint64_t t;
     int n = 0;
@@ -419,28 +348,10 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32w(tr_desc d, ModeSrc ms, P
     const TX* X = static_cast<const TX*>(xsrc.rep[n] ? xsrc.rep[n] : xsrc.X);
     const int64_t xsn = xsrc.rep[n] ? 1 : d.x_stride[n];
     const bool fast_fiber = wm.fast != 0;
-    const double wbase = wm.wbase, lbase = 0.5 / (double)m;
     const int erow = 16 * w + 4 * lk;   // first of this lane's 4 D rows (block-local)
 
-    // Each sample's fiber offset and weights, stored in lane order (sample
-    // 16 u + r at slot 8 r + u) so that a lane's eight samples are adjacent.
-    if (tid < TF) {
-        const int f = f0 + tid;
-        bool ok = f < m;
-        int64_t off = 0;
-#pragma unroll
-        for (int k = 0; k < kMaxOrder; ++k) {
-            if (k >= N) break;
-            if (k != n && (ik[k] < 0 || ik[k] >= d.I[k])) ok = false;
-            off += (int64_t)ik[k] * wm.xs[k];
-        }
-        off = ok ? off : 0;
-        const double rp = 1.0 / pf;
-        const int slot = 8 * (tid & 15) + (tid >> 4);
-        sB[slot] = ok ? off : 0;
-        sW[slot] = ok ? (float)(wbase * rp) : 0.f;
-        sL[slot] = ok ? lbase * rp : 0.0;
-    }
+    // each sample's fiber offset and weights, in lane order
+    wide_sample_meta(smp, d, wm, n, f0, m, sB, sW, sL);
 #pragma unroll
     for (int j = 0; j < CT; ++j) ga[j] = mask4(ga[j], grow < In && 4 * CT * lk + 4 * j < RR);
     __builtin_amdgcn_s_waitcnt(0);   // this wavefront's direct loads have landed
@@ -616,49 +527,10 @@ static hipError_t launch_wide(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs,
                               int maxIRR, hipStream_t st) {
     constexpr size_t shm = WideCfg<CT>::shm();
     if (!allow_lds(reinterpret_cast<const void*>(&k_grad_mfma_f32w<TX, CT>), shm)) return hipErrorInvalidValue;
-    int rr_fixed = d.R[0] * d.R[1 % d.N];
-    for (int k = 1; k < d.N; ++k)
-        if (d.R[k] * d.R[(k + 1) % d.N] != rr_fixed) rr_fixed = 0;
-    WideModes tab{};
-    for (int n = 0; n < d.N; ++n) {
-        WideMode& md = tab.md[n];
-        const void* src = xs.rep[n] ? xs.rep[n] : xs.X;
-        int64_t xsn;
-        if (xs.rep[n]) {   // mode-major replica: mode n fastest, then the ring order after n
-            int64_t s = d.I[n];
-            xsn = 1;
-            for (int q = 1, k = n; q < d.N; ++q) {
-                k = (k + 1) % d.N;
-                md.xs[k] = s;
-                s *= d.I[k];
-            }
-        } else {
-            for (int k = 0; k < d.N; ++k) md.xs[k] = d.x_stride[k];
-            xsn = d.x_stride[n];
-        }
-        md.xs[n] = 0;
-        md.wbase = 1.0 / ((double)m * (double)J_of(d, n));
-        md.fast = xsn == 1 && (d.I[n] & 3) == 0 &&
-                  (reinterpret_cast<uintptr_t>(src) & (4 * sizeof(TX) - 1)) == 0;
-    }
+    const WideModes tab = wide_modes(d, xs, m, sizeof(TX));
     launch_timed(k_grad_mfma_f32w<TX, CT>, grid, dim3(256), shm, st, d, ms, cores, xs, idx, S, pF, m, groups,
-                 row_tiles, gp, lp, maxIRR, rr_fixed, tab);
+                 row_tiles, gp, lp, maxIRR, wide_rr_fixed(d), tab);
     return hipGetLastError();
-}
-
-// The wide-operand form applies: one chunk of 128 samples per sample group,
-// every R_n R_{n+1} a multiple of 4 with the largest in (32, 128], S, the
-// cores and the partials 16-byte aligned.
-static bool wide_applies(const tr_desc& d, Ptrs cores, const float* S, const float* gp, int m, int groups, int maxRR,
-                         int tf) {
-    if (tf != kWideTF || (m + kWideTF - 1) / kWideTF > groups || maxRR <= 32 || maxRR > 128) return false;
-    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
-    if (!al(S) || !al(gp)) return false;
-    for (int k = 0; k < d.N; ++k) {
-        if ((d.R[k] * d.R[(k + 1) % d.N]) % 4 != 0) return false;
-        if (cores.p[k] && !al(cores.p[k])) return false;
-    }
-    return true;
 }
 
 template <typename TX>

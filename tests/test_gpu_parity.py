@@ -544,6 +544,13 @@ MIXED_CASES = [
     (3, [70, 33, 130], [10, 12, 9], 300),
     (3, [40, 20, 30], [16, 16, 16], 129),
     (2, [9, 13], [4, 3], 1),
+    # every R_n R_{n+1} a multiple of 4 (the 16-byte-operand form): RR = 100
+    # with a ragged chunk and odd I_n, RR of 128 and 64, mixed RR, RR = 36
+    # with one sample
+    (3, [70, 33, 65], [10, 10, 10], 300),
+    (3, [36, 24, 28], [8, 16, 8], 256),
+    (4, [9, 12, 10, 8], [2, 6, 10, 4], 129),
+    (3, [20, 21, 22], [6, 6, 6], 1),
 ]
 
 
