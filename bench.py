@@ -541,7 +541,7 @@ def cpu_baseline(seconds, seed, I, R, kappa, m, alpha, threads=None):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scaled-illcond-n3-i400-r10.txt")
 KERNEL_SOURCE = {"k_sweep": "sweep.hip", "k_grad_mfma_f32": "grad_mfma.hip", "k_grad_mfma_f32w": "grad_mfma.hip",
-                 "k_grad_mixed": "grad_mixed.hip"}
+                 "k_grad_mixed": "grad_mixed.hip", "k_grad_mixed_w": "grad_mixed.hip"}
 
 
 def measured_traffic(kernel):
@@ -823,7 +823,7 @@ def main():
     peak, unit = PEAK[args.prec]
     g_ach = flops / (main["grad_us"] * 1e-6) / 1e12
     # FP32: the 16-byte-operand form (R_n R_{n+1} = 100, one 128-sample chunk per sample group)
-    gkern = "k_grad_mfma_f32w" if args.prec == "f32" else "k_grad_mixed"
+    gkern = "k_grad_mfma_f32w" if args.prec == "f32" else "k_grad_mixed_w"
     grad_roof = {"bound": "mfma", "achieved": round(g_ach, 3), "peak": peak, "unit": unit,
                  "frac": round(g_ach / peak, 5), "traffic": measured_traffic(gkern),
                  "kernel": gkern,
