@@ -592,7 +592,10 @@ hipError_t launch_grad_mfma_f32(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc x
     const Shape sh = shape_of(d);
     const dim3 grid(xcd_grid(row_tiles, groups));
     const int maxIRR = sh.maxI * sh.maxRR;
-    if (wide_applies(d, cores, S, gp, m, groups, sh.maxRR, tf)) {
+    // (the 16-byte form takes one chunk of 128 samples per group whatever
+    // chunk the layout chose: with 64-sample chunks m <= 64 groups, and a
+    // group past the last sample writes a zero partial)
+    if (wide_applies(d, cores, S, gp, m, groups, sh.maxRR, kWideTF)) {
         if (d.x_dtype == TR_F32)
             return launch_wide_tx<float>(d, ms, cores, xs, idx, S, pF, m, grid, groups, row_tiles, gp, lp, maxIRR,
                                          sh.maxRR, st);
