@@ -9,7 +9,12 @@ namespace trk {
 
 // A block takes SB samples.  Phase 1: one thread per (sample, mode) draws
 // the index (the optimal law: one thread per sample draws over J_n); the
-// probabilities are multiplied per sample in the order n+1, ..., n-1.
+// probabilities are multiplied per sample in the order n+1, ..., n-1.  When
+// the kernel draws the step's mode itself and the law is one per mode, the
+// index draws do not depend on the mode: threads draw for every mode of
+// every sample and one more thread draws the mode, all in the same Philox
+// instruction stream, instead of one chain after the other; a draw for the
+// step's own mode is dropped.
 // do_sample == 2 enumerates instead: sample f is column j = f of X_[n]
 // (every column once, m = J_n), decoded in the cyclic order, p = 1/J_n.
 // Phase 2: the N-1 core slices of every sample are copied to LDS in one
@@ -24,15 +29,45 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
                                                          const uint64_t* __restrict__ cdf_J, int stream_tag,
                                                          Ptrs cores, int32_t* __restrict__ idx, double* __restrict__ pF,
                                                          TC* __restrict__ S, int do_sample, int do_subchain) {
-    uint64_t t;
-    int n;
-    resolve_mode(ms, d.N, &t, &n);
-    if (ms.n_pub && blockIdx.x == 0 && threadIdx.x == 0) *ms.n_pub = n;
     const int N = d.N, tid = threadIdx.x;
-    const int n1 = ring_next(n, N);
-    const int Rn = d.R[n], Rn1 = d.R[n1], RR = Rn * Rn1;
     const int f0 = blockIdx.x * SB;
     const int nb = min(SB, m - f0);
+    uint64_t t;
+    int n;
+    // per-mode laws with the mode drawn here: the draws of every mode beside
+    // the mode's draw (thread nb N), one Philox chain per thread
+    const bool early_draws = do_sample == 1 && !cdf_J && ms.n == -1;
+    int dr_i = 0;
+    double dr_p = 0.0;
+    if (early_draws) {
+        __shared__ int s_mode;
+        t = ms.t_dev ? *ms.t_dev : ms.t;
+        if (tid <= nb * N) {
+            const bool is_mode = tid == nb * N;
+            const int fl = tid / N, k = tid - fl * N;
+            const uint64_t r = draw_word(ms.seed, t, is_mode ? 0 : (uint64_t)(f0 + fl), is_mode ? 0 : (uint64_t)k,
+                                         is_mode ? (uint64_t)TR_STREAM_MODE : (uint64_t)stream_tag);
+            if (is_mode) {
+                s_mode = (int)mulhi64(r, (uint64_t)N);
+            } else {
+                const gptr<uint64_t> ck = lane_pick_global<uint64_t>(cdf.p, k);   // k differs across lanes
+                const int Ik = lane_pick(d.I, k);
+                if (ck) {
+                    dr_i = cdf_pick(ck, Ik, r, &dr_p);
+                } else {
+                    dr_i = (int)mulhi64(r, (uint64_t)Ik);
+                    dr_p = 1.0 / (double)Ik;
+                }
+            }
+        }
+        __syncthreads();
+        n = s_mode;
+    } else {
+        resolve_mode(ms, d.N, &t, &n);
+    }
+    if (ms.n_pub && blockIdx.x == 0 && threadIdx.x == 0) *ms.n_pub = n;
+    const int n1 = ring_next(n, N);
+    const int Rn = d.R[n], Rn1 = d.R[n1], RR = Rn * Rn1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int* sidx = reinterpret_cast<int*>(smem_raw);                   // [SB][kMaxOrder]
     double* sp = reinterpret_cast<double*>(sidx + SB * kMaxOrder);  // [SB][kMaxOrder], order of the chain
@@ -90,6 +125,18 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
                 }
                 sidx[fl * kMaxOrder + n] = -1;
                 sok[fl] = 1;
+            }
+        } else if (early_draws) {
+            // thread (sample fl, mode k): its draw at chain position q
+            if (tid < nb * N) {
+                const int fl = tid / N, k = tid - fl * N;
+                if (k == n) {
+                    sidx[fl * kMaxOrder + n] = -1;
+                    sok[fl] = 1;
+                } else {
+                    sidx[fl * kMaxOrder + k] = dr_i;
+                    sp[fl * kMaxOrder + (k - n - 1 + N) % N] = dr_p;
+                }
             }
         } else {
             for (int w = tid; w < nb * (N - 1); w += blockDim.x) {
