@@ -947,7 +947,7 @@ def main():
         "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": "scaled-illcond-n3-i400-r10", "N": N, "I": I, "R": R, "kappa": kappa,
-                   "m": m, "m_H": m, "law": "uniform", "alpha": args.alpha, "prec": args.prec,
+                   "m": m, "H_n": "F_n", "law": "uniform", "alpha": args.alpha, "prec": args.prec,
                    "overlap": not args.no_overlap},
         "roofline": roof,
         "roofline_gradient": grad_roof,

@@ -506,21 +506,30 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
         // a damping schedule needs t: then the shape-only kernels read it too
         const ModeSrc ms_shape = same_shape ? ModeSrc{sched ? t_dev : nullptr, 0, 0, c->seed} : ms;
         double* loss = loss_out ? loss_out + it : lossw;
-        if (c->law == TR_LAW_OPTIMAL)
-            e = launch_dist_optimal(d, ms_draw, cores, xs_paper, p->cdf_J, dev_status, w + L.opt, st);
-        if (e == hipSuccess)
-            e = launch_sample_subchain(d, ms_draw, c->m, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr,
-                                       TR_STREAM_IDX, cores, idx, pF, S, true, true, st);
         // Scaled steps (RR <= 128) with a second stream: the Gram, its
         // reduction and the inverse need only the draws, so they run on
         // ``hs``; the gradient waits for the Gram's group sums (it is not
         // on the critical path) and then runs beside the reduction and the
         // inverse, and the gradient partials are added on ``st`` too.
+        // With an independent H draw and modes of one shape, nothing on
+        // ``hs`` reads the step's draws: the branch forks before them, and
+        // its sample kernel draws the step's mode itself (the same counter,
+        // so the same mode) and runs beside the step's own.
         const bool fork = any_aux && c->scaled && sweep_supported(d);
+        const bool fork_early = fork && c->m_H > 0 && same_shape;
         hipStream_t hs = fork ? (hipStream_t)o.aux : st;
+        if (c->law == TR_LAW_OPTIMAL)
+            e = launch_dist_optimal(d, ms_draw, cores, xs_paper, p->cdf_J, dev_status, w + L.opt, st);
+        if (e == hipSuccess && fork_early) {
+            e = hipEventRecord((hipEvent_t)o.ev_fork, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(hs, (hipEvent_t)o.ev_fork, 0);
+        }
+        if (e == hipSuccess)
+            e = launch_sample_subchain(d, ms_draw, c->m, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr,
+                                       TR_STREAM_IDX, cores, idx, pF, S, true, true, st);
         if (c->scaled && sweep_supported(d)) {
             const Shape sh = shape_of(d);
-            if (e == hipSuccess && fork) {
+            if (e == hipSuccess && fork && !fork_early) {
                 e = hipEventRecord((hipEvent_t)o.ev_fork, st);
                 if (e == hipSuccess) e = hipStreamWaitEvent(hs, (hipEvent_t)o.ev_fork, 0);
             }
@@ -529,7 +538,8 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
                     int32_t* idxH = reinterpret_cast<int32_t*>(w + L.idxH);
                     double* pH = reinterpret_cast<double*>(w + L.pH);
                     void* SH = w + L.SH;
-                    e = launch_sample_subchain(d, ms, c->m_H, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr,
+                    const ModeSrc ms_h = fork_early ? ModeSrc{t_dev, 0, -1, c->seed, nullptr, nullptr} : ms;
+                    e = launch_sample_subchain(d, ms_h, c->m_H, cdf, c->law == TR_LAW_OPTIMAL ? p->cdf_J : nullptr,
                                                TR_STREAM_H, cores, idxH, pH, SH, true, true, hs);
                     if (e == hipSuccess)
                         e = launch_gram(d, ms_shape, SH, pH, c->m_H, gram, w + L.gramws, L.mlH, hs,

@@ -204,15 +204,19 @@ def test_mixed_scaled_run_tracks_oracle(prec):
 
 
 @pytest.mark.parametrize("m_H", [0, 150])
-def test_overlapped_branch_equals_serial_bitwise(m_H):
+@pytest.mark.parametrize("shape", [([30, 25, 28], [3, 4, 3]), ([28, 28, 28], [3, 3, 3])])
+def test_overlapped_branch_equals_serial_bitwise(m_H, shape):
     """The Gram/inverse branch on a second stream changes no arithmetic: the
-    same cores, step counter and loss as the one-stream run."""
+    same cores, step counter and loss as the one-stream run.  With an
+    independent H draw and modes of one shape the branch forks before the
+    step's own draws and its sample kernel draws the mode itself."""
     dtype = torch.float32
-    X, _, init = planted(3, [30, 25, 28], [3, 4, 3], dtype, noise_db=40.0)
+    I, R = shape
+    X, _, init = planted(3, I, R, dtype, noise_db=40.0)
     dX = to_dev(flat_paper(X), dtype)
     outs = []
     for overlap in (False, True):
-        s = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [30, 25, 28], [3, 4, 3], 200, scaled=True,
+        s = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, I, R, 200, scaled=True,
                      prec="f32", rule=api.step_rule("fixed", alpha=0.5), m_H=m_H, overlap=overlap)
         losses = torch.zeros(12, dtype=torch.float64, device=DEV)
         s.run(12, loss_out=losses)
@@ -247,25 +251,26 @@ def _graph_steps(sol, steps):
     return g
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_benchmarked_configuration_equal_shapes(prec):
+@pytest.mark.parametrize("prec,m_H", [("f32", None), ("bf16", None), ("f32", 150)])
+def test_benchmarked_configuration_equal_shapes(prec, m_H):
     """The launch configuration the benchmark times, on a small problem:
     every mode with the same I_n and R_n R_{n+1} (the Gram, its reduction
     and the inverse then take mode 0's shape and never read the step
     counter), the Gram/inverse branch on a second stream, the mode slot
     published by the first kernel, graph capture and replay.  11 steps
-    against the FP64 oracle's trajectory."""
+    against the FP64 oracle's trajectory; with an independent H draw the
+    branch forks before the step's draws."""
     dtype = torch.float32
     N, I, R, m = 3, 28, 3, 300
     X, _, init = planted(N, I, R, dtype, seed=3, noise_db=None)
     dX = to_dev(flat_paper(X), dtype)
     sol = TRSolver([to_dev(unfold(c), dtype) for c in init], dX, [I] * N, [R] * N, m, scaled=True, prec=prec,
-                   rule=api.step_rule("fixed", alpha=0.5), seed=3, overlap=True)
+                   rule=api.step_rule("fixed", alpha=0.5), seed=3, overlap=True, m_H=m_H or 0)
     assert sol.opts is not None
     _graph_steps(sol, 10)
     assert sol.t == 11
     st = brsgd.State(init)
-    cfg = brsgd.Config(m=m, variant="scaled", alpha=0.5, seed=3)
+    cfg = brsgd.Config(m=m, variant="scaled", alpha=0.5, seed=3, m_H=m_H)
     for _ in range(11):
         brsgd.step(st, X, cfg)
     tol = 2e-4 if prec == "f32" else 5e-3
