@@ -449,8 +449,10 @@ hipError_t launch_gram(const tr_desc& d, ModeSrc ms, const void* S, const double
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (mid && (e = hipEventRecord(mid, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((maxRR2 + 255) / 256), dim3(256), 0, st, d, ms, part, L.groups,
-                       maxRR2, gram);
+    // one wavefront per block: the partials' reads spread over as many CUs
+    // as there are blocks of 64 entries
+    hipLaunchKernelGGL(k_gram_reduce, dim3((maxRR2 + 63) / 64), dim3(64), 0, st, d, ms, part, L.groups, maxRR2,
+                       gram);
     return hipGetLastError();
 }
 
