@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void k_lev_rows(tr_desc d, ModeSrc ms, int use
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int c = 16 * (w + 4 * u) + lr, cc = c < RR ? c : RR - 1;
-                hb[u][ks] = hm[sym_lower_at(kc, cc, RR)];
+                hb[u][ks] = hm[(int64_t)kc * RR + cc];
             }
         }
     }

@@ -136,13 +136,6 @@ struct StepBump {
     uint64_t* t;
     unsigned* ctr;
 };
-// Entry (r, c) of the sweep's -M^{-1} (row-major, RR x RR): only its 16 x 16
-// tiles on and below the diagonal are stored, and an entry above them is
-// read at its mirror (the matrix is symmetric).
-__device__ __forceinline__ int64_t sym_lower_at(int r, int c, int RR) {
-    return (r >> 4) >= (c >> 4) ? (int64_t)r * RR + c : (int64_t)c * RR + r;
-}
-
 __device__ inline void bump_if_last(const StepBump& b, bool t_read) {
     if (!b.t) return;
     if (!t_read) {   // no block uses t: one block advances it, nobody waits

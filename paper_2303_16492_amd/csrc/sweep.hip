@@ -316,9 +316,8 @@ __device__ __forceinline__ void fill_tiles(dbl4 (&acc)[tpw<NT>()], const double*
     }
 }
 
-// -M^{-1} into hm, the wavefront's tiles only (those on and below the
-// diagonal; readers take an entry above them at its mirror), with the
-// deferred -2 on the diagonal, scaled back by sc (the sweep ran on sc M).
+// -M^{-1} into hm (both triangles), with the deferred -2 on the diagonal,
+// scaled back by sc (the sweep ran on sc M).
 template <int NT, int WV>
 __device__ __forceinline__ void store_tiles(const dbl4 (&acc)[tpw<NT>()], double* __restrict__ hm, int RR,
                                             double sc) {
@@ -330,7 +329,10 @@ __device__ __forceinline__ void store_tiles(const dbl4 (&acc)[tpw<NT>()], double
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = 16 * rt + 4 * j + lr, c = 16 * ct + lc;
-            if (r < RR && c < RR) hm[(int64_t)r * RR + c] = (acc[k][j] - (r == c ? 2.0 : 0.0)) * sc;
+            if (r < RR && c < RR) {
+                hm[(int64_t)r * RR + c] = (acc[k][j] - (r == c ? 2.0 : 0.0)) * sc;
+                if (rt != ct) hm[(int64_t)c * RR + r] = acc[k][j] * sc;
+            }
         }
     }
 }
@@ -483,11 +485,10 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
     return -1;
 }
 
-// -(gram + eta I)^{-1} into hm (RR x RR, row-major, the 16 x 16 tiles on and
-// below the diagonal: see sym_lower_at), with the fallback ladder; flag: 0
-// ok, 1 damped, 2 failed.  With rank_tol > 0 (the leverage law) there is no
-// ladder: flag 2 means a pivot at or below rank_tol * max_i gram_ii, i.e.
-// the Gram is taken as singular.  256 threads.
+// -(gram + eta I)^{-1} into hm (RR x RR, row-major, both triangles), with
+// the fallback ladder; flag: 0 ok, 1 damped, 2 failed.  With rank_tol > 0
+// (the leverage law) there is no ladder: flag 2 means a pivot at or below
+// rank_tol * max_i gram_ii, i.e. the Gram is taken as singular.  256 threads.
 template <int NT>
 __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const double* __restrict__ gram,
                                                Damp dmp, double rank_tol, double* __restrict__ hm,
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(64) void k_scaled_apply(tr_desc d, ModeSrc ms, cons
             const int k = 4 * ks + lk, kc = k < RR ? k : RR - 1;
             if (4 * ks < RR) {   // uniform
                 ga[ks] = g[(int64_t)rowc * RR + kc];
-                hb[ks] = hm[sym_lower_at(kc, cc, RR)];
+                hb[ks] = hm[(int64_t)kc * RR + cc];
             }
         }
         const int fl = *flag;
