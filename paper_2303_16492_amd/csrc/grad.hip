@@ -299,7 +299,9 @@ hipError_t launch_grad_reduce(const tr_desc& d, ModeSrc ms, const void* ws, cons
 constexpr int kGramT = 32;
 template <typename TC>
 struct GramChunk {   // samples staged per round: 2 x F x 33 values of TC stay under 64 KiB
-    static constexpr int F = sizeof(TC) == 8 ? 64 : 128;
+    // (FP32: 192, so a group of m / 24 samples at m = 4096 is one round, all
+    // of its loads in flight together)
+    static constexpr int F = sizeof(TC) == 8 ? 64 : 192;
 };
 
 __host__ __device__ inline void gram_tile(int tile, int& ct, int& et) {   // tile -> (ct >= et)
