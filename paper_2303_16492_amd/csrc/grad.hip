@@ -345,36 +345,55 @@ __global__ __launch_bounds__(256) void k_gram_partial(tr_desc d, ModeSrc ms, con
     const int qr = w >> 1, qc = w & 1;
     typedef double gd4 __attribute__((ext_vector_type(4)));
     gd4 acc = {0.0, 0.0, 0.0, 0.0};
+    // A round stages kGramF samples in two halves of rows: every load of
+    // the round is issued first, the first half goes to LDS as soon as its
+    // loads have landed, and its matrix-core steps run while the second
+    // half's loads are still in flight (the halves are disjoint rows).
+    constexpr int V = kGramF * kGramT / 256, VH = V / 2, FH = kGramF / 2;
+    static_assert(V % 2 == 0 && FH % 4 == 0, "two halves of whole K steps");
     for (int f0 = fb; f0 < fe; f0 += kGramF) {
         __syncthreads();
-        {   // every load of the chunk issued before any LDS store
-            constexpr int V = kGramF * kGramT / 256;
-            const int c = tid & (kGramT - 1), fo = tid >> 5;
-            TC av[V], bv[V];
-            double pv = 1.0;
-            if (tid < kGramF && pF) pv = f0 + tid < fe ? pF[f0 + tid] : 1.0;
+        // loads at clamped (in-bounds) indices, masked afterwards: no load
+        // sits behind a branch, so the first half's wait counts only the
+        // loads issued before its own
+        const int c = tid & (kGramT - 1), fo = tid >> 5;   // row fo + 8 v, column c
+        const bool okA = c0 + c < RR, okB = e0 + c < RR;
+        const int cA = okA ? c0 + c : RR - 1, cB = okB ? e0 + c : RR - 1;
+        double pv = 1.0;
+        if (pF) {   // uniform
+            const int fp = f0 + (tid < kGramF ? tid : 0);
+            pv = pF[fp < fe ? fp : fe - 1];
+        }
+        TC av[V], bv[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
+        for (int h = 0; h < 2; ++h) {   // the first half's loads issue first
+#pragma unroll
+            for (int v = h * VH; v < (h + 1) * VH; ++v) {
+                const int f = f0 + fo + 8 * v, fr = f < fe ? f : fe - 1;
+                av[v] = S[(int64_t)fr * RR + cA];
+                bv[v] = S[(int64_t)fr * RR + cB];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const int nf = min(kGramF, fe - f0);   // rows past nf are staged as zeros with weight 0
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int v = h * VH; v < (h + 1) * VH; ++v) {   // rows fo + 8 v of half h
                 const int f = fo + 8 * v;
                 const bool okf = f0 + f < fe;
-                av[v] = (okf && c0 + c < RR) ? S[(int64_t)(f0 + f) * RR + c0 + c] : TC(0);
-                bv[v] = (okf && e0 + c < RR) ? S[(int64_t)(f0 + f) * RR + e0 + c] : TC(0);
+                sA[f][c] = okf && okA ? av[v] : TC(0);
+                sB[f][c] = okf && okB ? bv[v] : TC(0);
             }
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int f = fo + 8 * v;
-                sA[f][c] = av[v];
-                sB[f][c] = bv[v];
+            if (h == 0 && tid < kGramF) sw[tid] = f0 + tid < fe ? wbase / pv : 0.0;
+            __syncthreads();
+            const int qe = min(nf, (h + 1) * FH);
+            for (int q = h * FH; q < qe; q += 4) {
+                const int f = q + lk;
+                const double a = (double)sA[f][16 * qr + lc] * sw[f];
+                const double b = (double)sB[f][16 * qc + lc];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
-            if (tid < kGramF) sw[tid] = f0 + tid < fe ? wbase / pv : 0.0;
-        }
-        __syncthreads();
-        const int nf = min(kGramF, fe - f0);
-        for (int q = 0; q < nf; q += 4) {   // rows past nf were staged as zeros with weight 0
-            const int f = q + lk;
-            const double a = (double)sA[f][16 * qr + lc] * sw[f];
-            const double b = (double)sB[f][16 * qc + lc];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
     }
     double* out = part + (int64_t)grp * maxRR2;
