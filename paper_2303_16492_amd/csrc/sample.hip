@@ -37,6 +37,7 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
     // per-mode laws with the mode drawn here: the draws of every mode beside
     // the mode's draw (thread nb N), one Philox chain per thread
     const bool early_draws = do_sample == 1 && !cdf_J && ms.n == -1;
+    static_assert(16 * kMaxOrder + 1 <= 256, "one thread per (sample, mode) and one for the mode");
     int dr_i = 0;
     double dr_p = 0.0;
     if (early_draws) {
