@@ -442,7 +442,11 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32w(tr_desc d, ModeSrc ms, P
             sEw[(4 * lk + j) * EP + fl] = -e * wf;
         }
     }
-    // GEMM2: g[erow + j][CW lr + c] += sum_s E[.][TQ lk + s] S[TQ lk + s][.]
+    // GEMM2: g[erow + j][col(c)] += sum_s E[.][TQ lk + s] S[TQ lk + s][col(c)]
+    // for the lane's CW columns col(c) = 64 (c / 4) + 4 lr + c % 4: each
+    // 16-byte read of S covers 64 consecutive columns across 16 lanes, so
+    // no two lanes of a read share an LDS bank (columns CW lr + c put lanes
+    // lr and lr + 4 in one bank when CW = 8)
     // (the residual rows are this wavefront's own: LDS operations of a
     // wavefront complete in order, so no barrier)
     __builtin_amdgcn_wave_barrier();
@@ -454,18 +458,18 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32w(tr_desc d, ModeSrc ms, P
     // scheduling groups keep that order (left alone, the compiler reads
     // each step's operands right before they are used).
     const float* erw = sEw + lr * EP + TQ * lk;
-    const float* scl = sS + (TQ * lk) * SP + CW * lr;
+    const float* scl = sS + (TQ * lk) * SP + 4 * lr;
     constexpr int RPS = CW / 4;   // 16-byte B reads per K step
     float4 acur = *reinterpret_cast<const float4*>(erw), anxt = acur;
     float4 bcur[RPS], bnxt[RPS];
 #pragma unroll
-    for (int h = 0; h < RPS; ++h) bcur[h] = *reinterpret_cast<const float4*>(scl + 4 * h);
+    for (int h = 0; h < RPS; ++h) bcur[h] = *reinterpret_cast<const float4*>(scl + 64 * h);
     __builtin_amdgcn_sched_group_barrier(0x100, 1 + RPS, 0);
 #pragma unroll
     for (int st = 0; st < TQ; ++st) {
         if (st + 1 < TQ) {
 #pragma unroll
-            for (int h = 0; h < RPS; ++h) bnxt[h] = *reinterpret_cast<const float4*>(scl + (st + 1) * SP + 4 * h);
+            for (int h = 0; h < RPS; ++h) bnxt[h] = *reinterpret_cast<const float4*>(scl + (st + 1) * SP + 64 * h);
             if ((st + 1) % 4 == 0) anxt = *reinterpret_cast<const float4*>(erw + (st + 1));
         }
         const float at = (st & 3) == 0 ? acur.x : (st & 3) == 1 ? acur.y : (st & 3) == 2 ? acur.z : acur.w;
@@ -489,7 +493,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma_f32w(tr_desc d, ModeSrc ms, P
         const int row = i0 + erow + j;
 #pragma unroll
         for (int h = 0; h < CW / 4; ++h) {
-            const int col = CW * lr + 4 * h;
+            const int col = 64 * h + 4 * lr;
             if (row < In && col < RR)
                 *reinterpret_cast<float4*>(out + (int64_t)row * RR + col) =
                     make_float4(acc2[4 * h][j], acc2[4 * h + 1][j], acc2[4 * h + 2][j], acc2[4 * h + 3][j]);
