@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
             }
         }
         __syncthreads();
-        n = s_mode;
+        n = __builtin_amdgcn_readfirstlane(s_mode);   // uniform: what follows from it stays scalar
     } else {
         resolve_mode(ms, d.N, &t, &n);
     }
@@ -136,7 +136,8 @@ __global__ __launch_bounds__(256) void k_sample_subchain(tr_desc d, ModeSrc ms, 
                     sok[fl] = 1;
                 } else {
                     sidx[fl * kMaxOrder + k] = dr_i;
-                    sp[fl * kMaxOrder + (k - n - 1 + N) % N] = dr_p;
+                    const int q = k - n - 1;   // position in the chain n+1, ..., n-1
+                    sp[fl * kMaxOrder + (q < 0 ? q + N : q)] = dr_p;
                 }
             }
         } else {
