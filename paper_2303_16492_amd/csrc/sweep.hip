@@ -527,89 +527,111 @@ __global__ __launch_bounds__(256) void k_sweep(tr_desc d, ModeSrc ms, const doub
 }
 
 constexpr int kApplyRows = 16;
+constexpr int kApplyWaves = 4;   // the K range split four ways
 
-// p = g (-M^{-1}), then the rule: one wavefront per block, one 16 x 16 tile
-// of p per block (rows 16 blockIdx.x.., columns 16 blockIdx.y..), so the
-// product spreads over as many CUs as there are tiles.  The tile is one
-// chain of FP64 matrix-core steps over K in fours (K = R_n R_{n+1} <= 128);
-// every operand (the tile's rows of g, its columns of -M^{-1}, the core and
-// accumulator entries it updates) is loaded straight from global memory
-// with all loads in flight.  With lp.part set, block (0, 0) also writes the
-// loss.  With ``step`` set, the block that finishes last advances the step
-// counter (after every block has read it).
+// p = g (-M^{-1}), then the rule: one 16 x 16 tile of p per block (rows
+// 16 blockIdx.x.., columns 16 blockIdx.y..), so the product spreads over
+// as many CUs as there are tiles.  Each of the block's four wavefronts runs
+// one chain of FP64 matrix-core steps over its quarter of K (K steps of
+// four, K = R_n R_{n+1} <= 128) on its own SIMD; wavefronts 1-3 leave their
+// partial tiles in LDS and wavefront 0 adds them in a fixed order and
+// applies the rule.  Every operand (the tile's rows of g, its columns of
+// -M^{-1}, the core and accumulator entries it updates) is loaded straight
+// from global memory with all loads in flight.  With lp.part set, block
+// (0, 0) also writes the loss.  With ``step`` set, the block that finishes
+// last advances the step counter (after every block has read it).
 // SHAPE0: every mode has the same I_n and R_n R_{n+1}, so the loads of g and
 // -M^{-1} are issued before the step's mode has arrived.
 template <typename TC, bool SHAPE0>
-__global__ __launch_bounds__(64) void k_scaled_apply(tr_desc d, ModeSrc ms, const TC* __restrict__ g,
-                                                     LossParts lp, double* __restrict__ loss,
-                                                     const double* __restrict__ hm, const int* __restrict__ flag,
-                                                     MutPtrs cores, MutPtrs accum, tr_step rule, int32_t* status,
-                                                     StepBump step) {
-    uint64_t t;
+__global__ __launch_bounds__(64 * kApplyWaves) void k_scaled_apply(tr_desc d, ModeSrc ms, const TC* __restrict__ g,
+                                                                   LossParts lp, double* __restrict__ loss,
+                                                                   const double* __restrict__ hm,
+                                                                   const int* __restrict__ flag, MutPtrs cores,
+                                                                   MutPtrs accum, tr_step rule, int32_t* status,
+                                                                   StepBump step) {
+    uint64_t t = 0;
     int n = 0;
     if (!SHAPE0) resolve_mode(ms, d.N, &t, &n);
     const int ns = SHAPE0 ? 0 : n;
     const int In = d.I[ns];
     const int RR = d.R[ns] * d.R[ring_next(ns, d.N)];
-    const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
-    __shared__ double red[4];
+    const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ double red[kApplyWaves];
+    __shared__ dbl4 part[kApplyWaves - 1][64];
     if (blockIdx.x == 0 && blockIdx.y == 0 && lp.part) {
         const double s = loss_parts_sum(lp, In, red);
-        if (l == 0) *loss = s;
+        if (threadIdx.x == 0) *loss = s;
     }
-    constexpr int KS = 32;                          // K steps of 4: RR <= 128
+    constexpr int KW = 32 / kApplyWaves;            // K steps of 4 per wavefront: RR <= 128
     const int r0 = blockIdx.x * kApplyRows, c = 16 * blockIdx.y + lr;
-    if (r0 < In && 16 * (int)blockIdx.y < RR) {
+    const bool live = r0 < In && 16 * (int)blockIdx.y < RR;   // uniform
+    const int row = r0 + lr, rowc = row < In ? row : In - 1, cc = c < RR ? c : RR - 1;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    TC* G = nullptr;
+    TC* A = nullptr;
+    double gold[4] = {0.0, 0.0, 0.0, 0.0}, aold[4] = {0.0, 0.0, 0.0, 0.0};
+    int fl = 0;
+    if (live) {
         // Loads at clamped (in-bounds) indices, masked afterwards: no load
         // sits behind a branch, so all of them are in flight together (with
         // SHAPE0 the ones that do not need the mode go before its read).
-        double a[KS], b[KS];                        // g[r0 + lr][4ks + lk], (-M^{-1})[4ks + lk][c]
-        const int row = r0 + lr, rowc = row < In ? row : In - 1, cc = c < RR ? c : RR - 1;
-        TC ga[KS];
-        double hb[KS];
+        TC ga[KW];
+        double hb[KW];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int k = 4 * ks + lk, kc = k < RR ? k : RR - 1;
+        for (int s = 0; s < KW; ++s) {
+            const int ks = w * KW + s, k = 4 * ks + lk, kc = k < RR ? k : RR - 1;
+            ga[s] = TC(0);
+            hb[s] = 0.0;
             if (4 * ks < RR) {   // uniform
-                ga[ks] = g[(int64_t)rowc * RR + kc];
-                hb[ks] = hm[(int64_t)kc * RR + cc];
+                ga[s] = g[(int64_t)rowc * RR + kc];
+                hb[s] = hm[(int64_t)kc * RR + cc];
             }
         }
-        const int fl = *flag;
-        if (SHAPE0) resolve_mode(ms, d.N, &t, &n);
-        TC* G = static_cast<TC*>(cores.p[n]);
-        TC* A = static_cast<TC*>(accum.p[n]);
         TC gv[4], av[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = r0 + 4 * j + lk, rc = r < In ? r : In - 1;
-            gv[j] = G[(int64_t)rc * RR + cc];
-            av[j] = TC(0);
-        }
-        if (rule.kind == 1) {   // uniform; the accumulator exists only for AdaGrad
+        if (w == 0) {   // the entries the rule updates
+            fl = *flag;
+            if (SHAPE0) resolve_mode(ms, d.N, &t, &n);
+            G = static_cast<TC*>(cores.p[n]);
+            A = static_cast<TC*>(accum.p[n]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int r = r0 + 4 * j + lk, rc = r < In ? r : In - 1;
-                av[j] = A[(int64_t)rc * RR + cc];
+                gv[j] = G[(int64_t)rc * RR + cc];
+                av[j] = TC(0);
+            }
+            if (rule.kind == 1) {   // uniform; the accumulator exists only for AdaGrad
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = r0 + 4 * j + lk, rc = r < In ? r : In - 1;
+                    av[j] = A[(int64_t)rc * RR + cc];
+                }
+            }
+        }
+        double a[KW], b[KW];
+#pragma unroll
+        for (int s = 0; s < KW; ++s) {
+            const int ks = w * KW + s, k = 4 * ks + lk;
+            a[s] = (row < In && k < RR) ? (double)ga[s] : 0.0;
+            b[s] = (k < RR && c < RR) ? hb[s] : 0.0;
+        }
+        if (w == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool in = r0 + 4 * j + lk < In && c < RR;
+                gold[j] = in ? (double)gv[j] : 0.0;
+                aold[j] = in ? (double)av[j] : 0.0;
             }
         }
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int k = 4 * ks + lk;
-            a[ks] = (4 * ks < RR && row < In && k < RR) ? (double)ga[ks] : 0.0;
-            b[ks] = (4 * ks < RR && k < RR && c < RR) ? hb[ks] : 0.0;
-        }
-        double gold[4], aold[4];
+        for (int s = 0; s < KW; ++s)
+            if (4 * (w * KW + s) < RR) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+        if (w > 0) part[w - 1][l] = acc;
+    }
+    __syncthreads();
+    if (live && w == 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool in = r0 + 4 * j + lk < In && c < RR;
-            gold[j] = in ? (double)gv[j] : 0.0;
-            aold[j] = in ? (double)av[j] : 0.0;
-        }
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            if (4 * ks < RR) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+        for (int v = 0; v < kApplyWaves - 1; ++v) acc += part[v][l];   // fixed order
         if (fl != 2) {   // fl == 2: not positive definite even with damping, core unchanged
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -671,7 +693,7 @@ hipError_t launch_sweep_apply(const tr_desc& d, ModeSrc ms, const void* g, LossP
     for (int k = 1; k < d.N; ++k)
         same = same && d.I[k] == d.I[0] && d.R[k] * d.R[(k + 1) % d.N] == d.R[0] * d.R[1 % d.N];
 #define TRK_APPLY(TC, S0)                                                                                   \
-    hipLaunchKernelGGL((k_scaled_apply<TC, S0>), grid, dim3(64), 0, st, d, ms, static_cast<const TC*>(g), lp, \
+    hipLaunchKernelGGL((k_scaled_apply<TC, S0>), grid, dim3(64 * kApplyWaves), 0, st, d, ms, static_cast<const TC*>(g), lp, \
                        loss, hm, flag, cores, accum, rule, status, step)
     if (d.core_dtype == TR_F64) {
         if (same) TRK_APPLY(double, true);
