@@ -354,6 +354,7 @@ struct SweepShared {
     double D8[2][64];        // pivot block q+1 as published before step q, by (q + 1) & 1
     double Dn[64];           // factor wavefront: pivot block 0 in the prologue, then the exchange of w = B C
     double red[kSweepWaves];
+    double mxdiag;           // largest diagonal entry of h, found by the factor wavefront
     int good[2];             // verdict of the factorisation of step q's pivot block, by q & 1
 };
 
@@ -419,33 +420,51 @@ __device__ __forceinline__ int sweep_wave(const double* __restrict__ gram, int R
             base = (block_sum(tr, sh.red) + damping * RR) / RR;
         }
         const double eta = attempt == 0 ? damping : damping + pow(10.0, (double)(attempt - 1 - 10)) * base;
-        __syncthreads();   // the previous attempt's readers are done with the shared buffers
-        double dg[2] = {0.0, 0.0};   // diagonal entries l and l + 64, loaded with the tiles
-        if (attempt == 0) {
+        // The factor wavefront's loads go out before the barrier below and
+        // the update wavefronts' after it, so that the CU serves the first
+        // pivot blocks and the diagonal first: the first 8 x 8 sweep then
+        // runs while the tiles are still arriving.  Diagonal entries l and
+        // l + 64: the factor wavefront alone loads them (64 rows per load;
+        // the update wavefronts' loads are their tiles).
+        double dg[2] = {0.0, 0.0};
+        double xg[2] = {0.0, 0.0};   // factor wavefront: entry (u, v) of pivot blocks 0 and 1 of h
+        if (WV == kFactorWave) {
+            if (attempt == 0) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int c = l + 64 * u, cc = c < RR ? c : RR - 1;
-                const double v = gram[(int64_t)cc * RR + cc];
-                dg[u] = c < RR ? v : 0.0;
+                for (int u = 0; u < 2; ++u) {
+                    const int c = l + 64 * u, cc = c < RR ? c : RR - 1;
+                    const double v = gram[(int64_t)cc * RR + cc];
+                    dg[u] = c < RR ? v : 0.0;
+                }
+            }
+            const int u = l >> 3, v = l & 7;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int r = 8 * b + u, c = 8 * b + v;
+                const int rc = r < RR ? r : RR - 1, cc = c < RR ? c : RR - 1;
+                xg[b] = gram[(int64_t)rc * RR + cc];
             }
         }
+        __syncthreads();   // the previous attempt's readers are done with the shared buffers
         double xb[2];      // factor wavefront: entry (u, v) of pivot blocks 0 and 1 of h + eta I
         if (WV == kFactorWave) {
             const int u = l >> 3, v = l & 7;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int r = 8 * b + u, c = 8 * b + v;
-                const int rc = r < RR ? r : RR - 1, cc = c < RR ? c : RR - 1;
-                const double gv = gram[(int64_t)rc * RR + cc];
-                xb[b] = (r < RR && c < RR ? gv : 0.0) + (r == c ? (r < RR ? eta : 1.0) : 0.0);
+                xb[b] = (r < RR && c < RR ? xg[b] : 0.0) + (r == c ? (r < RR ? eta : 1.0) : 0.0);
             }
         } else {
             fill_tiles<NT, WV>(acc, gram, RR, eta);
         }
-        if (attempt == 0) {   // largest diagonal entry of h + eta I: every wavefront reads it itself
-            double mx = fmax(dg[0], dg[1]);
-            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-            const double mxa = mx + eta;
+        if (attempt == 0) {   // largest diagonal entry of h + eta I, handed out through LDS
+            if (WV == kFactorWave) {
+                double mx = fmax(dg[0], dg[1]);
+                for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+                if (l == 0) sh.mxdiag = mx;
+            }
+            __syncthreads();
+            const double mxa = sh.mxdiag + eta;
             int ex = 0;
             if (mxa > 0.0 && isfinite(mxa)) {
                 (void)frexp(mxa, &ex);
