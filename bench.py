@@ -55,6 +55,8 @@ def parse(argv=None):
                     help="timed steps of the 64-problem batched workload (0: skip it)")
     ap.add_argument("--autograd-steps", type=int, default=4000,
                     help="step cap of the differentiation workload's time-to-target runs (0: skip the leg)")
+    ap.add_argument("--seeds", type=int, default=10,
+                    help="time the headline step for seeds 0..SEEDS-1 too (mean and std; 0: skip)")
     ap.add_argument("--methods-budget", type=float, default=0.25,
                     help="seconds of GPU time per comparison method (0: skip the leg)")
     return ap.parse_args(argv)
@@ -378,6 +380,114 @@ def autograd_leg(dev, K=50, steps_cap=4000, every=250):
                        "reading": "10 x the noise floor (noise level x sqrt(parameters / entries)); AdaGrad's "
                                   "stochastic steps plateau near 5 x the floor in both forms"},
             "time_to_target": runs, "rse_every": every}
+
+
+LAWS_ETA = 0.1   # AdaGrad eta of the four-law workload (every law)
+
+
+def seeds_leg(args, I, R, kappa, m, dev, K, seeds=range(10)):
+    """Steps/s of the headline step (the scaled method in ``args.prec``,
+    same launch configuration) for every seed of ``seeds``: each seed plants
+    its own ill-conditioned ring, initial cores and draws; exactly K steps
+    replayed from HIP graphs after ``args.warmup`` eager steps.  Mean,
+    sample standard deviation and median over the seeds."""
+    import torch
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    N = 3
+    rates, status = [], []
+    for sd in seeds:
+        _, X, _, init3 = build_problem(sd, I, R, kappa, dev)
+        sol = TRSolver(cores_to_device(init3, torch.float32, dev), X, [I] * N, [R] * N, m, law="U", scaled=True,
+                       prec=args.prec, rule=api.step_rule("fixed", alpha=args.alpha), seed=sd,
+                       overlap=not args.no_overlap)
+        if args.warmup > 0:
+            sol.run(args.warmup)
+        rates.append(1e3 / replay_timed(sol, K))
+        status.append(int(sol.status.item()))
+        del sol, X
+    r = np.array(rates)
+    return {"seeds": list(seeds), "prec": args.prec, "steps": K,
+            "steps_per_s": [round(float(v), 2) for v in r],
+            "mean": round(float(r.mean()), 2), "std": round(float(r.std(ddof=1)), 2) if r.size > 1 else 0.0,
+            "median": round(float(np.median(r)), 2), "dev_status": status}
+
+
+def laws_leg(dev, K, G=50, every=250, cap=5000):
+    """The four-law workload: order 4, 64 per mode, ranks 5, planted Gaussian
+    ring at RMS 1 + 40 dB noise, FP32 tensor and cores, m = 512 fibers,
+    plain method (TR-BRSGD) with AdaGrad from random cores at the data's
+    scale.  For each fiber law (uniform, Euclidean, leverage, optimal):
+    (1) exactly K steps replayed from HIP graphs (steps/s; the E/L law
+    refresh and the optimal law's per-step distribution are part of each
+    step); (2) the time from the initial cores until the RSE against the
+    noise-free tensor reaches 10x its noise floor sigma sqrt(P / J), P the
+    number of core parameters, J = 64^4 entries (checks every ``every``
+    steps, counted; the steps between checks replay one captured graph)."""
+    import torch
+    import tr_inputs as ti
+    from paper_2303_16492_amd import api
+    from paper_2303_16492_amd.driver import TRSolver, cores_to_device
+    N, I, R, m, db = 4, 64, 5, 512, 40.0
+    desc = api.make_desc([I] * N, [R] * N, torch.float32)
+    Xt = api.tr_reconstruct(desc, cores_to_device(ti.gaussian_cores(0, N, [I] * N, [R] * N), torch.float32, dev))
+    Xt.div_(float(Xt.double().pow(2).mean().sqrt()))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(21)
+    sigma = 10.0 ** (-db / 20.0)
+    X = Xt + sigma * torch.randn(Xt.numel(), generator=gen, device=dev, dtype=torch.float32)
+    # i.i.d. N(0, s^2) cores with E[X(i)^2] = s^(2N) R^N matched to mean(X^2)
+    s = (float(X.double().pow(2).mean()) / float(R ** N)) ** (1.0 / (2 * N))
+    init = ti.gaussian_cores(1, N, [I] * N, [R] * N, scale=s)
+    floor = sigma * (N * I * R * R / float(I ** N)) ** 0.5
+    target = 10.0 * floor
+    xt2 = float(Xt.double().pow(2).sum())
+    out = {"workload": "four-laws-n4-i64-r5-40db", "m": m, "method": "plain (TR-BRSGD)", "precision": "fp32",
+           "rule": f"AdaGrad eta {LAWS_ETA}", "data": "planted Gaussian ring rescaled to RMS 1, 40 dB noise",
+           "start": "i.i.d. Gaussian cores at the data's scale",
+           "target": {"rse_true": target, "floor_estimate": floor,
+                      "reading": "10 x the noise floor (noise level x sqrt(parameters / entries)); AdaGrad's "
+                                 "stochastic steps plateau near 7 x the floor at this eta"},
+           "rse_every": every, "laws": {}}
+    rule = api.step_rule("adagrad", eta=LAWS_ETA)
+    for law in ("U", "E", "L", "O"):
+        sol = TRSolver(cores_to_device(init, torch.float32, dev), X, [I] * N, [R] * N, m, law=law, scaled=False,
+                       prec="f32", rule=rule, seed=0)
+        ms = replay_timed(sol, K, G)
+        rate = {"steps_per_s": round(1e3 / ms, 2), "us_per_step": round(ms * 1e3, 3), "steps": K}
+        del sol
+        sol = TRSolver(cores_to_device(init, torch.float32, dev), X, [I] * N, [R] * N, m, law=law, scaled=False,
+                       prec="f32", rule=rule, seed=0)
+        graph = sol.capture(every)
+        # undo the capture's warm-up step: the run starts from the initial cores at t = 0
+        for c, c0 in zip(sol.cores, cores_to_device(init, torch.float32, dev)):
+            c.copy_(c0)
+        for a in sol.accum:
+            a.zero_()
+        sol.t_dev.zero_()
+        sol.status.zero_()
+        sol.rse(Xt, xt2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, rse, hist = 0, float("nan"), []
+        while steps < cap:
+            graph.replay()
+            steps += every
+            rse = float(sol.rse(Xt, xt2))       # synchronises
+            hist.append((steps, rse))
+            if rse <= target:
+                break
+        wall = time.perf_counter() - t0
+        status = int(sol.status.item())
+        del graph, sol
+        out["laws"][law] = {**rate, "time_to_target": {
+            "reached": rse <= target, "seconds": round(wall, 4) if rse <= target else None, "steps": steps,
+            "rse_at_stop": rse, "rse_trace": [[s_, float(f"{r_:.4e}")] for s_, r_ in hist[:: max(1, len(hist) // 8)]]},
+            "dev_status": status}
+        print(f"[bench] four-law workload, law {law}: {rate['us_per_step']} us/step, "
+              f"rse {rse:.3e} after {steps} steps ({wall:.3f} s)", file=sys.stderr, flush=True)
+    del X, Xt
+    return out
 
 
 def c1_time_to_target(dev, target=1e-4, every=10, cap=2000):
@@ -909,6 +1019,15 @@ def main():
     if args.autograd_steps > 0:
         autograd = autograd_leg(dev, steps_cap=args.autograd_steps)
         print(f"[bench] autograd: {json.dumps(autograd)}", file=sys.stderr, flush=True)
+    seeds = None
+    if args.seeds > 0:
+        seeds = seeds_leg(args, I, R, kappa, m, dev, max(K, 200), seeds=range(args.seeds))
+        print(f"[bench] seeds 0-{args.seeds - 1}: {seeds['mean']} +- {seeds['std']} steps/s", file=sys.stderr,
+              flush=True)
+    laws4 = None
+    if args.ttt_steps > 0:
+        laws4 = laws_leg(dev, K)
+        torch.cuda.empty_cache()
     c1 = None
     if args.ttt_steps > 0:
         c1 = c1_time_to_target(dev)
@@ -966,6 +1085,8 @@ def main():
         "eager_steps_per_s": round(1e3 / main["eager_ms_per_step"], 2),
         "forms_plain_method": plain,
         "forms_laws": laws,
+        "four_laws": laws4,
+        "seeds": seeds,
         "time_to_target": ttt,
         "time_to_target_planted": {"workload": "planted-gaussian-n3-i400-r10", "method": "scaled", "m": m,
                                    "law": "uniform", "alpha": args.alpha, "runs": planted},

@@ -272,7 +272,9 @@ typedef struct {
     void* cores[TR_MAX_ORDER];           /* device G_{k(2)}, updated in place */
     void* accum[TR_MAX_ORDER];           /* AdaGrad accumulators or NULL     */
     const void* X;                       /* device tensor (fit target)       */
-    const void* Xrep[TR_MAX_ORDER];      /* mode-major replicas or NULL      */
+    const void* Xrep[TR_MAX_ORDER];      /* mode-major replicas or NULL (with
+                                          * all N given, the fiber gathers and
+                                          * the optimal law read them)        */
     uint64_t* cdf[TR_MAX_ORDER];         /* per-mode CDF buffers [I_k] (laws L, E) */
     uint64_t* cdf_J;                     /* CDF buffer [max_n J_n] (law O)   */
 } tr_problem;

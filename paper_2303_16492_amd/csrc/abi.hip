@@ -476,8 +476,6 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
         xs.rep[k] = p->Xrep[k];
         if (c->law == TR_LAW_LEVERAGE || c->law == TR_LAW_EUCLID) cdf.p[k] = p->cdf[k];
     }
-    XSrc xs_paper{};
-    xs_paper.X = p->X;
     hipError_t e = hipSuccess;
     const bool refresh = c->law == TR_LAW_LEVERAGE || c->law == TR_LAW_EUCLID;
     // The step counter advances in the last kernel of a step: the update,
@@ -519,7 +517,7 @@ tr_status tr_run_ex(const tr_problem* p, const tr_config* c, uint64_t* t_dev, in
         const bool fork_early = fork && c->m_H > 0 && same_shape;
         hipStream_t hs = fork ? (hipStream_t)o.aux : st;
         if (c->law == TR_LAW_OPTIMAL)
-            e = launch_dist_optimal(d, ms_draw, cores, xs_paper, p->cdf_J, dev_status, w + L.opt, st);
+            e = launch_dist_optimal(d, ms_draw, cores, xs, p->cdf_J, dev_status, w + L.opt, st);
         if (e == hipSuccess && fork_early) {
             e = hipEventRecord((hipEvent_t)o.ev_fork, st);
             if (e == hipSuccess) e = hipStreamWaitEvent(hs, (hipEvent_t)o.ev_fork, 0);

@@ -583,6 +583,7 @@ __global__ __launch_bounds__(kOptBlock) void k_opt_terms(tr_desc d, ModeSrc ms, 
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    n = __builtin_amdgcn_readfirstlane(n);   // uniform: its table reads stay scalar
     const int N = d.N;
     const int n1 = ring_next(n, N);
     const int Rn = d.R[n], Rn1 = d.R[n1];
@@ -640,12 +641,177 @@ __global__ __launch_bounds__(kOptBlock) void k_opt_terms(tr_desc d, ModeSrc ms, 
     a[j] = sqrt(rr) * sqrt(ss);
 }
 
+// The same terms read from the mode-major replica of X, where the fiber
+// X_[n](:,j) is contiguous at j I_n (columns in the ring order n+1, n+2, ...
+// with the first fastest, as above).  A block takes kOptCols consecutive
+// columns.  It copies the other cores into LDS (one coalesced pass), forms
+// s_j of every column there (one thread per (column, row s of the chain
+// product)), and each wavefront then takes kOptCols / 4 consecutive columns
+// with one lane per row i = lane + 64 q of the fiber: all of its fiber loads
+// are issued before any arithmetic, its rows of G_{n(2)} sit in registers,
+// and the squared residuals of its columns are added across the wavefront
+// in a fixed order, the columns' reductions interleaved.  Needs I_n <= 64 Q,
+// R_n R_{n+1} <= kOptRRMax, every rank <= kOptRank, J_n < 2^31 and the other
+// cores within the LDS bound.
+constexpr int kOptCols = 64;
+constexpr int kOptRRMax = 32;
+constexpr int kOptRank = 8;                   // every R_k
+constexpr int kOptCpw = kOptCols / 4;          // columns per wavefront
+constexpr size_t kOptCoreLds = 40 * 1024;      // bytes of staged cores (with the static LDS, under 64 KiB)
+
+template <typename TC, typename TX, int Q>
+__global__ __launch_bounds__(256) void k_opt_terms_rep(tr_desc d, ModeSrc ms, Ptrs cores, XSrc xs,
+                                                       double* __restrict__ a) {
+    uint64_t t;
+    int n;
+    resolve_mode(ms, d.N, &t, &n);
+    n = __builtin_amdgcn_readfirstlane(n);   // uniform: its table reads stay scalar
+    const int N = d.N;
+    const int n1 = ring_next(n, N);
+    const int Rn = d.R[n], Rn1 = d.R[n1];
+    const int RR = Rn * Rn1, In = d.I[n];
+    const int64_t J = J_of(d, n);
+    const int64_t j0 = (int64_t)blockIdx.x * kOptCols;
+    if (j0 >= J) return;   // the whole block
+    extern __shared__ __align__(16) unsigned char opt_smem[];
+    TC* sC = reinterpret_cast<TC*>(opt_smem);   // cores n+1, ..., n-1 back to back
+    __shared__ double sS[kOptCols][kOptRRMax + 1];
+    __shared__ double sN[kOptCols];
+    __shared__ int coff[kMaxOrder];
+    const int tid = threadIdx.x;
+    {
+        int o = 0, k = n1;
+        for (int q = 1; q < N; ++q) {
+            const int sz = d.I[k] * d.R[k] * d.R[ring_next(k, N)];
+            if (tid == 0) coff[k] = o;
+            const TC* src = static_cast<const TC*>(cores.p[k]);
+            for (int e = tid; e < sz; e += 256) sC[o + e] = src[e];
+            o += sz;
+            k = ring_next(k, N);
+        }
+    }
+    for (int e = tid; e < kOptCols * (kOptRRMax + 1); e += 256) (&sS[0][0])[e] = 0.0;
+    __syncthreads();
+    // Row s of the chain product of column j: the slices of cores n+1, ...,
+    // n-1 at the column's indices (decoded in that order, the first
+    // fastest), every loop bounded by kOptRank at compile time so that the
+    // row stays in registers and a stage's LDS reads issue together.
+    for (int w = tid; w < kOptCols * Rn1; w += 256) {
+        const int c = w / Rn1, s = w - c * Rn1;
+        if (j0 + c >= J) continue;
+        uint32_t rem = (uint32_t)(j0 + c);
+        int k = n1;
+        int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
+        uint32_t ik = rem % (uint32_t)d.I[k];
+        rem /= (uint32_t)d.I[k];
+        const TC* A = sC + coff[k] + ik * Rk * Rk1;
+        double v[kOptRank];
+#pragma unroll
+        for (int cc = 0; cc < kOptRank; ++cc) v[cc] = cc < Rk1 ? (double)A[s + Rk * cc] : 0.0;
+        for (int q = 2; q < N; ++q) {
+            k = ring_next(k, N);
+            Rk = d.R[k];
+            Rk1 = d.R[ring_next(k, N)];
+            ik = rem % (uint32_t)d.I[k];
+            rem /= (uint32_t)d.I[k];
+            A = sC + coff[k] + ik * Rk * Rk1;
+            double nv[kOptRank];
+#pragma unroll
+            for (int cc = 0; cc < kOptRank; ++cc) nv[cc] = 0.0;
+#pragma unroll
+            for (int r = 0; r < kOptRank; ++r) {
+                if (r < Rk) {
+#pragma unroll
+                    for (int cc = 0; cc < kOptRank; ++cc)
+                        if (cc < Rk1) nv[cc] += v[r] * (double)A[r + Rk * cc];
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < kOptRank; ++cc) v[cc] = nv[cc];
+        }
+#pragma unroll
+        for (int r = 0; r < kOptRank; ++r)
+            if (r < Rn) sS[c][r + Rn * s] = v[r];
+    }
+    // the wavefront's fibers: requested before the barrier, used after it
+    const int lane = tid & 63, wv = tid >> 6;
+    const TX* Xn = static_cast<const TX*>(xs.rep[n]);
+    double xv[Q][kOptCpw];
+#pragma unroll
+    for (int u = 0; u < kOptCpw; ++u) {
+        const int64_t j = j0 + wv * kOptCpw + u;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = lane + 64 * q;
+            xv[q][u] = (j < J && i < In) ? to_f64(Xn[j * In + i]) : 0.0;
+        }
+    }
+    const TC* Gn = static_cast<const TC*>(cores.p[n]);
+    double gr[Q][kOptRRMax];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = lane + 64 * q;
+#pragma unroll
+        for (int cc = 0; cc < kOptRRMax; ++cc)
+            gr[q][cc] = (i < In && cc < RR) ? (double)Gn[(int64_t)i * RR + cc] : 0.0;
+    }
+    __syncthreads();
+    if (tid < kOptCols) {
+        double ss = 0.0;
+        for (int cc = 0; cc < RR; ++cc) ss += sS[tid][cc] * sS[tid][cc];
+        sN[tid] = ss;
+    }
+    __syncthreads();
+    double rr[kOptCpw];
+#pragma unroll
+    for (int u = 0; u < kOptCpw; ++u) {
+        const int c = wv * kOptCpw + u;
+        rr[u] = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = lane + 64 * q;
+            double pred = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < kOptRRMax; ++cc) pred += gr[q][cc] * sS[c][cc];
+            const double r = xv[q][u] - pred;
+            rr[u] += i < In ? r * r : 0.0;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int u = 0; u < kOptCpw; ++u) rr[u] += __shfl_xor(rr[u], o, 64);
+    if (lane < kOptCpw) {
+        double mine = rr[0];
+#pragma unroll
+        for (int u = 1; u < kOptCpw; ++u) mine = lane == u ? rr[u] : mine;
+        const int c = wv * kOptCpw + lane;
+        const int64_t j = j0 + c;
+        if (j < J) a[j] = sqrt(mine) * sqrt(sN[c]);
+    }
+}
+
+// Bytes of the other cores staged by k_opt_terms_rep for the mode with the
+// largest sum, or 0 above the LDS bound.
+size_t opt_core_lds(const tr_desc& d) {
+    const size_t es = d.core_dtype == TR_F64 ? 8 : 4;
+    size_t worst = 0;
+    for (int n = 0; n < d.N; ++n) {
+        size_t tot = 0;
+        for (int k = 0; k < d.N; ++k)
+            if (k != n) tot += (size_t)d.I[k] * d.R[k] * d.R[ring_next(k, d.N)] * es;
+        worst = tot > worst ? tot : worst;
+    }
+    return worst <= kOptCoreLds ? (worst + 15) / 16 * 16 : 0;
+}
+
 // Per-block FP64 sums of a (fixed order within a block).
 __global__ __launch_bounds__(kOptBlock) void k_opt_blocksum(tr_desc d, ModeSrc ms, const double* __restrict__ a,
                                                            double* __restrict__ bs) {
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    n = __builtin_amdgcn_readfirstlane(n);   // uniform: its table reads stay scalar
     const int64_t J = J_of(d, n);
     const int64_t nb = (J + kOptBlock - 1) / kOptBlock;
     if (blockIdx.x >= nb) return;
@@ -662,17 +828,15 @@ __global__ __launch_bounds__(kOptBlock) void k_opt_quantize(tr_desc d, ModeSrc m
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    n = __builtin_amdgcn_readfirstlane(n);   // uniform: its table reads stay scalar
     const int64_t J = J_of(d, n);
     const int64_t nb = (J + kOptBlock - 1) / kOptBlock;
     if (blockIdx.x >= nb) return;
-    __shared__ double tot_s;
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int64_t b = 0; b < nb; ++b) s += bs[b];
-        tot_s = s;
-    }
-    __syncthreads();
-    const double tot = tot_s;
+    // the total of the block sums, the same fixed order in every block
+    double part = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += kOptBlock) part += bs[b];
+    __shared__ double red[kOptBlock / 64];
+    const double tot = block_sum(part, red);
     const bool zero = !(tot > 0.0) || !isfinite(tot);
     if (zero && blockIdx.x == 0 && threadIdx.x == 0) set_status(status, TR_DEV_ZERO_DIST);
     const int64_t j = (int64_t)blockIdx.x * kOptBlock + threadIdx.x;
@@ -699,31 +863,21 @@ __global__ __launch_bounds__(1024) void k_opt_offsets(tr_desc d, ModeSrc ms, uin
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    n = __builtin_amdgcn_readfirstlane(n);   // uniform: its table reads stay scalar
     const int64_t J = J_of(d, n);
     const int64_t nb = (J + kOptBlock - 1) / kOptBlock;
-    // exclusive scan of the block totals, in place
-    __shared__ uint64_t part[1024];
+    // exclusive scan of the block totals, in place: the inclusive scan
+    // (integer sums, exact), then every entry takes its predecessor's value,
+    // each thread shifting its own segment (the one entry it reads from the
+    // segment before is read ahead of a barrier)
+    block_scan_u64(wbs, nb);
     const int T = blockDim.x;
     const int64_t per = (nb + T - 1) / T;
     const int64_t b = threadIdx.x * per, e = min(nb, b + per);
-    uint64_t s = 0;
-    for (int64_t i = b; i < e; ++i) {
-        const uint64_t v = wbs[i];
-        wbs[i] = s;
-        s += v;
-    }
-    part[threadIdx.x] = s;
+    const uint64_t prev = (b > 0 && b < nb) ? wbs[b - 1] : 0ull;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t run = 0;
-        for (int i = 0; i < T; ++i) {
-            const uint64_t v = part[i];
-            part[i] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    for (int64_t i = b; i < e; ++i) wbs[i] += part[threadIdx.x];
+    for (int64_t i = e - 1; i > b; --i) wbs[i] = wbs[i - 1];
+    if (b < nb) wbs[b] = prev;
 }
 
 __global__ __launch_bounds__(kOptBlock) void k_opt_apply(tr_desc d, ModeSrc ms, const uint64_t* __restrict__ wbs,
@@ -731,6 +885,7 @@ __global__ __launch_bounds__(kOptBlock) void k_opt_apply(tr_desc d, ModeSrc ms, 
     uint64_t t;
     int n;
     resolve_mode(ms, d.N, &t, &n);
+    n = __builtin_amdgcn_readfirstlane(n);   // uniform: its table reads stay scalar
     const int64_t J = J_of(d, n);
     const int64_t j = (int64_t)blockIdx.x * kOptBlock + threadIdx.x;
     if (j < J) w[j] += wbs[blockIdx.x];
@@ -752,7 +907,26 @@ hipError_t launch_dist_optimal(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
     uint64_t* wbs = reinterpret_cast<uint64_t*>(w + align_up((size_t)sh.maxJ * 8) + align_up((size_t)nb * 8));
     const dim3 grid((unsigned)nb);
     const bool f64 = d.core_dtype == TR_F64;
-    if (f64 && d.x_dtype == TR_F64)
+    bool reps = true;
+    for (int k = 0; k < d.N; ++k) reps = reps && xs.rep[k] != nullptr;
+    const size_t clds = opt_core_lds(d);
+    if (reps && clds > 0 && sh.maxI <= 128 && sh.maxRR <= kOptRRMax && sh.maxR <= kOptRank &&
+        sh.maxJ < ((int64_t)1 << 31)) {
+        const dim3 gr((unsigned)((sh.maxJ + kOptCols - 1) / kOptCols));
+        const bool one = sh.maxI <= 64;
+        if (f64 && d.x_dtype == TR_F64) {
+            if (one) hipLaunchKernelGGL((k_opt_terms_rep<double, double, 1>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+            else hipLaunchKernelGGL((k_opt_terms_rep<double, double, 2>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+        } else if (!f64 && d.x_dtype == TR_F32) {
+            if (one) hipLaunchKernelGGL((k_opt_terms_rep<float, float, 1>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+            else hipLaunchKernelGGL((k_opt_terms_rep<float, float, 2>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+        } else if (!f64 && d.x_dtype == TR_F16) {
+            if (one) hipLaunchKernelGGL((k_opt_terms_rep<float, __half, 1>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+            else hipLaunchKernelGGL((k_opt_terms_rep<float, __half, 2>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (f64 && d.x_dtype == TR_F64)
         hipLaunchKernelGGL((k_opt_terms<double, double>), grid, dim3(kOptBlock), 0, st, d, ms, cores, xs, a);
     else if (!f64 && d.x_dtype == TR_F32)
         hipLaunchKernelGGL((k_opt_terms<float, float>), grid, dim3(kOptBlock), 0, st, d, ms, cores, xs, a);

@@ -242,6 +242,17 @@ def test_adagrad_run_each_law_at_full_size(law):
         assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-4, (law, k)
 
 
+def test_optimal_law_run_fibers_longer_than_a_wavefront():
+    """Law O through tr_run with mode sizes above 64 (two fiber rows per
+    lane when the law's terms read the mode-major replicas) and mixed ranks:
+    12 AdaGrad steps in FP64 against the oracle."""
+    say("run law O, I up to 100")
+    sol, st, X = _run_both(3, [70, 90, 100], [3, 4, 2], torch.float64, 64, "O", False, "adagrad", 12)
+    assert sol.t == 12 and int(sol.status.item()) == st.status
+    for k in range(3):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-10, k
+
+
 def _graph_steps(sol, steps):
     """``steps`` steps from one captured graph of that length, replayed once
     (the capture itself runs one eager step first)."""
