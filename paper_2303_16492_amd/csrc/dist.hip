@@ -646,17 +646,16 @@ __global__ __launch_bounds__(kOptBlock) void k_opt_terms(tr_desc d, ModeSrc ms, 
 // with the first fastest, as above).  A block takes kOptCols consecutive
 // columns.  It copies the other cores into LDS (one coalesced pass), forms
 // s_j of every column there (one thread per (column, row s of the chain
-// product)), and each wavefront then takes kOptCols / 4 consecutive columns
-// with one lane per row i = lane + 64 q of the fiber: all of its fiber loads
-// are issued before any arithmetic, its rows of G_{n(2)} sit in registers,
-// and the squared residuals of its columns are added across the wavefront
-// in a fixed order, the columns' reductions interleaved.  Needs I_n <= 64 Q,
+// product)), and each wavefront then takes kOptCols / 4 consecutive columns:
+// the predictions G_{n(2)} s_j of its 16 columns are 16 x 16 tiles of FP64
+// matrix-core products (its fiber entries requested, in the products'
+// result layout, before any arithmetic), and the squared residuals of a
+// column are added over its rows in a fixed order.  Needs I_n <= 64 Q,
 // R_n R_{n+1} <= kOptRRMax, every rank <= kOptRank, J_n < 2^31 and the other
 // cores within the LDS bound.
 constexpr int kOptCols = 64;
 constexpr int kOptRRMax = 32;
 constexpr int kOptRank = 8;                   // every R_k
-constexpr int kOptCpw = kOptCols / 4;          // columns per wavefront
 constexpr size_t kOptCoreLds = 40 * 1024;      // bytes of staged cores (with the static LDS, under 64 KiB)
 
 template <typename TC, typename TX, int Q>
@@ -733,62 +732,68 @@ __global__ __launch_bounds__(256) void k_opt_terms_rep(tr_desc d, ModeSrc ms, Pt
         for (int r = 0; r < kOptRank; ++r)
             if (r < Rn) sS[c][r + Rn * s] = v[r];
     }
-    // the wavefront's fibers: requested before the barrier, used after it
-    const int lane = tid & 63, wv = tid >> 6;
+    // Wavefront w takes the block's columns 16 w .. 16 w + 15.  Its fiber
+    // entries are requested before the barrier, in the layout of the matrix
+    // core's result: lane l holds column 16 w + l % 16 at rows
+    // 16 rt + 4 e + l / 16 (row tile rt, entry e of the 16 x 16 result).
+    const int lane = tid & 63, wv = tid >> 6, lc = lane & 15, lk = lane >> 4;
+    const int c = wv * 16 + lc;
+    const int64_t jc = j0 + c;
+    const bool colok = jc < J;
     const TX* Xn = static_cast<const TX*>(xs.rep[n]);
-    double xv[Q][kOptCpw];
+    const int RT = (In + 15) >> 4, KS = (RR + 3) >> 2;
+    double xv[4 * Q][4];
 #pragma unroll
-    for (int u = 0; u < kOptCpw; ++u) {
-        const int64_t j = j0 + wv * kOptCpw + u;
+    for (int rt = 0; rt < 4 * Q; ++rt)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int i = lane + 64 * q;
-            xv[q][u] = (j < J && i < In) ? to_f64(Xn[j * In + i]) : 0.0;
+        for (int e = 0; e < 4; ++e) {
+            const int i = 16 * rt + 4 * e + lk;
+            xv[rt][e] = (colok && i < In) ? to_f64(Xn[jc * In + i]) : 0.0;
         }
-    }
-    const TC* Gn = static_cast<const TC*>(cores.p[n]);
-    double gr[Q][kOptRRMax];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int i = lane + 64 * q;
-#pragma unroll
-        for (int cc = 0; cc < kOptRRMax; ++cc)
-            gr[q][cc] = (i < In && cc < RR) ? (double)Gn[(int64_t)i * RR + cc] : 0.0;
-    }
     __syncthreads();
     if (tid < kOptCols) {
         double ss = 0.0;
         for (int cc = 0; cc < RR; ++cc) ss += sS[tid][cc] * sS[tid][cc];
         sN[tid] = ss;
     }
-    __syncthreads();
-    double rr[kOptCpw];
+    // pred = G_{n(2)} s_j on the FP64 matrix cores, K = 4 entries of s_j per
+    // instruction: A[row][k] = G(16 rt + row, 4 ks + k) (lane l: row l % 16,
+    // k = l / 16), B[k][col] = s_j(4 ks + k) of column 16 w + col (lane l:
+    // k = l / 16, col = l % 16); entries past R_n R_{n+1} are zeros in sS.
+    // (A operands loaded beside the fibers instead measured slower: the
+    // extra registers cut the wavefronts per SIMD from 6 to 3.)
+    typedef double od4 __attribute__((ext_vector_type(4)));
+    const TC* Gn = static_cast<const TC*>(cores.p[n]);
+    double bv[kOptRRMax / 4];
 #pragma unroll
-    for (int u = 0; u < kOptCpw; ++u) {
-        const int c = wv * kOptCpw + u;
-        rr[u] = 0.0;
+    for (int ks = 0; ks < kOptRRMax / 4; ++ks) bv[ks] = sS[c][4 * ks + lk];
+    double rr = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int i = lane + 64 * q;
-            double pred = 0.0;
+    for (int rt = 0; rt < 4 * Q; ++rt) {
+        if (rt < RT) {
+            od4 acc = {0.0, 0.0, 0.0, 0.0};
+            const int gi = 16 * rt + lc;
 #pragma unroll
-            for (int cc = 0; cc < kOptRRMax; ++cc) pred += gr[q][cc] * sS[c][cc];
-            const double r = xv[q][u] - pred;
-            rr[u] += i < In ? r * r : 0.0;
+            for (int ks = 0; ks < kOptRRMax / 4; ++ks) {
+                if (ks < KS) {
+                    const int gk = 4 * ks + lk;
+                    const double av = (gi < In && gk < RR) ? (double)Gn[gi * RR + gk] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ks], acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * rt + 4 * e + lk;
+                const double r = xv[rt][e] - acc[e];
+                rr += i < In ? r * r : 0.0;
+            }
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int u = 0; u < kOptCpw; ++u) rr[u] += __shfl_xor(rr[u], o, 64);
-    if (lane < kOptCpw) {
-        double mine = rr[0];
-#pragma unroll
-        for (int u = 1; u < kOptCpw; ++u) mine = lane == u ? rr[u] : mine;
-        const int c = wv * kOptCpw + lane;
-        const int64_t j = j0 + c;
-        if (j < J) a[j] = sqrt(mine) * sqrt(sN[c]);
-    }
+    // the four row groups of each column, in a fixed order
+    rr += __shfl_xor(rr, 16, 64);
+    rr += __shfl_xor(rr, 32, 64);
+    __syncthreads();
+    if (lk == 0 && colok) a[jc] = sqrt(rr) * sqrt(sN[c]);
 }
 
 // Bytes of the other cores staged by k_opt_terms_rep for the mode with the
