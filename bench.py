@@ -842,6 +842,40 @@ def relerr_timing(desc, cores, X, reps=20):
     return a.elapsed_time(b) / reps * 1e3, float(out.item())
 
 
+def step_roofline(main, plain, batched, laws4, I, R, m):
+    """Whole-step fractions: the algorithmic lower bound of one step (what
+    the method must compute or move, at the chip's peak) over the measured
+    step time, for the workloads whose bound is not latency."""
+    out = {}
+    RR = R * R
+    # 400^3, ranks 10, m = 4096: prediction and gradient contractions
+    # 2 I m RR FMA plus the sampled Gram m RR^2 FMA on FP32 matrix cores
+    fma = 2.0 * I * m * RR + m * RR * RR
+    b_c3 = 2.0 * fma / (PEAK["f32"][0] * 1e12) * 1e6
+    out["scaled_fp32"] = {"bound_us": round(b_c3, 3), "measured_us": round(main["ms_per_step"] * 1e3, 3),
+                          "frac": round(b_c3 / (main["ms_per_step"] * 1e3), 4),
+                          "basis": f"{fma / 1e6:.1f} M FMA at the FP32 matrix-core peak (the FP64 inverse's "
+                                   f"RR^3/3 FMA and the HBM traffic, 0.9 us at 8 TB/s, below it)"}
+    if plain and "f32" in plain:
+        out["plain_fp32"] = {"bound_us": round(b_c3, 3), "measured_us": plain["f32"]["us_per_step"],
+                             "frac": round(b_c3 / plain["f32"]["us_per_step"], 4), "basis": "as scaled_fp32"}
+    if batched:
+        # the 64-problem draw: fibers and cores of every problem's step, about 9.4 MB, at 8 TB/s
+        b_c5 = 9.4e6 / (HBM_PEAK_GBS * 1e9) * 1e6
+        ms = batched["ms_per_batch_step"] * 1e3
+        out["batched_64"] = {"bound_us": round(b_c5, 3), "measured_us": round(ms, 3), "frac": round(b_c5 / ms, 4),
+                             "basis": "about 9.4 MB of fibers and cores per step of all 64 problems at 8 TB/s"}
+    if laws4 and "O" in laws4["laws"]:
+        # law O: the residual of every column, J I RR = 64^4 25 FP64 FMA at the FP64 peak (10.7 us), above
+        # the 64 MiB tensor read once at 8 TB/s (8.4 us)
+        b_o = 2.0 * 64 ** 4 * 25 / (PEAK["f64"][0] * 1e12) * 1e6
+        us = laws4["laws"]["O"]["us_per_step"]
+        out["optimal_law_order4"] = {"bound_us": round(b_o, 3), "measured_us": us, "frac": round(b_o / us, 4),
+                                     "basis": "419 M FP64 FMA of the law's residuals at the FP64 peak (the 64 MiB "
+                                              "tensor read once: 8.4 us at 8 TB/s)"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1096,6 +1130,7 @@ def main():
                                                            if len(planted_plain) == 2 and planted_plain[0]["reached"]
                                                            and planted_plain[1]["reached"] else None)},
         "relerr": relerr,
+        "step_roofline": step_roofline(main, plain, batched, laws4, I, R, m),
         "batched": batched,
         "autograd": autograd,
         "time_to_target_plain_fp64": c1,

@@ -44,3 +44,25 @@ def test_more_than_one_gpu_exits_with_message():
 def test_host_info_fields():
     h = bench.host_info()
     assert h["nproc"] >= 1 and h["logical_cpus"] >= 1
+
+
+def test_step_roofline_bounds_and_fractions():
+    """Whole-step bounds from their closed forms: 2 (2 I m RR + m RR^2) FLOP
+    at 157.3 TFLOP/s for the 400^3 step, 9.4 MB at 8 TB/s for the batch, and
+    2 * 64^4 * 25 FLOP at 78.6 TFLOP/s for the optimal law; each fraction is
+    bound / measured."""
+    main = {"ms_per_step": 0.05}
+    plain = {"f32": {"us_per_step": 25.0}}
+    batched = {"ms_per_batch_step": 0.1}
+    laws4 = {"laws": {"O": {"us_per_step": 100.0}}}
+    out = bench.step_roofline(main, plain, batched, laws4, 400, 10, 4096)
+    c3 = 2 * (2 * 400 * 4096 * 100 + 4096 * 100 * 100) / 157.3e12 * 1e6
+    assert out["scaled_fp32"]["bound_us"] == pytest.approx(c3, abs=1e-3)
+    assert out["scaled_fp32"]["frac"] == pytest.approx(c3 / 50.0, abs=1e-4)
+    assert out["plain_fp32"]["frac"] == pytest.approx(c3 / 25.0, abs=1e-4)
+    assert out["batched_64"]["bound_us"] == pytest.approx(9.4e6 / 8e12 * 1e6, abs=1e-3)
+    assert out["batched_64"]["frac"] == pytest.approx(1.175 / 100.0, abs=1e-4)
+    o = 2 * 64 ** 4 * 25 / 78.6e12 * 1e6
+    assert out["optimal_law_order4"]["bound_us"] == pytest.approx(o, abs=1e-3)
+    assert out["optimal_law_order4"]["frac"] == pytest.approx(o / 100.0, abs=1e-4)
+    assert set(bench.step_roofline(main, None, None, None, 400, 10, 4096)) == {"scaled_fp32"}
