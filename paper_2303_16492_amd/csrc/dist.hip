@@ -644,19 +644,20 @@ __global__ __launch_bounds__(kOptBlock) void k_opt_terms(tr_desc d, ModeSrc ms, 
 // The same terms read from the mode-major replica of X, where the fiber
 // X_[n](:,j) is contiguous at j I_n (columns in the ring order n+1, n+2, ...
 // with the first fastest, as above).  A block takes kOptCols consecutive
-// columns.  It copies the other cores into LDS (one coalesced pass), forms
-// s_j of every column there (one thread per (column, row s of the chain
-// product)), and each wavefront then takes kOptCols / 4 consecutive columns:
+// columns.  It forms s_j of every column in LDS (one thread per (column,
+// row s of the chain product), the slices read from the cores in global
+// memory, which stay in cache), and each wavefront then takes kOptCols / 4
+// consecutive columns:
 // the predictions G_{n(2)} s_j of its 16 columns are 16 x 16 tiles of FP64
 // matrix-core products (its fiber entries requested, in the products'
 // result layout, before any arithmetic), and the squared residuals of a
 // column are added over its rows in a fixed order.  Needs I_n <= 64 Q,
-// R_n R_{n+1} <= kOptRRMax, every rank <= kOptRank, J_n < 2^31 and the other
-// cores within the LDS bound.
+// R_n R_{n+1} <= kOptRRMax, every rank <= kOptRank and J_n < 2^31.  (At the
+// order-4 workload, staging the other cores in LDS measured the same, 98 us;
+// all N cores 120 us and G_{n(2)} alone 102 us.)
 constexpr int kOptCols = 64;
 constexpr int kOptRRMax = 32;
 constexpr int kOptRank = 8;                   // every R_k
-constexpr size_t kOptCoreLds = 40 * 1024;      // bytes of staged cores (with the static LDS, under 64 KiB)
 
 template <typename TC, typename TX, int Q>
 __global__ __launch_bounds__(256) void k_opt_terms_rep(tr_desc d, ModeSrc ms, Ptrs cores, XSrc xs,
@@ -672,23 +673,9 @@ __global__ __launch_bounds__(256) void k_opt_terms_rep(tr_desc d, ModeSrc ms, Pt
     const int64_t J = J_of(d, n);
     const int64_t j0 = (int64_t)blockIdx.x * kOptCols;
     if (j0 >= J) return;   // the whole block
-    extern __shared__ __align__(16) unsigned char opt_smem[];
-    TC* sC = reinterpret_cast<TC*>(opt_smem);   // cores n+1, ..., n-1 back to back
     __shared__ double sS[kOptCols][kOptRRMax + 1];
     __shared__ double sN[kOptCols];
-    __shared__ int coff[kMaxOrder];
     const int tid = threadIdx.x;
-    {
-        int o = 0, k = n1;
-        for (int q = 1; q < N; ++q) {
-            const int sz = d.I[k] * d.R[k] * d.R[ring_next(k, N)];
-            if (tid == 0) coff[k] = o;
-            const TC* src = static_cast<const TC*>(cores.p[k]);
-            for (int e = tid; e < sz; e += 256) sC[o + e] = src[e];
-            o += sz;
-            k = ring_next(k, N);
-        }
-    }
     for (int e = tid; e < kOptCols * (kOptRRMax + 1); e += 256) (&sS[0][0])[e] = 0.0;
     __syncthreads();
     // Row s of the chain product of column j: the slices of cores n+1, ...,
@@ -703,7 +690,7 @@ __global__ __launch_bounds__(256) void k_opt_terms_rep(tr_desc d, ModeSrc ms, Pt
         int Rk = d.R[k], Rk1 = d.R[ring_next(k, N)];
         uint32_t ik = rem % (uint32_t)d.I[k];
         rem /= (uint32_t)d.I[k];
-        const TC* A = sC + coff[k] + ik * Rk * Rk1;
+        const TC* A = static_cast<const TC*>(cores.p[k]) + ik * Rk * Rk1;
         double v[kOptRank];
 #pragma unroll
         for (int cc = 0; cc < kOptRank; ++cc) v[cc] = cc < Rk1 ? (double)A[s + Rk * cc] : 0.0;
@@ -713,7 +700,7 @@ __global__ __launch_bounds__(256) void k_opt_terms_rep(tr_desc d, ModeSrc ms, Pt
             Rk1 = d.R[ring_next(k, N)];
             ik = rem % (uint32_t)d.I[k];
             rem /= (uint32_t)d.I[k];
-            A = sC + coff[k] + ik * Rk * Rk1;
+            A = static_cast<const TC*>(cores.p[k]) + ik * Rk * Rk1;
             double nv[kOptRank];
 #pragma unroll
             for (int cc = 0; cc < kOptRank; ++cc) nv[cc] = 0.0;
@@ -796,19 +783,6 @@ __global__ __launch_bounds__(256) void k_opt_terms_rep(tr_desc d, ModeSrc ms, Pt
     if (lk == 0 && colok) a[jc] = sqrt(rr) * sqrt(sN[c]);
 }
 
-// Bytes of the other cores staged by k_opt_terms_rep for the mode with the
-// largest sum, or 0 above the LDS bound.
-size_t opt_core_lds(const tr_desc& d) {
-    const size_t es = d.core_dtype == TR_F64 ? 8 : 4;
-    size_t worst = 0;
-    for (int n = 0; n < d.N; ++n) {
-        size_t tot = 0;
-        for (int k = 0; k < d.N; ++k)
-            if (k != n) tot += (size_t)d.I[k] * d.R[k] * d.R[ring_next(k, d.N)] * es;
-        worst = tot > worst ? tot : worst;
-    }
-    return worst <= kOptCoreLds ? (worst + 15) / 16 * 16 : 0;
-}
 
 // Per-block FP64 sums of a (fixed order within a block).
 __global__ __launch_bounds__(kOptBlock) void k_opt_blocksum(tr_desc d, ModeSrc ms, const double* __restrict__ a,
@@ -914,20 +888,19 @@ hipError_t launch_dist_optimal(const tr_desc& d, ModeSrc ms, Ptrs cores, XSrc xs
     const bool f64 = d.core_dtype == TR_F64;
     bool reps = true;
     for (int k = 0; k < d.N; ++k) reps = reps && xs.rep[k] != nullptr;
-    const size_t clds = opt_core_lds(d);
-    if (reps && clds > 0 && sh.maxI <= 128 && sh.maxRR <= kOptRRMax && sh.maxR <= kOptRank &&
+    if (reps && sh.maxI <= 128 && sh.maxRR <= kOptRRMax && sh.maxR <= kOptRank &&
         sh.maxJ < ((int64_t)1 << 31)) {
         const dim3 gr((unsigned)((sh.maxJ + kOptCols - 1) / kOptCols));
         const bool one = sh.maxI <= 64;
         if (f64 && d.x_dtype == TR_F64) {
-            if (one) hipLaunchKernelGGL((k_opt_terms_rep<double, double, 1>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
-            else hipLaunchKernelGGL((k_opt_terms_rep<double, double, 2>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+            if (one) hipLaunchKernelGGL((k_opt_terms_rep<double, double, 1>), gr, dim3(256), 0, st, d, ms, cores, xs, a);
+            else hipLaunchKernelGGL((k_opt_terms_rep<double, double, 2>), gr, dim3(256), 0, st, d, ms, cores, xs, a);
         } else if (!f64 && d.x_dtype == TR_F32) {
-            if (one) hipLaunchKernelGGL((k_opt_terms_rep<float, float, 1>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
-            else hipLaunchKernelGGL((k_opt_terms_rep<float, float, 2>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+            if (one) hipLaunchKernelGGL((k_opt_terms_rep<float, float, 1>), gr, dim3(256), 0, st, d, ms, cores, xs, a);
+            else hipLaunchKernelGGL((k_opt_terms_rep<float, float, 2>), gr, dim3(256), 0, st, d, ms, cores, xs, a);
         } else if (!f64 && d.x_dtype == TR_F16) {
-            if (one) hipLaunchKernelGGL((k_opt_terms_rep<float, __half, 1>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
-            else hipLaunchKernelGGL((k_opt_terms_rep<float, __half, 2>), gr, dim3(256), clds, st, d, ms, cores, xs, a);
+            if (one) hipLaunchKernelGGL((k_opt_terms_rep<float, __half, 1>), gr, dim3(256), 0, st, d, ms, cores, xs, a);
+            else hipLaunchKernelGGL((k_opt_terms_rep<float, __half, 2>), gr, dim3(256), 0, st, d, ms, cores, xs, a);
         } else {
             return hipErrorInvalidValue;
         }
