@@ -253,6 +253,31 @@ def test_optimal_law_run_fibers_longer_than_a_wavefront():
         assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-10, k
 
 
+def test_optimal_law_run_fp16_tensor():
+    """Law O through tr_run with an FP16 tensor and FP32 cores (the law's
+    terms read the FP16 mode-major replicas): 8 AdaGrad steps against the
+    oracle run on the FP16 values of X."""
+    say("run law O, FP16 tensor")
+    N, I, R, m, steps = 3, [40, 36, 44], [3, 4, 3], 128, 8
+    Xt = tr.full_tensor(ti.gaussian_cores(3, N, I, R))
+    X = rounded(brsgd.add_noise(Xt, ti.standard_normal(8, Xt.shape), 40.0), torch.float16)
+    sig = brsgd.init_scale(X, R)
+    init = [rounded(c, torch.float32) for c in ti.gaussian_cores(4, N, I, R, scale=sig)]
+    dX = to_dev(flat_paper(X), torch.float16)
+    dcores = [to_dev(unfold(c), torch.float32) for c in init]
+    rule = api.step_rule("adagrad", eta=0.05)
+    sol = TRSolver(dcores, dX, I, R, m, law="O", scaled=False, prec="f32", rule=rule, seed=2)
+    sol.run(steps)
+    st = brsgd.State(init)
+    cfg = brsgd.Config(m=m, dist="O", rule="adagrad", eta=0.05, seed=2)
+    for _ in range(steps):
+        brsgd.step(st, X, cfg)
+    torch.cuda.synchronize()
+    assert sol.t == steps and int(sol.status.item()) == st.status
+    for k in range(N):
+        assert rel(sol.cores[k].cpu().numpy(), unfold(st.cores[k])) < 1e-4, k
+
+
 def _graph_steps(sol, steps):
     """``steps`` steps from one captured graph of that length, replayed once
     (the capture itself runs one eager step first)."""
